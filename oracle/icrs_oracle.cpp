@@ -1,0 +1,966 @@
+// icrs_oracle.cpp -- plain, slow FP64 CPU oracle of image-centred ray shooting (ICRS).
+//
+// TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or call this
+// file: only the tests, the package's smoke check and the benchmark's CPU-baseline leg
+// do.  It shares no code, header, table or constant generator with the HIP library.
+//
+// What it computes (paper: "microJAX", arXiv 2510.02639):
+//   * lens equation and point-source magnification          -- Sec. 2.1, eqs. lens_eq, amp_point, detJ
+//   * lens polynomial of degree N^2+1 (= 5(N-1) for N=2,3)    -- Sec. 2.1, eq. lens_eq_z
+//   * Ehrlich-Aberth roots from a Cauchy-radius circle        -- Sec. 3.1 (EA update equation)
+//   * root validation by substitution into the lens equation -- Sec. 2.1 (text after lens_eq_z)
+//   * limb sampling, polar binning into sectors               -- Sec. 3.2 (limb-point equation, binning)
+//   * fixed N_r x N_theta polar grid per sector, ray map      -- Sec. 2.2 (chi definition), Sec. 3.3
+//   * row quadrature, cubic boundary crossing, uniform and
+//     linear limb-darkened rules, radial sum, normalisation  -- App. A.1 and A.2
+// Where the paper is silent or garbled the reading taken is stated at the spot; each
+// reading also has a line in the repository's design notes.
+//
+// Plain scalar loops, std::complex<double>, no blocking or fusion.  Built with g++ -O2
+// (no fast-math; x86-64 baseline has no FMA so nothing is contracted).
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+using cplx = std::complex<double>;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// Status bits of one epoch (shared meaning with the library, defined separately there).
+enum : uint32_t {
+  ST_ROOT_NONCONV = 1u,   // an EA solve hit its iteration cap
+  ST_IMG_COUNT = 2u,      // an image count outside the allowed set after seeding
+  ST_CAP_OVERFLOW = 4u,   // more sector candidates than the cap; pairs were merged
+  ST_CLIP = 8u,           // inside rays still touch a sector edge after the retries
+  ST_NAN = 16u,           // non-finite result
+  ST_GIVEN = 64u,         // sectors were supplied by the caller
+};
+
+// ---------------------------------------------------------------------------------------
+// O1: lens frame.  Sec. 2.1 (eq. lens_eq): fractional masses eps_i summing to 1, complex
+// positions a_i, lengths in Einstein radii of the total mass.  Sec. 3.5 / Fig. 3 define the
+// parameters: q = m2/m1, separation s on the real axis, origin at the M1-M2 barycentre;
+// the third lens at (r3, psi) from the M1-M2 midpoint with q3 = m3/m1.
+// Reading: the primary sits on the negative real axis.
+// Parameter vector (doubles): [s, q, u0, alpha, t0, tE, rho, u1, q3, r3, psi].
+// n_lens = 1 is a unit point lens at the origin, n_lens = 0 the identity map w = z
+// (both used only as closed-form checks).
+struct Lens {
+  int n = 0;
+  double eps[3] = {0, 0, 0};
+  cplx a[3];
+};
+
+Lens make_lens(int n_lens, const double* p) {
+  Lens L;
+  L.n = n_lens;
+  if (n_lens == 1) {
+    L.eps[0] = 1.0;
+    L.a[0] = cplx(0.0, 0.0);
+  } else if (n_lens == 2) {
+    const double s = p[0], q = p[1];
+    L.eps[0] = 1.0 / (1.0 + q);
+    L.eps[1] = q / (1.0 + q);
+    L.a[0] = cplx(-q * s / (1.0 + q), 0.0);
+    L.a[1] = cplx(s / (1.0 + q), 0.0);
+  } else if (n_lens == 3) {
+    const double s = p[0], q = p[1], q3 = p[8], r3 = p[9], psi = p[10];
+    const double m = 1.0 + q + q3;
+    L.eps[0] = 1.0 / m;
+    L.eps[1] = q / m;
+    L.eps[2] = q3 / m;
+    L.a[0] = cplx(-q * s / (1.0 + q), 0.0);
+    L.a[1] = cplx(s / (1.0 + q), 0.0);
+    const cplx mid = 0.5 * (L.a[0] + L.a[1]);
+    L.a[2] = mid + cplx(r3 * std::cos(psi), r3 * std::sin(psi));
+  }
+  return L;
+}
+
+// Eq. lens_eq: w = z - sum_i eps_i / (conj(z) - conj(a_i)).
+cplx lens_map(const Lens& L, cplx z) {
+  cplx w = z;
+  for (int i = 0; i < L.n; ++i) w -= L.eps[i] / std::conj(z - L.a[i]);
+  return w;
+}
+
+// kappa(z) = sum_i eps_i / (conj(z) - conj(a_i))^2; eq. detJ gives det J = 1 - |kappa|^2.
+cplx kappa_of(const Lens& L, cplx z) {
+  cplx k(0.0, 0.0);
+  for (int i = 0; i < L.n; ++i) {
+    const cplx d = std::conj(z - L.a[i]);
+    k += L.eps[i] / (d * d);
+  }
+  return k;
+}
+
+// O2: source centre on a straight trajectory.  Sec. 3.5 names (t0, u0, tE, alpha) but not
+// the sign conventions.  Reading: tau = (t - t0)/tE; the source moves along (cos a, sin a)
+// and passes the origin at u0 * (-sin a, cos a) when t = t0.
+cplx source_center(const double* p, double t) {
+  const double u0 = p[2], alpha = p[3], t0 = p[4], tE = p[5];
+  const double tau = (t - t0) / tE;
+  return cplx(tau * std::cos(alpha) - u0 * std::sin(alpha), tau * std::sin(alpha) + u0 * std::cos(alpha));
+}
+
+// ---------------------------------------------------------------------------------------
+// O4: lens polynomial, Sec. 2.1 eq. lens_eq_z.  The paper cites the degree 5(N-1) without
+// printing coefficients.  Derivation used: conjugating eq. lens_eq gives conj(z) = G/H with
+// H = prod_k (z - a_k), G = conj(w) H + sum_k eps_k prod_{j!=k} (z - a_j); putting this back
+// into eq. lens_eq and clearing the denominators D_i = G - conj(a_i) H gives
+//   P(z) = (z - w) prod_i D_i - H sum_i eps_i prod_{j!=i} D_j,
+// of degree N^2 + 1 (5 for N = 2, 10 for N = 3) with leading coefficient prod_i(conj(w)-conj(a_i)).
+using Poly = std::vector<cplx>;  // index = power of z
+
+Poly pmul(const Poly& a, const Poly& b) {
+  Poly c(a.size() + b.size() - 1, cplx(0.0, 0.0));
+  for (size_t i = 0; i < a.size(); ++i)
+    for (size_t j = 0; j < b.size(); ++j) c[i + j] += a[i] * b[j];
+  return c;
+}
+
+Poly padd(const Poly& a, const Poly& b) {
+  Poly c(std::max(a.size(), b.size()), cplx(0.0, 0.0));
+  for (size_t i = 0; i < a.size(); ++i) c[i] += a[i];
+  for (size_t i = 0; i < b.size(); ++i) c[i] += b[i];
+  return c;
+}
+
+Poly pscale(const Poly& a, cplx s) {
+  Poly c(a);
+  for (auto& x : c) x *= s;
+  return c;
+}
+
+Poly lens_polynomial(const Lens& L, cplx w) {
+  const int n = L.n;
+  Poly H{cplx(1.0, 0.0)};
+  for (int k = 0; k < n; ++k) H = pmul(H, Poly{-L.a[k], cplx(1.0, 0.0)});
+  Poly G = pscale(H, std::conj(w));
+  for (int k = 0; k < n; ++k) {
+    Poly Pk{cplx(1.0, 0.0)};
+    for (int j = 0; j < n; ++j)
+      if (j != k) Pk = pmul(Pk, Poly{-L.a[j], cplx(1.0, 0.0)});
+    G = padd(G, pscale(Pk, cplx(L.eps[k], 0.0)));
+  }
+  std::vector<Poly> D(n);
+  for (int i = 0; i < n; ++i) D[i] = padd(G, pscale(H, -std::conj(L.a[i])));
+  Poly prodD{cplx(1.0, 0.0)};
+  for (int i = 0; i < n; ++i) prodD = pmul(prodD, D[i]);
+  Poly P = pmul(Poly{-w, cplx(1.0, 0.0)}, prodD);
+  Poly S{cplx(0.0, 0.0)};
+  for (int i = 0; i < n; ++i) {
+    Poly Q{cplx(L.eps[i], 0.0)};
+    for (int j = 0; j < n; ++j)
+      if (j != i) Q = pmul(Q, D[j]);
+    S = padd(S, Q);
+  }
+  P = padd(P, pscale(pmul(H, S), cplx(-1.0, 0.0)));
+  P.resize(n * n + 2);  // degree n^2 + 1
+  return P;
+}
+
+// ---------------------------------------------------------------------------------------
+// O5: Ehrlich-Aberth, Sec. 3.1.  All estimates are updated together (Jacobi form) by
+//   z_k <- z_k - ( P'(z_k)/P(z_k) - sum_{j!=k} 1/(z_k - z_j) )^{-1}.
+// Start: uniformly on a circle of Cauchy radius R = 1 + max_{j<n} |b_j / b_n| (Sec. 3.1).
+// Readings: circle centred at 0 with angular offset pi/(2n); the paper fixes an iteration
+// count without giving it -- here each root stops on its own test (below), cap 500.
+void horner(const Poly& P, cplx z, cplx* p, cplx* dp) {
+  const int n = static_cast<int>(P.size()) - 1;
+  cplx v = P[n], d(0.0, 0.0);
+  for (int j = n - 1; j >= 0; --j) {
+    d = d * z + v;
+    v = v * z + P[j];
+  }
+  *p = v;
+  *dp = d;
+}
+
+bool ea_roots(const Poly& P, std::vector<cplx>& z, int* iters_out) {
+  const int n = static_cast<int>(P.size()) - 1;
+  z.assign(n, cplx(0.0, 0.0));
+  double R = 0.0;
+  for (int j = 0; j < n; ++j) R = std::max(R, std::abs(P[j] / P[n]));
+  R += 1.0;
+  for (int k = 0; k < n; ++k) {
+    const double ang = 2.0 * kPi * k / n + kPi / (2.0 * n);
+    z[k] = cplx(R * std::cos(ang), R * std::sin(ang));
+  }
+  // A root is finished once its step is below 1e-14 max(1,|z|) or |P(z)| is down to the
+  // rounding noise of evaluating P there, 8 n u sum_j |b_j| |z|^j with u = 2^-53 (clustered
+  // roots never reach the first test).  Finished roots are no longer moved.
+  std::vector<char> done(n, 0);
+  std::vector<cplx> step(n);
+  for (int it = 0; it < 500; ++it) {
+    for (int k = 0; k < n; ++k) {
+      step[k] = cplx(0.0, 0.0);
+      if (done[k]) continue;
+      cplx p, dp;
+      horner(P, z[k], &p, &dp);
+      double noise = 0.0;
+      const double az = std::abs(z[k]);
+      for (int j = n; j >= 0; --j) noise = noise * az + std::abs(P[j]);
+      noise *= 8.0 * n * 1.1102230246251565e-16;
+      if (std::abs(p) <= noise) {
+        done[k] = 1;
+        continue;
+      }
+      cplx rep(0.0, 0.0);
+      for (int j = 0; j < n; ++j)
+        if (j != k && z[k] != z[j]) rep += 1.0 / (z[k] - z[j]);
+      const cplx den = dp / p - rep;
+      step[k] = (den == cplx(0.0, 0.0)) ? cplx(0.0, 0.0) : 1.0 / den;
+    }
+    bool all = true;
+    for (int k = 0; k < n; ++k) {
+      if (done[k]) continue;
+      z[k] -= step[k];
+      if (std::abs(step[k]) <= 1e-14 * std::max(1.0, std::abs(z[k]))) done[k] = 1;
+      all = all && done[k];
+    }
+    if (all) {
+      if (iters_out) *iters_out = it + 1;
+      return true;
+    }
+  }
+  if (iters_out) *iters_out = 500;
+  return false;
+}
+
+// ---------------------------------------------------------------------------------------
+// O6: validation, Sec. 2.1 ("each root ... must be validated by substituting it back").
+// Reading of the tolerance: every root is polished by at most 8 Newton steps on the lens
+// equation itself (with F = lens_map(z) - w and kappa as above, the step solving
+// dz + kappa conj(dz) = -F is dz = (kappa conj(F) - F) / (1 - |kappa|^2)), kept when
+// |F| <= 1e-10 afterwards, and dropped as a duplicate within 1e-9 max(1,|z|) of a kept one.
+// An image count outside {N+1, N+3, ..., 5(N-1)} triggers one extra pass seeded next to
+// each lens (z = a_k - eps_k / conj(w' - a_k), w' = w shifted by the other lenses'
+// deflection at a_k -- the leading-order image near a lens); a count still outside the
+// set raises ST_IMG_COUNT.
+cplx polish(const Lens& L, cplx w, cplx z) {
+  for (int s = 0; s < 8; ++s) {
+    const cplx F = lens_map(L, z) - w;
+    const cplx k = kappa_of(L, z);
+    const double den = 1.0 - std::norm(k);
+    if (den == 0.0 || !std::isfinite(den)) break;
+    const cplx dz = (k * std::conj(F) - F) / den;
+    z += dz;
+    if (std::abs(dz) <= 1e-14 * std::max(1.0, std::abs(z))) break;
+  }
+  return z;
+}
+
+bool count_ok(int n_lens, int count) {
+  if (n_lens == 0) return count == 1;
+  if (n_lens == 1) return count == 2;
+  const int lo = n_lens + 1, hi = 5 * (n_lens - 1);
+  return count >= lo && count <= hi && ((count - lo) % 2 == 0);
+}
+
+void try_accept(const Lens& L, cplx w, cplx z0, std::vector<cplx>& out) {
+  const cplx z = polish(L, w, z0);
+  const double res = std::abs(lens_map(L, z) - w);
+  if (!(res <= 1e-10)) return;
+  for (const cplx& y : out)
+    if (std::abs(z - y) <= 1e-9 * std::max(1.0, std::abs(z))) return;
+  out.push_back(z);
+}
+
+// Images of the point source at w.  Returns status bits (ST_ROOT_NONCONV, ST_IMG_COUNT).
+uint32_t find_images(const Lens& L, cplx w, std::vector<cplx>& images) {
+  uint32_t st = 0;
+  images.clear();
+  const Poly P = lens_polynomial(L, w);
+  std::vector<cplx> roots;
+  int iters = 0;
+  if (!ea_roots(P, roots, &iters)) st |= ST_ROOT_NONCONV;
+  for (const cplx& r : roots) try_accept(L, w, r, images);
+  if (!count_ok(L.n, static_cast<int>(images.size()))) {
+    for (int k = 0; k < L.n; ++k) {
+      cplx wk = w;
+      for (int j = 0; j < L.n; ++j)
+        if (j != k) wk += L.eps[j] / std::conj(L.a[k] - L.a[j]);
+      try_accept(L, w, L.a[k] - L.eps[k] / std::conj(wk - L.a[k]), images);
+    }
+    if (!count_ok(L.n, static_cast<int>(images.size()))) st |= ST_IMG_COUNT;
+  }
+  return st;
+}
+
+// ---------------------------------------------------------------------------------------
+// O8: sectors, Sec. 3.2.  The paper bins image-limb points in polar (r, theta) separately in
+// r and theta, forms candidate (r-bin x theta-bin) sectors, keeps occupied ones, merges
+// periodic/overlapping ones, caps the count by the maximum number of images, and sets
+// bounds from min/max of enclosed points plus a safety margin.  It gives none of the
+// constants.  Readings taken:
+//   polar origin = frame origin; 64 theta bins on (-pi, pi]; r bins of width
+//   max((r_max - r_min)/32, 2 rho) from r_min (32 bins); a run = occupied bins joined across
+//   gaps of at most one empty bin (theta circular; no gap of >= 2 empty bins = full ring);
+//   candidate = (r-run, theta-run) pair holding >= 1 point; bounds = member min/max (theta
+//   unwrapped within its run); margin per side 0.1 x extent + floor (rho/100 in r,
+//   rho/(100 r_mid) in theta), r_lo >= 0, theta extent >= 2 pi -> full ring; merge any two
+//   sectors overlapping in r and circularly in theta into their bounding box, to a fixpoint;
+//   cap at 5(N-1) by merging the pair of least union area; sort by (theta_lo, r_lo).
+struct Sector {
+  double r_lo, r_hi, th_lo, th_hi;
+  bool periodic;
+};
+
+constexpr int kBinsTheta = 64;
+constexpr int kBinsR = 32;
+
+void normalise_theta(Sector& s) {
+  if (s.periodic || s.th_hi - s.th_lo >= 2.0 * kPi) {
+    s.periodic = true;
+    s.th_lo = -kPi;
+    s.th_hi = kPi;
+    return;
+  }
+  while (s.th_lo < -kPi) {
+    s.th_lo += 2.0 * kPi;
+    s.th_hi += 2.0 * kPi;
+  }
+  while (s.th_lo >= kPi) {
+    s.th_lo -= 2.0 * kPi;
+    s.th_hi -= 2.0 * kPi;
+  }
+}
+
+// Shift (k in {-1,0,1}) of b's theta interval by 2 pi k that makes it overlap a; 2 if none.
+int theta_overlap_shift(const Sector& a, const Sector& b) {
+  if (a.periodic || b.periodic) return 0;
+  for (int k = -1; k <= 1; ++k) {
+    const double lo = b.th_lo + 2.0 * kPi * k, hi = b.th_hi + 2.0 * kPi * k;
+    if (lo <= a.th_hi && a.th_lo <= hi) return k;
+  }
+  return 2;
+}
+
+bool overlaps(const Sector& a, const Sector& b) {
+  if (!(a.r_lo <= b.r_hi && b.r_lo <= a.r_hi)) return false;
+  return theta_overlap_shift(a, b) != 2;
+}
+
+Sector union_of(const Sector& a, const Sector& b) {
+  Sector u;
+  u.r_lo = std::min(a.r_lo, b.r_lo);
+  u.r_hi = std::max(a.r_hi, b.r_hi);
+  u.periodic = a.periodic || b.periodic;
+  if (u.periodic) {
+    u.th_lo = -kPi;
+    u.th_hi = kPi;
+    return u;
+  }
+  int k = theta_overlap_shift(a, b);
+  if (k == 2) {  // disjoint in theta (only in the cap step): join across the shorter gap
+    double best = 1e300;
+    for (int kk = -1; kk <= 1; ++kk) {
+      const double lo = std::min(a.th_lo, b.th_lo + 2.0 * kPi * kk);
+      const double hi = std::max(a.th_hi, b.th_hi + 2.0 * kPi * kk);
+      if (hi - lo < best) {
+        best = hi - lo;
+        k = kk;
+      }
+    }
+  }
+  u.th_lo = std::min(a.th_lo, b.th_lo + 2.0 * kPi * k);
+  u.th_hi = std::max(a.th_hi, b.th_hi + 2.0 * kPi * k);
+  normalise_theta(u);
+  return u;
+}
+
+double polar_area(const Sector& s) { return 0.5 * (s.r_hi * s.r_hi - s.r_lo * s.r_lo) * (s.th_hi - s.th_lo); }
+
+void merge_fixpoint(std::vector<Sector>& S) {
+  bool changed = true;
+  while (changed) {
+    changed = false;
+    for (size_t i = 0; i < S.size() && !changed; ++i)
+      for (size_t j = i + 1; j < S.size() && !changed; ++j)
+        if (overlaps(S[i], S[j])) {
+          S[i] = union_of(S[i], S[j]);
+          S.erase(S.begin() + j);
+          changed = true;
+        }
+  }
+}
+
+void sort_sectors(std::vector<Sector>& S) {
+  std::stable_sort(S.begin(), S.end(), [](const Sector& a, const Sector& b) {
+    if (a.th_lo != b.th_lo) return a.th_lo < b.th_lo;
+    return a.r_lo < b.r_lo;
+  });
+}
+
+// Circular runs over nb bins; returns (start, length) pairs, or one run of length nb.
+std::vector<std::pair<int, int>> circular_runs(const std::vector<int>& occ) {
+  const int nb = static_cast<int>(occ.size());
+  std::vector<std::pair<int, int>> runs;
+  int n_occ = 0;
+  for (int b = 0; b < nb; ++b) n_occ += occ[b] ? 1 : 0;
+  if (n_occ == 0) return runs;
+  // a gap of >= 2 empty bins breaks a run; find the first bin that follows such a gap
+  int start = -1;
+  for (int b = 0; b < nb; ++b) {
+    if (occ[b] && !occ[(b - 1 + nb) % nb] && !occ[(b - 2 + nb) % nb]) {
+      start = b;
+      break;
+    }
+  }
+  if (start < 0) {  // no gap of two empty bins anywhere: one full ring
+    runs.push_back({0, nb});
+    return runs;
+  }
+  int b = start;
+  int visited = 0;
+  while (visited < nb) {
+    if (!occ[b]) {
+      ++b;
+      b %= nb;
+      ++visited;
+      continue;
+    }
+    const int s = b;
+    int last = b;  // last occupied bin of this run
+    int len = 1;
+    ++b;
+    b %= nb;
+    ++visited;
+    while (visited < nb) {
+      if (occ[b]) {
+        last = b;
+      } else if (!occ[(b + 1) % nb]) {
+        break;  // two empty bins in a row end the run
+      }
+      ++b;
+      b %= nb;
+      ++visited;
+    }
+    len = (last - s + nb) % nb + 1;
+    runs.push_back({s, len});
+  }
+  return runs;
+}
+
+std::vector<std::pair<int, int>> linear_runs(const std::vector<int>& occ) {
+  const int nb = static_cast<int>(occ.size());
+  std::vector<std::pair<int, int>> runs;
+  int b = 0;
+  while (b < nb) {
+    if (!occ[b]) {
+      ++b;
+      continue;
+    }
+    const int s = b;
+    int last = b;
+    ++b;
+    while (b < nb) {
+      if (occ[b]) {
+        last = b;
+      } else if (b + 1 >= nb || !occ[b + 1]) {
+        break;
+      }
+      ++b;
+    }
+    runs.push_back({s, last - s + 1});
+    b = last + 1;
+  }
+  return runs;
+}
+
+uint32_t build_sectors(const std::vector<double>& r, const std::vector<double>& th, double rho, int cap,
+                       std::vector<Sector>& out) {
+  uint32_t st = 0;
+  out.clear();
+  const size_t P = r.size();
+  if (P == 0) return st;
+  // theta bins on (-pi, pi]
+  const double wth = 2.0 * kPi / kBinsTheta;
+  std::vector<int> tbin(P), occ_t(kBinsTheta, 0);
+  for (size_t p = 0; p < P; ++p) {
+    int b = static_cast<int>(std::floor((th[p] + kPi) / wth));
+    b = std::min(std::max(b, 0), kBinsTheta - 1);
+    tbin[p] = b;
+    occ_t[b] = 1;
+  }
+  // r bins
+  double rmin = r[0], rmax = r[0];
+  for (size_t p = 1; p < P; ++p) {
+    rmin = std::min(rmin, r[p]);
+    rmax = std::max(rmax, r[p]);
+  }
+  const double wr = std::max((rmax - rmin) / kBinsR, 2.0 * rho);
+  std::vector<int> rbin(P), occ_r(kBinsR, 0);
+  for (size_t p = 0; p < P; ++p) {
+    int b = static_cast<int>(std::floor((r[p] - rmin) / wr));
+    b = std::min(std::max(b, 0), kBinsR - 1);
+    rbin[p] = b;
+    occ_r[b] = 1;
+  }
+  const auto truns = circular_runs(occ_t);
+  const auto rruns = linear_runs(occ_r);
+  std::vector<Sector> cand;
+  for (const auto& rr : rruns) {
+    for (const auto& tr : truns) {
+      const bool full = tr.second >= kBinsTheta;
+      bool any = false;
+      Sector s{0, 0, 0, 0, full};
+      for (size_t p = 0; p < P; ++p) {
+        if (rbin[p] < rr.first || rbin[p] >= rr.first + rr.second) continue;
+        const int off = (tbin[p] - tr.first + kBinsTheta) % kBinsTheta;
+        if (!full && off >= tr.second) continue;
+        const double thu = (tbin[p] >= tr.first) ? th[p] : th[p] + 2.0 * kPi;
+        if (!any) {
+          s.r_lo = s.r_hi = r[p];
+          s.th_lo = s.th_hi = thu;
+          any = true;
+        } else {
+          s.r_lo = std::min(s.r_lo, r[p]);
+          s.r_hi = std::max(s.r_hi, r[p]);
+          s.th_lo = std::min(s.th_lo, thu);
+          s.th_hi = std::max(s.th_hi, thu);
+        }
+      }
+      if (!any) continue;
+      // safety margins
+      const double r_mid = 0.5 * (s.r_lo + s.r_hi);
+      const double mr = 0.1 * (s.r_hi - s.r_lo) + rho / 100.0;
+      const double mt = 0.1 * (s.th_hi - s.th_lo) + rho / (100.0 * r_mid);
+      s.r_lo = std::max(s.r_lo - mr, 0.0);
+      s.r_hi = s.r_hi + mr;
+      if (!full) {
+        s.th_lo -= mt;
+        s.th_hi += mt;
+      }
+      normalise_theta(s);
+      cand.push_back(s);
+    }
+  }
+  merge_fixpoint(cand);
+  while (static_cast<int>(cand.size()) > cap) {
+    st |= ST_CAP_OVERFLOW;
+    size_t bi = 0, bj = 1;
+    double best = 1e300;
+    for (size_t i = 0; i < cand.size(); ++i)
+      for (size_t j = i + 1; j < cand.size(); ++j) {
+        const double a = polar_area(union_of(cand[i], cand[j]));
+        if (a < best) {
+          best = a;
+          bi = i;
+          bj = j;
+        }
+      }
+    cand[bi] = union_of(cand[bi], cand[bj]);
+    cand.erase(cand.begin() + bj);
+    merge_fixpoint(cand);
+  }
+  sort_sectors(cand);
+  out = cand;
+  return st;
+}
+
+// ---------------------------------------------------------------------------------------
+// O9-O11: ray shooting and quadrature on one sector, Sec. 3.3 and App. A.
+//
+// Grid (Sec. 3.3): N_r x N_theta nodes; reading: cell-centred, r_i = r_lo + (i+1/2) dr,
+// theta_l = theta_lo + (l+1/2) dtheta, so r_i dr dtheta is the exact annular-cell area.
+// Each node z = r_i e^{i theta_l} is mapped by eq. lens_eq; d = |w - w_c|; chi = [d < rho]
+// (Sec. 2.2, strict).
+//
+// Surface brightness, App. A.2: I(x) = I0 [1 - u1 (1 - sqrt(1 - x^2))], x = d/rho, with
+// I0 = 3 / (pi (3 - u1)) (read as 3 divided by pi(3 - u1): it normalises the flux to one).
+//
+// Boundary weights, App. A.2: each inside node owns [theta_l - dtheta/2, theta_l + dtheta/2].
+// Reading of the garbled delta_enter: delta is the distance from the crossing to the node in
+// units of dtheta (in [0,1]), so a boundary node owns (delta + 1/2) dtheta of its row.  Node
+// weight W = 1 + sum over the sides whose neighbour is outside of (f(delta_side) - 1); for a
+// node with one outside neighbour this is exactly f(delta) (entering/exiting classes), for a
+// fully enclosed node 1.  f is the App. A.2 hybrid for u1 > 0 with b(delta) =
+// (2/3) sqrt(1 + 1/(2 delta)); the uniform source (u1 = 0) uses f(delta) = delta + 1/2, the
+// node-centred form of App. A.1.  delta_c is not given; reading: 0.1.
+//
+// Crossing (App. A.1/A.2): on the bracket (p, p+1), t = (theta - theta_p)/dtheta, the cubic
+// Lagrange interpolant L(t) of d through t = -1, 0, 1, 2 (nodes p-1..p+2) is solved for
+// L(t) = rho by bisection on [0,1] (60 halvings, left half kept on an exact hit).  At a
+// non-periodic edge where p-1 or p+2 does not exist, the linear interpolant is used.  A
+// neighbour beyond a non-periodic edge counts as outside with delta = 1/2 and is reported.
+//
+// Row sum A_i = r_i dtheta sum_l I_l chi_l W_l; sector sum dr sum_i A_i (App. A.1);
+// magnification = sum over sectors / rho^2 with I normalised (App. A.2).
+double lagrange4(const double d[4], double t) {
+  const double tm1 = t + 1.0, t0 = t, t1 = t - 1.0, t2 = t - 2.0;
+  return d[0] * (-(t0 * t1 * t2) / 6.0) + d[1] * (tm1 * t1 * t2 / 2.0) + d[2] * (-(tm1 * t0 * t2) / 2.0) +
+         d[3] * (tm1 * t0 * t1 / 6.0);
+}
+
+// Solve for the crossing in [0,1].  cubic != 0: d4 = {d_{p-1}, d_p, d_{p+1}, d_{p+2}};
+// cubic == 0: linear between d4[1] and d4[2].
+double crossing_t(const double d4[4], int cubic, double rho) {
+  if (!cubic) {
+    const double den = d4[2] - d4[1];
+    double t = (den == 0.0) ? 0.5 : (rho - d4[1]) / den;
+    return std::min(std::max(t, 0.0), 1.0);
+  }
+  double a = 0.0, b = 1.0;
+  const bool in_a = (lagrange4(d4, a) - rho) < 0.0;
+  for (int it = 0; it < 60; ++it) {
+    const double m = 0.5 * (a + b);
+    const double g = lagrange4(d4, m) - rho;
+    if (g == 0.0) {
+      b = m;
+    } else if ((g < 0.0) == in_a) {
+      a = m;
+    } else {
+      b = m;
+    }
+  }
+  return 0.5 * (a + b);
+}
+
+double brightness(double x, double u1) {
+  const double I0 = 3.0 / (kPi * (3.0 - u1));
+  const double c = 1.0 - x * x;
+  return I0 * (1.0 - u1 * (1.0 - std::sqrt(c > 0.0 ? c : 0.0)));
+}
+
+double edge_factor(double delta, double u1, double delta_c) {
+  if (u1 == 0.0) return delta + 0.5;
+  if (delta >= delta_c && delta > 0.0) return (0.5 + delta) * (2.0 / 3.0) * std::sqrt(1.0 + 1.0 / (2.0 * delta));
+  return (2.0 / 3.0) * delta + 0.5;
+}
+
+// Clip flags of one sector: bit0 r_lo row, bit1 r_hi row, bit2 theta_lo column, bit3 theta_hi column.
+double sector_flux(const Lens& L, cplx wc, double rho, double u1, double delta_c, int nr, int nth, const Sector& S,
+                   int* clip_flags) {
+  const double dr = (S.r_hi - S.r_lo) / nr;
+  const double dth = (S.th_hi - S.th_lo) / nth;
+  std::vector<double> d(nth);
+  std::vector<char> in(nth);
+  double total = 0.0;
+  int clip = 0;
+  for (int i = 0; i < nr; ++i) {
+    const double ri = S.r_lo + (i + 0.5) * dr;
+    bool any_in = false;
+    for (int l = 0; l < nth; ++l) {
+      const double th = S.th_lo + (l + 0.5) * dth;
+      const cplx z(ri * std::cos(th), ri * std::sin(th));
+      const cplx w = lens_map(L, z);
+      d[l] = std::abs(w - wc);
+      in[l] = d[l] < rho;
+      any_in = any_in || in[l];
+    }
+    if (!any_in) continue;
+    if (i == 0 && S.r_lo > 0.0) clip |= 1;
+    if (i == nr - 1) clip |= 2;
+    double row = 0.0;
+    for (int l = 0; l < nth; ++l) {
+      if (!in[l]) continue;
+      double W = 1.0;
+      // left side: crossing in (theta_{l-1}, theta_l), bracket p = l-1, delta = 1 - t
+      if (l == 0 && !S.periodic) {
+        clip |= 4;
+        W += edge_factor(0.5, u1, delta_c) - 1.0;
+      } else {
+        const int lm = (l - 1 + nth) % nth;
+        if (!in[lm]) {
+          const int p = lm;
+          double st[4];
+          int cubic = 1;
+          for (int j = -1; j <= 2; ++j) {
+            int idx = p + j;
+            if (S.periodic) {
+              idx = (idx % nth + nth) % nth;
+            } else if (idx < 0 || idx >= nth) {
+              cubic = 0;
+              idx = std::min(std::max(idx, 0), nth - 1);
+            }
+            st[j + 1] = d[idx];
+          }
+          const double t = crossing_t(st, cubic, rho);
+          W += edge_factor(1.0 - t, u1, delta_c) - 1.0;
+        }
+      }
+      // right side: crossing in (theta_l, theta_{l+1}), bracket p = l, delta = t
+      if (l == nth - 1 && !S.periodic) {
+        clip |= 8;
+        W += edge_factor(0.5, u1, delta_c) - 1.0;
+      } else {
+        const int lp = (l + 1) % nth;
+        if (!in[lp]) {
+          const int p = l;
+          double st[4];
+          int cubic = 1;
+          for (int j = -1; j <= 2; ++j) {
+            int idx = p + j;
+            if (S.periodic) {
+              idx = (idx % nth + nth) % nth;
+            } else if (idx < 0 || idx >= nth) {
+              cubic = 0;
+              idx = std::min(std::max(idx, 0), nth - 1);
+            }
+            st[j + 1] = d[idx];
+          }
+          const double t = crossing_t(st, cubic, rho);
+          W += edge_factor(t, u1, delta_c) - 1.0;
+        }
+      }
+      row += brightness(d[l] / rho, u1) * W;
+    }
+    total += ri * dth * row * dr;
+  }
+  if (clip_flags) *clip_flags = clip;
+  return total;
+}
+
+// O12: clip certificate (not in the paper; the paper's safety margin has no check).
+// A sector whose inside rays touch an edge row/column is widened by half its extent on that
+// side, the list is merged again, and the epoch is recomputed; at most max_retries times.
+void widen(Sector& s, int clip) {
+  const double er = s.r_hi - s.r_lo;
+  if (clip & 1) s.r_lo = std::max(s.r_lo - 0.5 * er, 0.0);
+  if (clip & 2) s.r_hi += 0.5 * er;
+  if (!s.periodic) {
+    const double et = s.th_hi - s.th_lo;
+    if (clip & 4) s.th_lo -= 0.5 * et;
+    if (clip & 8) s.th_hi += 0.5 * et;
+    normalise_theta(s);
+  }
+}
+
+struct Config {
+  int n_limb, n_r, n_theta, max_retries;
+  double delta_c;
+};
+
+// One epoch end to end.  Returns the magnification; fills status and the final sector list.
+double epoch_magnification(const Lens& L, const double* p, double t, const Config& cfg, uint32_t* status,
+                           std::vector<Sector>& sectors, double* a_ps, int* n_img_center) {
+  uint32_t st = 0;
+  const double rho = p[6], u1 = p[7];
+  const cplx wc = source_center(p, t);
+  // centre images: point-source magnification, eq. amp_point with eq. detJ
+  std::vector<cplx> img;
+  st |= find_images(L, wc, img);
+  double aps = 0.0;
+  for (const cplx& z : img) aps += 1.0 / std::abs(1.0 - std::norm(kappa_of(L, z)));
+  if (a_ps) *a_ps = aps;
+  if (n_img_center) *n_img_center = static_cast<int>(img.size());
+  // O3: limb points w_k = w_c + rho e^{2 pi i k / N_limb}, k = 0..N_limb-1 (Sec. 3.2; the
+  // printed exponent drops k -- read as the k-th of N_limb equally spaced points, phase 0).
+  std::vector<double> rr, tt;
+  for (int k = 0; k < cfg.n_limb; ++k) {
+    const double ph = 2.0 * kPi * k / cfg.n_limb;
+    const cplx w = wc + cplx(rho * std::cos(ph), rho * std::sin(ph));
+    st |= find_images(L, w, img);
+    for (const cplx& z : img) {
+      rr.push_back(std::abs(z));
+      tt.push_back(std::atan2(z.imag(), z.real()));
+    }
+  }
+  const int cap = (L.n >= 2) ? 5 * (L.n - 1) : 2;
+  st |= build_sectors(rr, tt, rho, cap, sectors);
+  double flux = 0.0;
+  for (int attempt = 0;; ++attempt) {
+    flux = 0.0;
+    std::vector<int> clips(sectors.size(), 0);
+    bool any = false;
+    for (size_t s = 0; s < sectors.size(); ++s) {
+      flux += sector_flux(L, wc, rho, u1, cfg.delta_c, cfg.n_r, cfg.n_theta, sectors[s], &clips[s]);
+      any = any || clips[s] != 0;
+    }
+    if (!any) break;
+    if (attempt >= cfg.max_retries) {
+      st |= ST_CLIP;
+      break;
+    }
+    for (size_t s = 0; s < sectors.size(); ++s)
+      if (clips[s]) widen(sectors[s], clips[s]);
+    merge_fixpoint(sectors);
+    sort_sectors(sectors);
+  }
+  const double mag = flux / (rho * rho);
+  if (!std::isfinite(mag)) st |= ST_NAN;
+  *status = st;
+  return mag;
+}
+
+}  // namespace
+
+// =======================================================================================
+// C entry points for ctypes (tests only).  Complex numbers are passed as (re, im) pairs.
+extern "C" {
+
+int orc_abi_version() { return 1; }
+
+void orc_frame(int n_lens, const double* params, double* eps, double* a) {
+  const Lens L = make_lens(n_lens, params);
+  for (int i = 0; i < n_lens; ++i) {
+    eps[i] = L.eps[i];
+    a[2 * i] = L.a[i].real();
+    a[2 * i + 1] = L.a[i].imag();
+  }
+}
+
+void orc_source_center(const double* params, double t, double* wc) {
+  const cplx w = source_center(params, t);
+  wc[0] = w.real();
+  wc[1] = w.imag();
+}
+
+// Lens given directly by masses and positions (n <= 3).
+static Lens lens_from(int n, const double* eps, const double* a) {
+  Lens L;
+  L.n = n;
+  for (int i = 0; i < n; ++i) {
+    L.eps[i] = eps[i];
+    L.a[i] = cplx(a[2 * i], a[2 * i + 1]);
+  }
+  return L;
+}
+
+void orc_lens_map(int n, const double* eps, const double* a, const double* z, double* w) {
+  const cplx r = lens_map(lens_from(n, eps, a), cplx(z[0], z[1]));
+  w[0] = r.real();
+  w[1] = r.imag();
+}
+
+int orc_lens_poly(int n, const double* eps, const double* a, const double* w, double* coef) {
+  const Poly P = lens_polynomial(lens_from(n, eps, a), cplx(w[0], w[1]));
+  for (size_t j = 0; j < P.size(); ++j) {
+    coef[2 * j] = P[j].real();
+    coef[2 * j + 1] = P[j].imag();
+  }
+  return static_cast<int>(P.size()) - 1;
+}
+
+int orc_ea_roots(int deg, const double* coef, double* roots, int* iters) {
+  Poly P(deg + 1);
+  for (int j = 0; j <= deg; ++j) P[j] = cplx(coef[2 * j], coef[2 * j + 1]);
+  std::vector<cplx> z;
+  const bool ok = ea_roots(P, z, iters);
+  for (int k = 0; k < deg; ++k) {
+    roots[2 * k] = z[k].real();
+    roots[2 * k + 1] = z[k].imag();
+  }
+  return ok ? 1 : 0;
+}
+
+// Validated images of a point source at w; returns the count, status bits in *status.
+int orc_images(int n, const double* eps, const double* a, const double* w, double* z, uint32_t* status) {
+  std::vector<cplx> img;
+  const uint32_t st = find_images(lens_from(n, eps, a), cplx(w[0], w[1]), img);
+  for (size_t j = 0; j < img.size(); ++j) {
+    z[2 * j] = img[j].real();
+    z[2 * j + 1] = img[j].imag();
+  }
+  if (status) *status = st;
+  return static_cast<int>(img.size());
+}
+
+// eq. amp_point: A = sum_j 1/|det J(z_j)|; parities (sign det J) and per-image |mu| returned.
+double orc_point_mag(int n, const double* eps, const double* a, const double* w, int* n_img, double* mu_signed) {
+  const Lens L = lens_from(n, eps, a);
+  std::vector<cplx> img;
+  find_images(L, cplx(w[0], w[1]), img);
+  double A = 0.0;
+  for (size_t j = 0; j < img.size(); ++j) {
+    const double det = 1.0 - std::norm(kappa_of(L, img[j]));
+    A += 1.0 / std::abs(det);
+    if (mu_signed) mu_signed[j] = 1.0 / det;
+  }
+  if (n_img) *n_img = static_cast<int>(img.size());
+  return A;
+}
+
+double orc_brightness(double x, double u1) { return brightness(x, u1); }
+double orc_edge_factor(double delta, double u1, double delta_c) { return edge_factor(delta, u1, delta_c); }
+double orc_crossing_t(const double* d4, int cubic, double rho) { return crossing_t(d4, cubic, rho); }
+
+// Sectors from given image-limb points (r, theta); returns the count (<= cap).
+int orc_build_sectors(int n_pts, const double* r, const double* th, double rho, int cap, double* sec, int* periodic,
+                      uint32_t* status) {
+  std::vector<double> rr(r, r + n_pts), tt(th, th + n_pts);
+  std::vector<Sector> S;
+  const uint32_t st = build_sectors(rr, tt, rho, cap, S);
+  for (size_t s = 0; s < S.size(); ++s) {
+    sec[4 * s + 0] = S[s].r_lo;
+    sec[4 * s + 1] = S[s].r_hi;
+    sec[4 * s + 2] = S[s].th_lo;
+    sec[4 * s + 3] = S[s].th_hi;
+    periodic[s] = S[s].periodic ? 1 : 0;
+  }
+  if (status) *status = st;
+  return static_cast<int>(S.size());
+}
+
+// Quadrature over one given sector (no retries).  Returns the un-normalised flux
+// (divide by rho^2 for the sector's magnification share).
+double orc_sector_flux(int n, const double* eps, const double* a, const double* wc, double rho, double u1,
+                       double delta_c, int nr, int nth, const double* sec4, int periodic, int* clip) {
+  const Lens L = lens_from(n, eps, a);
+  Sector S{sec4[0], sec4[1], sec4[2], sec4[3], periodic != 0};
+  return sector_flux(L, cplx(wc[0], wc[1]), rho, u1, delta_c, nr, nth, S, clip);
+}
+
+// Whole light curve for one event.  params: [s, q, u0, alpha, t0, tE, rho, u1, q3, r3, psi].
+// sec_out: [n_epochs][kmax][4] (r_lo, r_hi, th_lo, th_hi), periodic_out [n_epochs][kmax],
+// nsec_out [n_epochs]; any of these may be NULL.  a_ps_out [n_epochs] may be NULL.
+void orc_magnification(int n_lens, const double* params, int64_t n_epochs, const double* t, int n_limb, int n_r,
+                       int n_theta, double delta_c, int max_retries, int kmax, double* mag, uint32_t* status,
+                       double* sec_out, uint8_t* periodic_out, int32_t* nsec_out, double* a_ps_out) {
+  const Lens L = make_lens(n_lens, params);
+  const Config cfg{n_limb, n_r, n_theta, max_retries, delta_c};
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t e = 0; e < n_epochs; ++e) {
+    std::vector<Sector> S;
+    uint32_t st = 0;
+    double aps = 0.0;
+    mag[e] = epoch_magnification(L, params, t[e], cfg, &st, S, &aps, nullptr);
+    status[e] = st;
+    if (a_ps_out) a_ps_out[e] = aps;
+    if (nsec_out) nsec_out[e] = static_cast<int32_t>(S.size());
+    for (size_t s = 0; s < S.size() && static_cast<int>(s) < kmax; ++s) {
+      if (sec_out) {
+        double* o = sec_out + (e * kmax + s) * 4;
+        o[0] = S[s].r_lo;
+        o[1] = S[s].r_hi;
+        o[2] = S[s].th_lo;
+        o[3] = S[s].th_hi;
+      }
+      if (periodic_out) periodic_out[e * kmax + s] = S[s].periodic ? 1 : 0;
+    }
+  }
+}
+
+// Same quadrature on caller-given sectors (one pass, no retries): the "given grid" mode.
+void orc_magnification_given(int n_lens, const double* params, int64_t n_epochs, const double* t, int n_r,
+                             int n_theta, double delta_c, int kmax, const double* sec, const uint8_t* periodic,
+                             const int32_t* nsec, double* mag, uint32_t* status) {
+  const Lens L = make_lens(n_lens, params);
+  const double rho = params[6], u1 = params[7];
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t e = 0; e < n_epochs; ++e) {
+    const cplx wc = source_center(params, t[e]);
+    double flux = 0.0;
+    uint32_t st = ST_GIVEN;
+    for (int s = 0; s < nsec[e]; ++s) {
+      const double* g = sec + (e * kmax + s) * 4;
+      Sector S{g[0], g[1], g[2], g[3], periodic[e * kmax + s] != 0};
+      int clip = 0;
+      flux += sector_flux(L, wc, rho, u1, delta_c, n_r, n_theta, S, &clip);
+      if (clip) st |= ST_CLIP;
+    }
+    mag[e] = flux / (rho * rho);
+    if (!std::isfinite(mag[e])) st |= ST_NAN;
+    status[e] = st;
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,373 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix (CPU only).
+
+Each test ties one oracle step to something other than itself: a closed form, a library
+routine (LAPACK eigenvalues through numpy.roots), an independent brute-force computation,
+or an exact property of the formula the paper prints.  Together they are chosen so that a
+dropped term, a wrong sign or index, or a transposed operand in any step fails at least one.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+from oracle import oracle as O
+from tests import reference_math as R
+
+RNG = np.random.default_rng(12345)
+
+
+# --- O1/O2: frame and trajectory (Sec. 2.1, Sec. 3.5, Fig. 3) -----------------------------
+
+def test_binary_frame_masses_and_positions():
+    for s, q in [(0.9, 0.1), (1.3, 1e-4), (0.5, 1.0)]:
+        eps, a = O.frame(2, O.params(s=s, q=q))
+        assert abs(eps.sum() - 1.0) < 1e-15
+        assert abs(eps[1] / eps[0] - q) < 1e-14 * max(1, q)
+        assert abs(abs(a[1] - a[0]) - s) < 1e-14
+        assert abs((eps * a).sum()) < 1e-15            # centre of mass at the origin
+        assert a[0].real < 0 < a[1].real and np.all(a.imag == 0)
+
+
+def test_triple_frame_fig3_geometry():
+    s, q, q3, r3, psi = 1.1, 0.5, 0.03, 1.24, math.radians(76.0)   # Fig. 2 parameters
+    eps, a = O.frame(3, O.params(s=s, q=q, q3=q3, r3=r3, psi=psi))
+    assert abs(eps.sum() - 1.0) < 1e-15
+    assert abs(eps[1] / eps[0] - q) < 1e-14 and abs(eps[2] / eps[0] - q3) < 1e-14
+    assert abs(abs(a[1] - a[0]) - s) < 1e-14
+    mid = 0.5 * (a[0] + a[1])
+    assert abs(a[2] - mid - r3 * np.exp(1j * psi)) < 1e-14
+    # origin at the M1-M2 barycentre
+    assert abs(eps[0] * a[0] + eps[1] * a[1]) < 1e-15
+
+
+def test_trajectory_conventions():
+    p = O.params(u0=0.12, alpha=0.7, t0=3.0, tE=25.0)
+    w0 = O.source_center(p, 3.0)
+    assert abs(abs(w0) - 0.12) < 1e-15
+    w1 = O.source_center(p, 28.0)
+    assert abs((w1 - w0) - np.exp(0.7j)) < 1e-15
+    assert abs((np.conj(w0) * (w1 - w0)).real) < 1e-15   # closest approach is perpendicular
+
+
+# --- O4/O5/O6: polynomial, EA roots, validation (Sec. 2.1, Sec. 3.1) ---------------------
+
+def _random_lens(n):
+    if n == 2:
+        p = O.params(s=float(np.exp(RNG.uniform(np.log(0.5), np.log(2.0)))), q=float(10 ** RNG.uniform(-4, 0)))
+    else:
+        p = O.params(s=float(RNG.uniform(0.7, 1.4)), q=float(10 ** RNG.uniform(-3, 0)),
+                     q3=float(10 ** RNG.uniform(-3, -1)), r3=float(RNG.uniform(0.5, 1.5)),
+                     psi=float(RNG.uniform(0, 2 * np.pi)))
+    return O.frame(n, p)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_polynomial_degree_and_images_are_roots(n):
+    for _ in range(6):
+        eps, a = _random_lens(n) if n > 1 else (np.array([1.0]), np.array([0j]))
+        w = complex(*RNG.uniform(-0.6, 0.6, 2))
+        c = O.lens_poly(eps, a, w)
+        assert c.size - 1 == n * n + 1                    # 5(N-1) for N = 2, 3 (Sec. 2.1)
+        lead = np.prod([np.conj(w) - np.conj(ak) for ak in a])
+        assert abs(c[-1] - lead) < 1e-12 * max(1, abs(lead))
+        imgs = R.newton_images(eps, a, w)               # found without any polynomial
+        assert imgs.size >= n + 1
+        for z in imgs:
+            val = np.polyval(c[::-1], z)
+            scale = np.sum(np.abs(c) * np.abs(z) ** np.arange(c.size))
+            assert abs(val) <= 1e-11 * scale
+
+
+@pytest.mark.parametrize("n", [2, 3])
+def test_ea_roots_match_lapack_companion(n):
+    for _ in range(40):
+        eps, a = _random_lens(n)
+        w = complex(*RNG.uniform(-0.5, 0.5, 2))
+        c = O.lens_poly(eps, a, w)
+        roots, ok, iters = O.ea_roots(c)
+        assert ok and iters < 500
+        ref = np.roots(c[::-1])                         # LAPACK eigenvalues of the companion matrix
+        assert R.roots_match_conditioned(roots, ref, c)
+
+
+def test_ea_generic_polynomials():
+    for deg in (3, 5, 10):
+        for _ in range(5):
+            c = RNG.normal(size=deg + 1) + 1j * RNG.normal(size=deg + 1)
+            roots, ok, _ = O.ea_roots(c)
+            assert ok
+            assert R.multiset_close(roots, np.roots(c[::-1]), 1e-9)
+
+
+@pytest.mark.parametrize("n", [2, 3])
+def test_validated_images_match_bruteforce_newton(n):
+    for _ in range(10):
+        eps, a = _random_lens(n)
+        w = complex(*RNG.uniform(-0.5, 0.5, 2))
+        imgs, st = O.images(eps, a, w)
+        ref = R.newton_images(eps, a, w)
+        assert R.multiset_close(imgs, ref, 1e-8), (imgs, ref)
+        assert st & O.ST_IMG_COUNT == 0
+        assert imgs.size in ((3, 5) if n == 2 else (4, 6, 8, 10))
+
+
+# --- O7: point-source magnification (eqs. amp_point, detJ) ------------------------------
+
+def test_single_lens_point_magnification_closed_form():
+    for u in [0.01, 0.1, 0.5, 1.0, 2.5]:
+        A, mu = O.point_mag([1.0], [0j], complex(u, 0.0) * np.exp(0.3j))
+        assert mu.size == 2
+        assert abs(A - R.point_lens_mag(u)) < 1e-12 * R.point_lens_mag(u)
+
+
+def test_binary_signed_magnification_sum_inside_caustic():
+    """Binary lens, 5 images: the signed magnifications sum to one (Witt & Mao 1995)."""
+    eps, a = O.frame(2, O.params(s=0.9, q=0.1))
+    seen = 0
+    for _ in range(400):
+        w = complex(*RNG.uniform(-0.15, 0.15, 2))
+        if R.newton_images(eps, a, w).size != 5:
+            continue
+        A, mu = O.point_mag(eps, a, w)
+        assert mu.size == 5
+        assert abs(mu.sum() - 1.0) < 1e-9
+        assert abs(A - np.abs(mu).sum()) < 1e-12 * A
+        seen += 1
+        if seen >= 10:
+            break
+    assert seen >= 5
+
+
+# --- App. A: brightness, edge factor and crossing ----------------------------------------
+
+@pytest.mark.parametrize("u1", [0.0, 0.3, 0.5, 0.9])
+def test_brightness_integrates_to_unit_flux(u1):
+    val = integrate.quad(lambda x: O.brightness(x, u1) * 2 * np.pi * x, 0, 1, epsabs=0, epsrel=1e-13)[0]
+    assert abs(val - 1.0) < 1e-12
+    assert abs(O.brightness(1.0, u1) - 3 * (1 - u1) / (np.pi * (3 - u1))) < 1e-15
+
+
+def test_edge_factor_is_exact_for_sqrt_profile():
+    """Above delta_c, f(delta) sqrt(delta) is the integral of sqrt(x) over the node's
+    partial cell [0, delta + 1/2] (App. A.2, b(delta)); below, the linear branch."""
+    for d in [0.1, 0.2, 0.5, 0.77, 1.0]:
+        assert abs(O.edge_factor(d, 0.5, 0.1) * math.sqrt(d) - (2 / 3) * (d + 0.5) ** 1.5) < 1e-14
+    for d in [0.0, 0.03, 0.0999]:
+        assert abs(O.edge_factor(d, 0.5, 0.1) - ((2 / 3) * d + 0.5)) < 1e-15
+    for d in [0.0, 0.3, 1.0]:                             # uniform source, App. A.1
+        assert O.edge_factor(d, 0.0, 0.1) == d + 0.5
+
+
+def test_cubic_crossing_exact_on_cubic_data():
+    rho = 0.37
+    for _ in range(50):
+        # a cubic in t with exactly one real root r in (0.05, 0.95) crossing rho
+        r = RNG.uniform(0.05, 0.95)
+        c2 = complex(RNG.uniform(-3, 3), RNG.uniform(0.5, 2.0))
+        poly = np.poly([r, c2, np.conj(c2)]).real * RNG.choice([-1, 1]) * RNG.uniform(0.2, 2)
+        d4 = [np.polyval(poly, t) + rho for t in (-1.0, 0.0, 1.0, 2.0)]
+        t = O.crossing_t(d4, 1, rho)
+        assert abs(t - r) < 1e-14
+    # linear at an edge
+    assert abs(O.crossing_t([0, 0.2, 0.6, 0], 0, 0.3) - 0.25) < 1e-15
+
+
+# --- O9-O11: quadrature against the identity map (A = 1) ---------------------------------
+
+def _identity_sector(wc, rho, pad=0.15):
+    r0, th0 = abs(wc), np.angle(wc)
+    dth = math.asin(rho / r0) * (1 + pad)
+    return [r0 - rho * (1 + pad), r0 + rho * (1 + pad), th0 - dth, th0 + dth]
+
+
+@pytest.mark.parametrize("u1", [0.0, 0.5])
+def test_identity_map_quadrature_converges_to_one(u1):
+    wc, rho = 1.0 + 0.2j, 0.1
+    sec = _identity_sector(wc, rho)
+    errs = []
+    for nr, nth in [(32, 128), (64, 256), (256, 1024)]:
+        f, clip = O.sector_flux([], [], wc, rho, u1, nr, nth, sec)
+        assert clip == 0
+        errs.append(abs(f / rho ** 2 - 1.0))
+    assert errs[1] < 2e-3 and errs[2] < 3e-4
+    assert errs[2] < errs[0]
+
+
+@pytest.mark.parametrize("u1", [0.0, 0.5])
+def test_identity_map_full_pipeline(u1):
+    """n_lens = 0: the 'polynomial' is z - w, the limb images are the limb points; the
+    whole path (limb sampling, binning, margins, grid, rows) must give A = 1."""
+    p = O.params(u0=0.8, alpha=0.3, t0=0.0, tE=10.0, rho=0.05, u1=u1)
+    r = O.magnification(0, p, [-3.0, 0.0, 4.0], n_limb=64, n_r=128, n_theta=512)
+    assert np.all(r["nsec"] == 1) and np.all(r["status"] == 0)
+    assert np.all(np.abs(r["mag"] - 1.0) < 5e-4)
+
+
+# --- end to end: single-lens closed forms and limits -------------------------------------
+
+@pytest.mark.parametrize("rho", [0.1, 0.01])
+def test_centered_uniform_source_single_lens(rho):
+    """Source centred on a point lens: a ring image with every row fully in or out.  The
+    quadrature must equal the plain midpoint sum over the rows whose ring radius maps inside,
+    and converge (first order, the radial integrand is a step) to sqrt(1 + 4/rho^2)."""
+    exact = math.sqrt(1 + 4 / rho ** 2)
+    p = O.params(u0=0.0, alpha=0.0, t0=0.0, tE=1.0, rho=rho, u1=0.0)
+    prev = None
+    for nr in (64, 256, 1024):
+        r = O.magnification(1, p, [0.0], n_limb=64, n_r=nr, n_theta=64)
+        assert r["nsec"][0] == 1 and r["periodic"][0, 0] == 1
+        lo, hi = r["sectors"][0, 0, :2]
+        dr = (hi - lo) / nr
+        ri = lo + (np.arange(nr) + 0.5) * dr
+        inside = np.abs(ri - 1.0 / ri) < rho
+        riemann = np.sum(2 * np.pi * ri[inside] * dr) / (np.pi * rho ** 2)
+        assert abs(r["mag"][0] - riemann) < 1e-12 * riemann
+        err = abs(r["mag"][0] / exact - 1)
+        assert err < 3.0 / nr
+        prev = err
+    assert prev < 3e-3
+
+
+def test_centered_limb_darkened_single_lens():
+    rho, u1 = 0.05, 0.6
+    p = O.params(rho=rho, u1=u1)
+    r = O.magnification(1, p, [0.0], n_limb=64, n_r=512, n_theta=32)
+    lo, hi = r["sectors"][0, 0, :2]
+    dr = (hi - lo) / 512
+    ri = lo + (np.arange(512) + 0.5) * dr
+    d = np.abs(ri - 1.0 / ri)
+    inside = d < rho
+    riemann = np.sum(2 * np.pi * ri[inside] * R.limb_darkened_I(d[inside] / rho, u1) * dr) / rho ** 2
+    assert abs(r["mag"][0] - riemann) < 1e-12 * riemann
+    exact = R.ld_disk_point_lens(0.0, rho, u1) if False else None  # centred: integrand singular at lens
+    # exact ring integral in the image plane
+    rp = (math.sqrt(rho ** 2 + 4) + rho) / 2
+    rm = (math.sqrt(rho ** 2 + 4) - rho) / 2
+    f = lambda x: 2 * np.pi * x * R.limb_darkened_I(abs(x - 1 / x) / rho, u1) / rho ** 2
+    exact = integrate.quad(f, rm, rp, epsabs=0, epsrel=1e-12, limit=200)[0]
+    assert abs(r["mag"][0] / exact - 1) < 5e-3
+
+
+@pytest.mark.parametrize("u_off,rho,u1", [(0.3, 0.1, 0.0), (0.05, 0.03, 0.0), (0.5, 0.05, 0.5)])
+def test_offset_single_lens_matches_disk_integral(u_off, rho, u1):
+    """Off-centre source: ICRS converges to the finite-source integral of Sec. 2.2."""
+    p = O.params(u0=u_off, alpha=0.4, rho=rho, u1=u1)
+    ref = R.uniform_disk_point_lens(u_off, rho) if u1 == 0.0 else R.ld_disk_point_lens(u_off, rho, u1)
+    r = O.magnification(1, p, [0.0], n_limb=128, n_r=256, n_theta=1024)
+    assert r["status"][0] == 0
+    assert abs(r["mag"][0] / ref - 1) < 5e-4
+
+
+def test_paper_accuracy_claim_large_source():
+    """Sec. 4.1: for rho >~ 1e-2 the relative error is below 1e-4 at N_r = 1000 and every
+    N_theta tested; checked here on a point lens (uniform source) at N_theta = 500."""
+    u_off, rho = 0.02, 0.01
+    ref = R.uniform_disk_point_lens(u_off, rho)
+    r = O.magnification(1, O.params(u0=u_off, rho=rho), [0.0], n_limb=128, n_r=1000, n_theta=500)
+    assert abs(r["mag"][0] / ref - 1) < 1e-4
+
+
+def test_small_mass_ratio_limit():
+    """q -> 0: a binary with q = 1e-12 is a unit point lens at the origin (centred source)."""
+    rho = 0.05
+    p = O.params(s=1.5, q=1e-12, u0=0.0, rho=rho)
+    r = O.magnification(2, p, [0.0], n_limb=64, n_r=1024, n_theta=256)
+    exact = math.sqrt(1 + 4 / rho ** 2)
+    assert abs(r["mag"][0] / exact - 1) < 3e-3
+
+
+def test_large_separation_limit():
+    """s = 1e3, q = 1: near one lens the other adds only a constant deflection (and a shear
+    ~ eps/s^2 ~ 5e-7), so A is the single-lens value with u, rho scaled by 1/sqrt(eps).
+    The third image sits 5e-4 from the far lens at |z| ~ 500, where z - a_2 keeps only ~6
+    digits: its lens-equation residual cannot reach the absolute 1e-10 gate, so it is
+    dropped and IMG_COUNT is raised; its magnification is ~1e-13, so A is unaffected."""
+    s, rho = 1000.0, 0.01
+    eps, a = O.frame(2, O.params(s=s, q=1.0))
+    p = O.params(s=s, q=1.0, u0=0.04, alpha=0.0, t0=0.0, tE=1.0, rho=rho)
+    t = a[0].real + 0.05                            # source near lens 1 (theta = pi wrap)
+    wc = O.source_center(p, t)
+    w_eff = wc + eps[1] / np.conj(a[0] - a[1])
+    u = abs(w_eff - a[0]) / math.sqrt(eps[0])
+    ref = R.uniform_disk_point_lens(u, rho / math.sqrt(eps[0]))
+    errs = []
+    for nr, nth in [(128, 512), (512, 1024)]:
+        r = O.magnification(2, p, [t], n_limb=128, n_r=nr, n_theta=nth)
+        assert r["status"][0] == O.ST_IMG_COUNT and r["nsec"][0] == 2
+        errs.append(abs(r["mag"][0] / ref - 1))
+    assert errs[0] < 1e-3 and errs[1] < 1e-4
+
+
+@pytest.mark.parametrize("u1", [0.0, 0.5])
+def test_point_source_limit_far_from_caustics(u1):
+    """rho = 1e-4 far from caustics: A_ICRS -> A_ps + O(rho^2) as the grid refines."""
+    p = O.params(s=0.9, q=0.1, u0=0.4, alpha=0.6, t0=0, tE=20, rho=1e-4, u1=u1)
+    errs = []
+    for nr, nth in [(64, 256), (256, 1024), (2048, 4096)]:
+        r = O.magnification(2, p, [-12.0, 9.0], n_limb=64, n_r=nr, n_theta=nth)
+        errs.append(np.max(np.abs(r["mag"] / r["a_ps"] - 1)))
+    assert errs[0] < 2e-3 and errs[1] < 5e-4 and errs[2] < 3e-5
+    assert errs[2] < errs[1] < errs[0]
+
+
+# --- any geometry: brute-force Cartesian inverse ray shooting ----------------------------
+
+@pytest.mark.slow
+@pytest.mark.parametrize("t,u1", [(-3.0, 0.5), (0.0, 0.0), (16.5, 0.5)])
+def test_binary_against_bruteforce_irs(t, u1):
+    p = O.params(s=0.9, q=0.1, u0=0.05, alpha=0.6, t0=0, tE=20, rho=0.05, u1=u1)
+    eps, a = O.frame(2, p)
+    wc = O.source_center(p, t)
+    ref = R.brute_force_irs(eps, a, wc, 0.05, u1, half=2.0, npix=8192)
+    r = O.magnification(2, p, [t], n_limb=128, n_r=256, n_theta=1024)
+    assert abs(r["mag"][0] / ref - 1) < 1e-3, (r["mag"][0], ref)
+
+
+# --- O8: sector construction on hand-made point clouds -----------------------------------
+
+def _margin(lo, hi, floor):
+    m = 0.1 * (hi - lo) + floor
+    return lo - m, hi + m
+
+
+def test_sectors_two_clusters_and_margins():
+    rho = 0.01
+    th = np.concatenate([np.linspace(0.40, 0.60, 20), np.linspace(1.90, 2.10, 20)])
+    r = np.concatenate([np.linspace(0.98, 1.02, 20), np.linspace(0.99, 1.01, 20)])
+    sec, per, st = O.build_sectors(r, th, rho, 5)
+    assert sec.shape[0] == 2 and not per.any() and st == 0
+    rlo, rhi = _margin(0.98, 1.02, rho / 100)
+    tlo, thi = _margin(0.40, 0.60, rho / (100 * 1.0))
+    assert np.allclose(sec[0], [rlo, rhi, tlo, thi], rtol=0, atol=1e-14)
+
+
+def test_sectors_wrap_across_pi():
+    th = np.concatenate([np.linspace(2.95, np.pi, 10), np.linspace(-np.pi + 0.01, -2.95, 10)])
+    r = np.full(th.size, 1.1)
+    sec, per, _ = O.build_sectors(r, th, 0.01, 5)
+    assert sec.shape[0] == 1 and not per[0]
+    tlo, thi = _margin(2.95, -2.95 + 2 * np.pi, 0.01 / (100 * 1.1))   # unwrapped across +-pi
+    assert np.allclose(sec[0, 2:], [tlo, thi], rtol=0, atol=1e-14)
+
+
+def test_sectors_full_ring_and_radial_split():
+    th = np.linspace(-np.pi, np.pi, 200, endpoint=False)
+    r = np.concatenate([np.full(100, 0.5), np.full(100, 1.5)])
+    th = np.concatenate([th[::2], th[1::2]])
+    sec, per, _ = O.build_sectors(r, th, 0.001, 5)
+    assert sec.shape[0] == 2 and per.all()
+    assert np.allclose(sec[:, 2], -np.pi) and np.allclose(sec[:, 3], np.pi)
+
+
+def test_sectors_overlap_merge_and_cap():
+    rho = 0.01
+    # two clusters whose margins overlap -> one sector
+    th = np.concatenate([np.linspace(0.0, 0.2, 10), np.linspace(0.24, 0.4, 10)])
+    sec, _, _ = O.build_sectors(np.full(20, 1.0), th, rho, 5)
+    assert sec.shape[0] == 1
+    # seven separated clusters with a cap of five -> merged, flagged
+    th = np.concatenate([np.linspace(k * 0.85 - 3.0, k * 0.85 - 2.95, 5) for k in range(7)])
+    sec, _, st = O.build_sectors(np.full(th.size, 1.0), th, rho, 5)
+    assert sec.shape[0] == 5 and st & O.ST_CAP_OVERFLOW
+    assert np.all(np.diff(sec[:, 2]) >= 0)
