@@ -1,0 +1,143 @@
+/* icrs.h -- C ABI of the MI355X (gfx950) image-centred ray-shooting library.
+ *
+ * Computes finite-source magnifications of binary- and triple-lens microlensing events
+ * with a uniform or linearly limb-darkened source, by the image-centred ray-shooting (ICRS)
+ * method of Miyazaki & Kawahara, "microJAX" (arXiv 2510.02639):
+ *   - source centre on a straight trajectory (t0, u0, tE, alpha)            -- Sec. 3.5
+ *   - N_limb points on the source limb, images by Ehrlich-Aberth roots of the
+ *     lens polynomial (degree 5 or 10), validated against the lens equation -- Secs. 2.1, 3.1, 3.2
+ *   - polar sectors around the images from 1-D binning of image-limb points -- Sec. 3.2
+ *   - an N_r x N_theta polar grid per sector, every node shot back through the
+ *     lens equation, row quadrature with cubic boundary crossings and the
+ *     uniform / limb-darkened edge rules, radial sum, normalisation          -- Sec. 3.3, App. A
+ *
+ * Conventions shared by every entry point
+ *   - Units: t, t0, tE in days; alpha, psi in radians; s, u0, rho, r3 in Einstein radii of
+ *     the total lens mass.
+ *   - Event parameters are a HOST array of ICRS_N_PARAMS doubles per event:
+ *       [s, q, u0, alpha, t0, tE, rho, u_ld, q3, r3, psi]
+ *     q = m2/m1 and the primary sits at -q s/(1+q) on the real axis, the secondary at
+ *     s/(1+q) (centre of mass of the pair at the origin).  Triple lenses (n_lens = 3) add
+ *     q3 = m3/m1 at r3 e^{i psi} from the M1-M2 midpoint (paper Fig. 3); binary events
+ *     ignore the last three entries.  u_ld = 0 selects the uniform-source rule.
+ *   - Epochs are grouped by event in CSR form: a HOST array epoch_offsets[n_events + 1]
+ *     (non-decreasing, offsets[0] = 0, offsets[n_events] = n_epochs) and a DEVICE array
+ *     t[n_epochs]; epoch e belongs to the event i with offsets[i] <= e < offsets[i+1].
+ *   - Outputs mag[n_epochs] (double) and status[n_epochs] (uint32, ICRS_ST_* bits) are
+ *     DEVICE arrays owned by the caller.
+ *   - The caller owns all memory.  The library allocates nothing inside a call: device
+ *     scratch comes from a caller workspace of icrs_workspace_bytes() bytes (device memory,
+ *     256-byte aligned).  Results stay valid in the workspace until the next call using it.
+ *   - Argument errors (bad sizes, NULL pointers, out-of-range parameters, unsorted offsets)
+ *     return ICRS_EINVAL before anything is enqueued.  A workspace that is too small gives
+ *     ICRS_ENOMEM.  A HIP runtime failure gives ICRS_EHIP.
+ *   - Work is enqueued asynchronously on the handle's stream; the call may block only to
+ *     read small device counters back (clip retries).  Data-dependent failures never fail a
+ *     call: they set status bits, and an epoch without a usable result gets NaN.
+ *   - A handle must not be used from two threads at once.
+ */
+#ifndef ICRS_H_
+#define ICRS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ICRS_ABI_VERSION 1u
+#define ICRS_N_PARAMS 11
+#define ICRS_MAX_SECTORS 10 /* 5(N-1) for N = 3: the sector cap per epoch (Sec. 3.2) */
+
+typedef enum {
+  ICRS_OK = 0,
+  ICRS_EINVAL = -1,
+  ICRS_ENOMEM = -2,
+  ICRS_EHIP = -3,
+  ICRS_EUNSUPPORTED = -4
+} icrs_status;
+
+/* Per-epoch status bits. */
+#define ICRS_ST_ROOT_NONCONV 1u   /* an Ehrlich-Aberth solve reached its iteration cap */
+#define ICRS_ST_IMG_COUNT 2u      /* an image count outside {N+1, N+3, ..., 5(N-1)} after seeding */
+#define ICRS_ST_CAP_OVERFLOW 4u   /* more sector candidates than the cap: pairs were merged */
+#define ICRS_ST_CLIP 8u           /* inside rays still touch a sector edge after the retries */
+#define ICRS_ST_NAN 16u           /* the magnification is not finite */
+#define ICRS_ST_GIVEN 64u         /* sectors were supplied by the caller */
+
+/* Ray-loop precision. */
+#define ICRS_FP64 0
+#define ICRS_FP32 1
+
+typedef struct icrs_config {
+  uint32_t abi_version;  /* must be ICRS_ABI_VERSION */
+  int32_t n_lens;        /* 2 (binary, degree-5 polynomial) or 3 (triple, degree 10) */
+  int32_t n_limb;        /* limb points per epoch for image finding, 8..256 (Sec. 3.2) */
+  int32_t n_r;           /* radial grid nodes per sector, 4..4096 (Sec. 3.3) */
+  int32_t n_theta;       /* angular grid nodes per sector, multiple of 64, 64..4096 (Sec. 3.3) */
+  int32_t ray_precision; /* ICRS_FP64 or ICRS_FP32 (FP32 rays relative to an FP64 anchor) */
+  int32_t root_precision;/* ICRS_FP64: FP64 Ehrlich-Aberth; ICRS_FP32: FP32 EA then FP64 polish */
+  int32_t max_retries;   /* sector-widening retries after an edge touch, 0..4 */
+  double delta_c;        /* threshold of the limb-darkened edge rule (App. A.2), 0 <= delta_c <= 1 */
+} icrs_config;
+
+typedef struct icrs_handle icrs_handle;
+
+/* Fill *cfg with the defaults: binary, N_limb 64, 64 x 256 grid, FP64 everywhere,
+ * 2 retries, delta_c = 0.1. */
+void icrs_default_config(icrs_config* cfg);
+
+/* Create a handle bound to a HIP stream (hipStream_t passed as void*, NULL = default
+ * stream) on the current device.  Validates the configuration (ICRS_EINVAL if invalid).
+ * The handle holds no device memory. */
+icrs_status icrs_create(const icrs_config* cfg, void* hip_stream, icrs_handle** out);
+void icrs_destroy(icrs_handle* h);
+
+/* Device workspace needed for a call over n_events events and n_epochs epochs. */
+size_t icrs_workspace_bytes(const icrs_handle* h, int64_t n_events, int64_t n_epochs);
+
+/* Plain ICRS light curves (the full path: trajectory, limb images, sectors, rays,
+ * quadrature, retries).  params: HOST [n_events][ICRS_N_PARAMS]; epoch_offsets: HOST
+ * [n_events + 1]; t: DEVICE [n_epochs]; mag, status: DEVICE [n_epochs] outputs;
+ * workspace: DEVICE, workspace_bytes >= icrs_workspace_bytes(h, n_events, n_epochs).
+ * Valid parameter ranges: s > 0, q > 0, tE > 0, 0 < rho <= 1, 0 <= u_ld < 1, and for
+ * triples q3 > 0, r3 >= 0; all finite.  After the call the final sectors of every epoch
+ * can be read with icrs_get_sectors(). */
+icrs_status icrs_magnification(icrs_handle* h, int64_t n_events, const double* params,
+                               const int64_t* epoch_offsets, int64_t n_epochs, const double* t,
+                               double* mag, uint32_t* status, void* workspace,
+                               size_t workspace_bytes);
+
+/* The same quadrature on caller-given sectors: one pass, no retries (status gets
+ * ICRS_ST_GIVEN, plus ICRS_ST_CLIP if inside rays touch an edge).  sectors: DEVICE
+ * [n_epochs][ICRS_MAX_SECTORS][4] doubles (r_lo, r_hi, theta_lo, theta_hi) with
+ * 0 <= r_lo < r_hi and theta_lo < theta_hi; periodic: DEVICE [n_epochs][ICRS_MAX_SECTORS]
+ * bytes (1 = full ring, theta range 2 pi wrapped); n_sectors: DEVICE [n_epochs] int32 in
+ * 0..ICRS_MAX_SECTORS.  Entries past n_sectors[e] are ignored. */
+icrs_status icrs_magnification_given(icrs_handle* h, int64_t n_events, const double* params,
+                                     const int64_t* epoch_offsets, int64_t n_epochs,
+                                     const double* t, const double* sectors,
+                                     const uint8_t* periodic, const int32_t* n_sectors,
+                                     double* mag, uint32_t* status, void* workspace,
+                                     size_t workspace_bytes);
+
+/* Copy the final sectors of the last icrs_magnification() on this workspace into DEVICE
+ * arrays laid out as in icrs_magnification_given(). */
+icrs_status icrs_get_sectors(icrs_handle* h, const void* workspace, int64_t n_epochs,
+                             double* sectors, uint8_t* periodic, int32_t* n_sectors);
+
+/* Point-source images of every epoch's source centre (Sec. 2.1, eqs. amp_point and detJ):
+ * images: DEVICE [n_epochs][10][2] doubles (re, im), n_images: DEVICE [n_epochs] int32,
+ * a_ps: DEVICE [n_epochs] doubles = sum_j 1/|det J(z_j)|.  Any of the three may be NULL. */
+icrs_status icrs_point_images(icrs_handle* h, int64_t n_events, const double* params,
+                              const int64_t* epoch_offsets, int64_t n_epochs, const double* t,
+                              double* images, int32_t* n_images, double* a_ps, void* workspace,
+                              size_t workspace_bytes);
+
+const char* icrs_status_string(icrs_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ICRS_H_ */

@@ -1,0 +1,280 @@
+// icrs_api.hip -- host side of the C ABI declared in include/icrs.h: argument checks,
+// workspace carving, and the launch sequence of one call.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+
+#include "../../include/icrs.h"
+#include "icrs_launch.hpp"
+
+struct icrs_handle {
+  icrs_config cfg;
+  hipStream_t stream;
+};
+
+namespace {
+
+using icrs::Batch;
+using icrs::RayWork;
+using icrs::SectorBuf;
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+struct Layout {
+  size_t params, offsets, epoch_event, sectors, periodic, nsec, partial, clip, list_a, list_b, counters, total;
+};
+
+Layout layout_for(int64_t n_events, int64_t n_epochs) {
+  Layout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  const size_t E = (size_t)n_epochs, V = (size_t)n_events;
+  // per-epoch blocks first (their offsets depend on n_epochs only), event blocks last
+  L.sectors = take(E * ICRS_MAX_SECTORS * 4 * sizeof(double));
+  L.periodic = take(E * ICRS_MAX_SECTORS);
+  L.nsec = take(E * sizeof(int32_t));
+  L.partial = take(E * ICRS_MAX_SECTORS * sizeof(double));
+  L.clip = take(E * ICRS_MAX_SECTORS);
+  L.epoch_event = take(E * sizeof(int32_t));
+  L.list_a = take(E * sizeof(int32_t));
+  L.list_b = take(E * sizeof(int32_t));
+  L.counters = take(64);
+  L.params = take(V * ICRS_N_PARAMS * sizeof(double));
+  L.offsets = take((V + 1) * sizeof(int64_t));
+  L.total = o;
+  return L;
+}
+
+bool config_ok(const icrs_config* c) {
+  if (!c || c->abi_version != ICRS_ABI_VERSION) return false;
+  if (c->n_lens != 2 && c->n_lens != 3) return false;
+  if (c->n_limb < 8 || c->n_limb > 256) return false;
+  if (c->n_r < 4 || c->n_r > 4096) return false;
+  if (c->n_theta < 64 || c->n_theta > 1024) return false;
+  if (c->ray_precision != ICRS_FP64 && c->ray_precision != ICRS_FP32) return false;
+  if (c->root_precision != ICRS_FP64 && c->root_precision != ICRS_FP32) return false;
+  if (c->max_retries < 0 || c->max_retries > 4) return false;
+  if (!(c->delta_c >= 0.0 && c->delta_c <= 1.0)) return false;
+  return true;
+}
+
+bool finite_all(const double* p, int n) {
+  for (int i = 0; i < n; ++i)
+    if (!isfinite(p[i])) return false;
+  return true;
+}
+
+// host checks of the event parameters and the CSR offsets
+bool events_ok(const icrs_config& c, int64_t n_events, const double* params, const int64_t* off, int64_t n_epochs) {
+  if (n_events < 0 || n_epochs < 0) return false;
+  if (n_epochs > 0x7fffffffLL / ICRS_MAX_SECTORS) return false;
+  if (n_events > 0x7fffffffLL) return false;
+  if (n_events > 0 && (!params || !off)) return false;
+  if (n_events == 0) return n_epochs == 0;
+  if (off[0] != 0 || off[n_events] != n_epochs) return false;
+  for (int64_t i = 0; i < n_events; ++i)
+    if (off[i + 1] < off[i]) return false;
+  for (int64_t i = 0; i < n_events; ++i) {
+    const double* p = params + i * ICRS_N_PARAMS;
+    if (!finite_all(p, c.n_lens == 3 ? ICRS_N_PARAMS : 8)) return false;
+    if (!(p[0] > 0.0 && p[1] > 0.0 && p[5] > 0.0)) return false;
+    if (!(p[6] > 0.0 && p[6] <= 1.0)) return false;
+    if (!(p[7] >= 0.0 && p[7] < 1.0)) return false;
+    if (c.n_lens == 3 && !(p[8] > 0.0 && p[9] >= 0.0)) return false;
+  }
+  return true;
+}
+
+icrs_status hip_status(hipError_t e) { return e == hipSuccess ? ICRS_OK : ICRS_EHIP; }
+
+#define ICRS_TRY(expr)                       \
+  do {                                       \
+    const hipError_t err_ = (expr);          \
+    if (err_ != hipSuccess) return ICRS_EHIP; \
+  } while (0)
+
+struct Views {
+  Batch b;
+  SectorBuf sec;
+  double* partial;
+  uint8_t* clip;
+  int32_t* list_a;
+  int32_t* list_b;
+  int32_t* counters;
+};
+
+icrs_status prepare(icrs_handle* h, int64_t n_events, const double* params, const int64_t* off, int64_t n_epochs,
+                    const double* t, void* ws, size_t ws_bytes, Views* v) {
+  const Layout L = layout_for(n_events, n_epochs);
+  if (!ws || ws_bytes < L.total) return ws ? ICRS_ENOMEM : ICRS_EINVAL;
+  if (((uintptr_t)ws & (kAlign - 1)) != 0) return ICRS_EINVAL;
+  char* base = (char*)ws;
+  v->b.params = (const double*)(base + L.params);
+  v->b.offsets = (const int64_t*)(base + L.offsets);
+  v->b.epoch_event = (const int32_t*)(base + L.epoch_event);
+  v->b.t = t;
+  v->b.n_events = n_events;
+  v->b.n_epochs = n_epochs;
+  v->sec.sectors = (double*)(base + L.sectors);
+  v->sec.periodic = (uint8_t*)(base + L.periodic);
+  v->sec.nsec = (int32_t*)(base + L.nsec);
+  v->partial = (double*)(base + L.partial);
+  v->clip = (uint8_t*)(base + L.clip);
+  v->list_a = (int32_t*)(base + L.list_a);
+  v->list_b = (int32_t*)(base + L.list_b);
+  v->counters = (int32_t*)(base + L.counters);
+  if (n_events == 0) return ICRS_OK;
+  ICRS_TRY(hipMemcpyAsync(base + L.params, params, (size_t)n_events * ICRS_N_PARAMS * sizeof(double),
+                          hipMemcpyHostToDevice, h->stream));
+  ICRS_TRY(hipMemcpyAsync(base + L.offsets, off, (size_t)(n_events + 1) * sizeof(int64_t), hipMemcpyHostToDevice,
+                          h->stream));
+  ICRS_TRY(icrs::launch_epoch_event(v->b, (int32_t*)(base + L.epoch_event), h->stream));
+  return ICRS_OK;
+}
+
+// rays + finalize with up to max_retries widening passes
+icrs_status run_rays(icrs_handle* h, const Views& v, int max_retries, double* mag, uint32_t* status,
+                     uint32_t extra_status) {
+  const icrs_config& c = h->cfg;
+  RayWork w{nullptr, v.b.n_epochs};
+  int32_t* cur = v.list_a;
+  int32_t* nxt = v.list_b;
+  for (int attempt = 0;; ++attempt) {
+    ICRS_TRY(icrs::launch_rays(c.n_lens, c.ray_precision, v.b, v.sec, w, c.n_r, c.n_theta, c.delta_c, v.partial,
+                               v.clip, h->stream));
+    ICRS_TRY(icrs::launch_fill_i32(v.counters, 1, 0, h->stream));
+    ICRS_TRY(icrs::launch_finalize(v.b, v.sec, w, v.partial, v.clip, attempt, max_retries, nxt, v.counters, mag,
+                                   status, extra_status, h->stream));
+    if (attempt >= max_retries) break;
+    int32_t count = 0;
+    ICRS_TRY(hipMemcpyAsync(&count, v.counters, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+    ICRS_TRY(hipStreamSynchronize(h->stream));
+    if (count == 0) break;
+    w = RayWork{nxt, count};
+    int32_t* tmp = cur;
+    cur = nxt;
+    nxt = tmp;
+  }
+  return ICRS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void icrs_default_config(icrs_config* cfg) {
+  if (!cfg) return;
+  memset(cfg, 0, sizeof(*cfg));
+  cfg->abi_version = ICRS_ABI_VERSION;
+  cfg->n_lens = 2;
+  cfg->n_limb = 64;
+  cfg->n_r = 64;
+  cfg->n_theta = 256;
+  cfg->ray_precision = ICRS_FP64;
+  cfg->root_precision = ICRS_FP64;
+  cfg->max_retries = 2;
+  cfg->delta_c = 0.1;
+}
+
+icrs_status icrs_create(const icrs_config* cfg, void* hip_stream, icrs_handle** out) {
+  if (!out || !config_ok(cfg)) return ICRS_EINVAL;
+  icrs_handle* h = new (std::nothrow) icrs_handle;
+  if (!h) return ICRS_ENOMEM;
+  h->cfg = *cfg;
+  h->stream = (hipStream_t)hip_stream;
+  *out = h;
+  return ICRS_OK;
+}
+
+void icrs_destroy(icrs_handle* h) { delete h; }
+
+size_t icrs_workspace_bytes(const icrs_handle* h, int64_t n_events, int64_t n_epochs) {
+  (void)h;
+  if (n_events < 0 || n_epochs < 0) return 0;
+  return layout_for(n_events, n_epochs).total;
+}
+
+icrs_status icrs_magnification(icrs_handle* h, int64_t n_events, const double* params, const int64_t* epoch_offsets,
+                               int64_t n_epochs, const double* t, double* mag, uint32_t* status, void* workspace,
+                               size_t workspace_bytes) {
+  if (!h || !events_ok(h->cfg, n_events, params, epoch_offsets, n_epochs)) return ICRS_EINVAL;
+  if (n_epochs > 0 && (!t || !mag || !status)) return ICRS_EINVAL;
+  Views v;
+  const icrs_status ps = prepare(h, n_events, params, epoch_offsets, n_epochs, t, workspace, workspace_bytes, &v);
+  if (ps != ICRS_OK || n_epochs == 0) return ps;
+  const icrs_config& c = h->cfg;
+  const int fp32_roots = c.root_precision == ICRS_FP32;
+  ICRS_TRY(icrs::launch_centre_images(c.n_lens, fp32_roots, v.b, nullptr, nullptr, nullptr, status, h->stream));
+  ICRS_TRY(icrs::launch_limb_sectors(c.n_lens, fp32_roots, c.n_limb, v.b, v.sec, status, h->stream));
+  return run_rays(h, v, c.max_retries, mag, status, 0u);
+}
+
+icrs_status icrs_magnification_given(icrs_handle* h, int64_t n_events, const double* params,
+                                     const int64_t* epoch_offsets, int64_t n_epochs, const double* t,
+                                     const double* sectors, const uint8_t* periodic, const int32_t* n_sectors,
+                                     double* mag, uint32_t* status, void* workspace, size_t workspace_bytes) {
+  if (!h || !events_ok(h->cfg, n_events, params, epoch_offsets, n_epochs)) return ICRS_EINVAL;
+  if (n_epochs > 0 && (!t || !mag || !status || !sectors || !periodic || !n_sectors)) return ICRS_EINVAL;
+  Views v;
+  const icrs_status ps = prepare(h, n_events, params, epoch_offsets, n_epochs, t, workspace, workspace_bytes, &v);
+  if (ps != ICRS_OK || n_epochs == 0) return ps;
+  const size_t E = (size_t)n_epochs;
+  ICRS_TRY(hipMemcpyAsync(v.sec.sectors, sectors, E * ICRS_MAX_SECTORS * 4 * sizeof(double),
+                          hipMemcpyDeviceToDevice, h->stream));
+  ICRS_TRY(hipMemcpyAsync(v.sec.periodic, periodic, E * ICRS_MAX_SECTORS, hipMemcpyDeviceToDevice, h->stream));
+  ICRS_TRY(hipMemcpyAsync(v.sec.nsec, n_sectors, E * sizeof(int32_t), hipMemcpyDeviceToDevice, h->stream));
+  ICRS_TRY(icrs::launch_fill_u32(status, n_epochs, 0u, h->stream));
+  return run_rays(h, v, 0, mag, status, ICRS_ST_GIVEN);
+}
+
+icrs_status icrs_get_sectors(icrs_handle* h, const void* workspace, int64_t n_epochs, double* sectors,
+                             uint8_t* periodic, int32_t* n_sectors) {
+  if (!h || !workspace || n_epochs < 0) return ICRS_EINVAL;
+  if (n_epochs == 0) return ICRS_OK;
+  if (!sectors || !periodic || !n_sectors) return ICRS_EINVAL;
+  const Layout L = layout_for(0, n_epochs);
+  const char* base = (const char*)workspace;
+  const size_t E = (size_t)n_epochs;
+  ICRS_TRY(hipMemcpyAsync(sectors, base + L.sectors, E * ICRS_MAX_SECTORS * 4 * sizeof(double),
+                          hipMemcpyDeviceToDevice, h->stream));
+  ICRS_TRY(hipMemcpyAsync(periodic, base + L.periodic, E * ICRS_MAX_SECTORS, hipMemcpyDeviceToDevice, h->stream));
+  ICRS_TRY(hipMemcpyAsync(n_sectors, base + L.nsec, E * sizeof(int32_t), hipMemcpyDeviceToDevice, h->stream));
+  return ICRS_OK;
+}
+
+icrs_status icrs_point_images(icrs_handle* h, int64_t n_events, const double* params, const int64_t* epoch_offsets,
+                              int64_t n_epochs, const double* t, double* images, int32_t* n_images, double* a_ps,
+                              void* workspace, size_t workspace_bytes) {
+  if (!h || !events_ok(h->cfg, n_events, params, epoch_offsets, n_epochs)) return ICRS_EINVAL;
+  if (n_epochs > 0 && !t) return ICRS_EINVAL;
+  Views v;
+  const icrs_status ps = prepare(h, n_events, params, epoch_offsets, n_epochs, t, workspace, workspace_bytes, &v);
+  if (ps != ICRS_OK || n_epochs == 0) return ps;
+  const icrs_config& c = h->cfg;
+  return hip_status(icrs::launch_centre_images(c.n_lens, c.root_precision == ICRS_FP32, v.b, images, n_images, a_ps,
+                                               nullptr, h->stream));
+}
+
+const char* icrs_status_string(icrs_status s) {
+  switch (s) {
+    case ICRS_OK:
+      return "ok";
+    case ICRS_EINVAL:
+      return "invalid argument";
+    case ICRS_ENOMEM:
+      return "workspace too small";
+    case ICRS_EHIP:
+      return "HIP runtime error";
+    case ICRS_EUNSUPPORTED:
+      return "unsupported";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

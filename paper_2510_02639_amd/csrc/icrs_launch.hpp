@@ -1,0 +1,53 @@
+// icrs_launch.hpp -- host-side launchers shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace icrs {
+
+// Device views of one call's inputs and workspace.
+struct Batch {
+  const double* params;        // [n_events][11] (device copy)
+  const int64_t* offsets;      // [n_events + 1] (device copy)
+  const int32_t* epoch_event;  // [n_epochs]
+  const double* t;             // [n_epochs]
+  int64_t n_events;
+  int64_t n_epochs;
+};
+
+struct SectorBuf {
+  double* sectors;   // [n_epochs][10][4]
+  uint8_t* periodic; // [n_epochs][10]
+  int32_t* nsec;     // [n_epochs]
+};
+
+hipError_t launch_epoch_event(const Batch& b, int32_t* epoch_event, hipStream_t s);
+
+// point images of every epoch's source centre; writes status[e] (assigns)
+hipError_t launch_centre_images(int n_lens, int root_fp32, const Batch& b, double* images, int32_t* n_images,
+                                double* a_ps, uint32_t* status, hipStream_t s);
+
+// limb images + sectors (one workgroup per epoch); ORs status bits
+hipError_t launch_limb_sectors(int n_lens, int root_fp32, int n_limb, const Batch& b, const SectorBuf& out,
+                               uint32_t* status, hipStream_t s);
+
+struct RayWork {
+  const int32_t* list;  // epochs to process, or nullptr = all epochs 0..n-1
+  int64_t n;            // number of epochs in the list
+};
+
+hipError_t launch_rays(int n_lens, int ray_fp32, const Batch& b, const SectorBuf& sec, const RayWork& w, int n_r,
+                       int n_theta, double delta_c, double* partial, uint8_t* clip, hipStream_t s);
+
+// sums sector fluxes into magnifications; epochs with edge touches and retries left get
+// widened sectors and are appended to next_list (count in *next_count)
+hipError_t launch_finalize(const Batch& b, const SectorBuf& sec, const RayWork& w, const double* partial,
+                           const uint8_t* clip, int attempt, int max_retries, int32_t* next_list,
+                           int32_t* next_count, double* mag, uint32_t* status, uint32_t extra_status,
+                           hipStream_t s);
+
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
+
+}  // namespace icrs

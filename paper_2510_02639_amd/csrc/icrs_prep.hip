@@ -1,0 +1,338 @@
+// icrs_prep.hip -- image finding and sector construction (Secs. 2.1, 3.1, 3.2).
+//
+// limb_sectors_kernel: one workgroup per epoch, one lane per source-limb point.  Each lane
+// builds the lens polynomial of its limb point, finds its roots by Ehrlich-Aberth (FP64, or
+// FP32 followed by an FP64 polish on the lens equation), validates them, and stages the
+// image-limb points (r, theta) in LDS.  The workgroup then bins them in r and theta with
+// LDS histograms, forms the candidate (r-run x theta-run) boxes with LDS atomic min/max,
+// and lane 0 applies margins, merges, caps and sorts the few resulting sectors.
+//
+// centre_images_kernel: one lane per epoch, images of the source centre and the
+// point-source magnification of eq. amp_point.
+#include "icrs_device.hpp"
+#include "icrs_launch.hpp"
+
+namespace icrs {
+
+namespace {
+
+constexpr int kEAMaxIterFP64 = 500;
+constexpr int kEAMaxIterFP32 = 200;
+
+__global__ void epoch_event_kernel(const int64_t* __restrict__ off, int64_t n_events, int64_t n_epochs,
+                                   int32_t* __restrict__ ev) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_epochs) return;
+  // largest i with off[i] <= e (offsets validated on the host: sorted, off[0] = 0)
+  int64_t lo = 0, hi = n_events - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= e)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  ev[e] = (int32_t)lo;
+}
+
+template <int N, typename T>
+__global__ __launch_bounds__(256) void centre_images_kernel(Batch b, double* __restrict__ images,
+                                                            int32_t* __restrict__ n_images, double* __restrict__ a_ps,
+                                                            uint32_t* __restrict__ status) {
+  constexpr int MI = N * N + 1;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= b.n_epochs) return;
+  const double* p = b.params + (int64_t)b.epoch_event[e] * kParams;
+  const Lens<N> L = make_lens<N>(p);
+  const c64 wc = source_center(p, b.t[e]);
+  c64 img[MI];
+  int n = 0;
+  const uint32_t st =
+      find_images<N, T>(L, wc, img, n, sizeof(T) == 8 ? kEAMaxIterFP64 : kEAMaxIterFP32);
+  double A = 0.0;
+  for (int j = 0; j < n; ++j) A += 1.0 / fabs(1.0 - norm2(lens_kappa(L, img[j])));
+  if (a_ps) a_ps[e] = A;
+  if (n_images) n_images[e] = n;
+  if (images)
+    for (int j = 0; j < 10; ++j) {
+      images[(e * 10 + j) * 2 + 0] = (j < n) ? img[j].x : 0.0;
+      images[(e * 10 + j) * 2 + 1] = (j < n) ? img[j].y : 0.0;
+    }
+  if (status) status[e] = st;
+}
+
+template <int N, typename T>
+__global__ __launch_bounds__(256) void limb_sectors_kernel(Batch b, int n_limb, SectorBuf out,
+                                                           uint32_t* __restrict__ status) {
+  constexpr int MI = N * N + 1;  // images per source point at most
+  constexpr int cap = 5 * (N - 1);
+  extern __shared__ double pts[];  // [blockDim.x * MI] r, then [blockDim.x * MI] theta
+  double* pr = pts;
+  double* pth = pts + blockDim.x * MI;
+  __shared__ unsigned long long rmin_k, rmax_k;
+  __shared__ int occ_t[kBinsTheta], occ_r[kBinsR];
+  __shared__ int trun_of[kBinsTheta], rrun_of[kBinsR], trun_first[kMaxRunsTheta];
+  __shared__ int n_tr, n_rr, full_ring;
+  __shared__ unsigned long long ck[kMaxCand][4];
+  __shared__ int ccount[kMaxCand];
+  __shared__ Sector S[kMaxCand];
+  __shared__ uint32_t st_sh;
+
+  const int64_t e = blockIdx.x;
+  const int tid = threadIdx.x;
+  const double* p = b.params + (int64_t)b.epoch_event[e] * kParams;
+  const double rho = p[6];
+  if (tid == 0) {
+    rmin_k = ~0ull;
+    rmax_k = 0ull;
+    st_sh = 0u;
+  }
+  if (tid < kBinsTheta) occ_t[tid] = 0;
+  if (tid < kBinsR) occ_r[tid] = 0;
+  __syncthreads();
+
+  // 1. images of limb point k = tid: w = w_c + rho e^{2 pi i k / N_limb}
+  int n = 0;
+  if (tid < n_limb) {
+    const Lens<N> L = make_lens<N>(p);
+    const c64 wc = source_center(p, b.t[e]);
+    double sp, cp;
+    sincospi(2.0 * tid / n_limb, &sp, &cp);
+    const c64 w = mk(wc.x + rho * cp, wc.y + rho * sp);
+    c64 img[MI];
+    const uint32_t st = find_images<N, T>(L, w, img, n, sizeof(T) == 8 ? kEAMaxIterFP64 : kEAMaxIterFP32);
+    if (st) atomicOr(&st_sh, st);
+    for (int j = 0; j < n; ++j) {
+      const double r = hypot(img[j].x, img[j].y);
+      pr[tid * MI + j] = r;
+      pth[tid * MI + j] = atan2(img[j].y, img[j].x);
+      atomicMin(&rmin_k, dkey(r));
+      atomicMax(&rmax_k, dkey(r));
+    }
+  }
+  __syncthreads();
+
+  // 2. occupancy of 64 theta bins on (-pi, pi] and 32 r bins of width
+  //    max((r_max - r_min)/32, 2 rho) from r_min
+  const double rmin = dkey_inv(rmin_k), rmax = dkey_inv(rmax_k);
+  const double wr = fmax((rmax - rmin) / kBinsR, 2.0 * rho);
+  for (int j = 0; j < n; ++j) {
+    occ_t[theta_bin(pth[tid * MI + j])] = 1;
+    occ_r[r_bin(pr[tid * MI + j], rmin, wr)] = 1;
+  }
+  __syncthreads();
+
+  // 3. runs of occupied bins joined across single empty bins (theta circular)
+  if (tid == 0) {
+    for (int i = 0; i < kBinsTheta; ++i) trun_of[i] = -1;
+    for (int i = 0; i < kBinsR; ++i) rrun_of[i] = -1;
+    int nt = 0, full = 0;
+    int start = -1;
+    for (int bb = 0; bb < kBinsTheta; ++bb)
+      if (occ_t[bb] && !occ_t[(bb + kBinsTheta - 1) % kBinsTheta] && !occ_t[(bb + kBinsTheta - 2) % kBinsTheta]) {
+        start = bb;
+        break;
+      }
+    bool any_t = false;
+    for (int bb = 0; bb < kBinsTheta; ++bb) any_t = any_t || occ_t[bb];
+    if (any_t && start < 0) {  // no gap of two empty bins: a full ring
+      full = 1;
+      nt = 1;
+      trun_first[0] = 0;
+      for (int i = 0; i < kBinsTheta; ++i) trun_of[i] = 0;
+    } else if (any_t) {
+      int bb = start, visited = 0;
+      while (visited < kBinsTheta) {
+        if (!occ_t[bb]) {
+          bb = (bb + 1) % kBinsTheta;
+          ++visited;
+          continue;
+        }
+        const int s0 = bb;
+        int last = bb;
+        bb = (bb + 1) % kBinsTheta;
+        ++visited;
+        while (visited < kBinsTheta) {
+          if (occ_t[bb])
+            last = bb;
+          else if (!occ_t[(bb + 1) % kBinsTheta])
+            break;
+          bb = (bb + 1) % kBinsTheta;
+          ++visited;
+        }
+        const int len = (last - s0 + kBinsTheta) % kBinsTheta + 1;
+        if (nt < kMaxRunsTheta) {
+          trun_first[nt] = s0;
+          for (int q = 0; q < len; ++q) trun_of[(s0 + q) % kBinsTheta] = nt;
+          ++nt;
+        }
+      }
+    }
+    int nr = 0;
+    int bb = 0;
+    while (bb < kBinsR) {
+      if (!occ_r[bb]) {
+        ++bb;
+        continue;
+      }
+      const int s0 = bb;
+      int last = bb;
+      ++bb;
+      while (bb < kBinsR) {
+        if (occ_r[bb])
+          last = bb;
+        else if (bb + 1 >= kBinsR || !occ_r[bb + 1])
+          break;
+        ++bb;
+      }
+      if (nr < kMaxRunsR) {
+        for (int q = s0; q <= last; ++q) rrun_of[q] = nr;
+        ++nr;
+      }
+      bb = last + 1;
+    }
+    n_tr = nt;
+    n_rr = nr;
+    full_ring = full;
+  }
+  __syncthreads();
+  const int nc = n_tr * n_rr;
+  for (int c = tid; c < nc; c += blockDim.x) {
+    ck[c][0] = ~0ull;
+    ck[c][1] = 0ull;
+    ck[c][2] = ~0ull;
+    ck[c][3] = 0ull;
+    ccount[c] = 0;
+  }
+  __syncthreads();
+
+  // 4. candidate boxes: min/max of member r and theta (theta unwrapped inside its run)
+  for (int j = 0; j < n; ++j) {
+    const double r = pr[tid * MI + j], th = pth[tid * MI + j];
+    const int tb = theta_bin(th), rb = r_bin(r, rmin, wr);
+    const int tr = trun_of[tb], rr = rrun_of[rb];
+    if (tr < 0 || rr < 0) continue;
+    const int c = rr * n_tr + tr;
+    const double thu = (tb >= trun_first[tr]) ? th : th + 2.0 * kPi;
+    atomicMin(&ck[c][0], dkey(r));
+    atomicMax(&ck[c][1], dkey(r));
+    atomicMin(&ck[c][2], dkey(thu));
+    atomicMax(&ck[c][3], dkey(thu));
+    atomicAdd(&ccount[c], 1);
+  }
+  __syncthreads();
+
+  // 5. margins, merge to a fixpoint, cap at 5(N-1), sort (lane 0; a handful of boxes)
+  if (tid == 0) {
+    uint32_t st = st_sh;
+    int ns = 0;
+    for (int rr = 0; rr < n_rr; ++rr)
+      for (int tr = 0; tr < n_tr; ++tr) {
+        const int c = rr * n_tr + tr;
+        if (ccount[c] == 0) continue;
+        S[ns++] = candidate_to_sector(dkey_inv(ck[c][0]), dkey_inv(ck[c][1]), dkey_inv(ck[c][2]),
+                                      dkey_inv(ck[c][3]), full_ring, rho);
+      }
+    merge_to_fixpoint(S, ns);
+    while (ns > cap) {
+      st |= kStCapOverflow;
+      int bi = 0, bj = 1;
+      double best = 1e300;
+      for (int i = 0; i < ns; ++i)
+        for (int j = i + 1; j < ns; ++j) {
+          const double a = sector_area(sector_union(S[i], S[j]));
+          if (a < best) {
+            best = a;
+            bi = i;
+            bj = j;
+          }
+        }
+      S[bi] = sector_union(S[bi], S[bj]);
+      for (int m = bj; m + 1 < ns; ++m) S[m] = S[m + 1];
+      --ns;
+      merge_to_fixpoint(S, ns);
+    }
+    sort_sectors(S, ns);
+    for (int s = 0; s < ns; ++s) {
+      double* o = out.sectors + (e * kMaxSectors + s) * 4;
+      o[0] = S[s].r_lo;
+      o[1] = S[s].r_hi;
+      o[2] = S[s].th_lo;
+      o[3] = S[s].th_hi;
+      out.periodic[e * kMaxSectors + s] = (uint8_t)S[s].periodic;
+    }
+    out.nsec[e] = ns;
+    status[e] |= st;
+  }
+}
+
+__global__ void fill_i32_kernel(int32_t* p, int64_t n, int32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+hipError_t launch_epoch_event(const Batch& b, int32_t* epoch_event, hipStream_t s) {
+  if (b.n_epochs == 0) return hipSuccess;
+  hipLaunchKernelGGL(epoch_event_kernel, dim3(blocks_for(b.n_epochs, 256)), dim3(256), 0, s, b.offsets, b.n_events,
+                     b.n_epochs, epoch_event);
+  return hipGetLastError();
+}
+
+hipError_t launch_centre_images(int n_lens, int root_fp32, const Batch& b, double* images, int32_t* n_images,
+                                double* a_ps, uint32_t* status, hipStream_t s) {
+  if (b.n_epochs == 0) return hipSuccess;
+  const dim3 g(blocks_for(b.n_epochs, 64)), blk(64);
+  if (n_lens == 2) {
+    if (root_fp32)
+      hipLaunchKernelGGL((centre_images_kernel<2, float>), g, blk, 0, s, b, images, n_images, a_ps, status);
+    else
+      hipLaunchKernelGGL((centre_images_kernel<2, double>), g, blk, 0, s, b, images, n_images, a_ps, status);
+  } else {
+    if (root_fp32)
+      hipLaunchKernelGGL((centre_images_kernel<3, float>), g, blk, 0, s, b, images, n_images, a_ps, status);
+    else
+      hipLaunchKernelGGL((centre_images_kernel<3, double>), g, blk, 0, s, b, images, n_images, a_ps, status);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_limb_sectors(int n_lens, int root_fp32, int n_limb, const Batch& b, const SectorBuf& out,
+                               uint32_t* status, hipStream_t s) {
+  if (b.n_epochs == 0) return hipSuccess;
+  const int bs = ((n_limb + 63) / 64) * 64;
+  const dim3 g((unsigned)b.n_epochs), blk(bs);
+  const size_t lds = (size_t)bs * (n_lens * n_lens + 1) * 2 * sizeof(double);
+  if (n_lens == 2) {
+    if (root_fp32)
+      hipLaunchKernelGGL((limb_sectors_kernel<2, float>), g, blk, lds, s, b, n_limb, out, status);
+    else
+      hipLaunchKernelGGL((limb_sectors_kernel<2, double>), g, blk, lds, s, b, n_limb, out, status);
+  } else {
+    if (root_fp32)
+      hipLaunchKernelGGL((limb_sectors_kernel<3, float>), g, blk, lds, s, b, n_limb, out, status);
+    else
+      hipLaunchKernelGGL((limb_sectors_kernel<3, double>), g, blk, lds, s, b, n_limb, out, status);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+}  // namespace icrs

@@ -1,0 +1,191 @@
+"""Python binding of the ICRS C ABI (``include/icrs.h``): argument marshalling only.
+
+Every step of the computation runs in the HIP library ``libicrs.so``; this module only
+packs host arrays, takes device pointers from torch tensors and calls the C entry points
+of the same names.  It raises if the library is missing -- there is no fallback.
+
+Event parameters: float64 [n_events, 11] = [s, q, u0, alpha, t0, tE, rho, u_ld, q3, r3, psi]
+(host); epoch offsets int64 [n_events + 1] (host); epochs t float64 [n_epochs] (device).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libicrs.so")
+
+ICRS_ABI_VERSION = 1
+ICRS_N_PARAMS = 11
+ICRS_MAX_SECTORS = 10
+ICRS_FP64, ICRS_FP32 = 0, 1
+ST_ROOT_NONCONV, ST_IMG_COUNT, ST_CAP_OVERFLOW, ST_CLIP, ST_NAN, ST_GIVEN = 1, 2, 4, 8, 16, 64
+_STATUS = {0: "ok", -1: "invalid argument", -2: "workspace too small", -3: "HIP runtime error", -4: "unsupported"}
+
+
+class IcrsError(RuntimeError):
+    def __init__(self, code, where):
+        super().__init__(f"{where}: {_STATUS.get(code, code)} ({code})")
+        self.code = code
+
+
+class icrs_config(ctypes.Structure):
+    _fields_ = [("abi_version", ctypes.c_uint32), ("n_lens", ctypes.c_int32), ("n_limb", ctypes.c_int32),
+                ("n_r", ctypes.c_int32), ("n_theta", ctypes.c_int32), ("ray_precision", ctypes.c_int32),
+                ("root_precision", ctypes.c_int32), ("max_retries", ctypes.c_int32), ("delta_c", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libicrs.so (built in-tree by ``__graft_entry__.build()``); raise if it is absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing (run __graft_entry__.build())")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_size_t
+    L.icrs_default_config.argtypes = [ctypes.POINTER(icrs_config)]
+    L.icrs_create.argtypes = [ctypes.POINTER(icrs_config), vp, ctypes.POINTER(vp)]
+    L.icrs_create.restype = ctypes.c_int
+    L.icrs_destroy.argtypes = [vp]
+    L.icrs_workspace_bytes.argtypes = [vp, i64, i64]
+    L.icrs_workspace_bytes.restype = sz
+    L.icrs_magnification.argtypes = [vp, i64, vp, vp, i64, vp, vp, vp, vp, sz]
+    L.icrs_magnification.restype = ctypes.c_int
+    L.icrs_magnification_given.argtypes = [vp, i64, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, sz]
+    L.icrs_magnification_given.restype = ctypes.c_int
+    L.icrs_get_sectors.argtypes = [vp, vp, i64, vp, vp, vp]
+    L.icrs_get_sectors.restype = ctypes.c_int
+    L.icrs_point_images.argtypes = [vp, i64, vp, vp, i64, vp, vp, vp, vp, vp, sz]
+    L.icrs_point_images.restype = ctypes.c_int
+    L.icrs_status_string.argtypes = [ctypes.c_int]
+    L.icrs_status_string.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+EXPORTED = ["icrs_default_config", "icrs_create", "icrs_destroy", "icrs_workspace_bytes", "icrs_magnification",
+            "icrs_magnification_given", "icrs_get_sectors", "icrs_point_images", "icrs_status_string"]
+
+
+def _check(code, where):
+    if code != 0:
+        raise IcrsError(code, where)
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, torch.Tensor):
+        return ctypes.c_void_p(x.data_ptr())
+    return x.ctypes.data_as(ctypes.c_void_p)
+
+
+def _host_events(params, offsets):
+    p = np.ascontiguousarray(np.asarray(params, dtype=np.float64).reshape(-1, ICRS_N_PARAMS))
+    o = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64).reshape(-1))
+    return p, o
+
+
+def _dev(t, dtype):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"expected a contiguous CUDA tensor of {dtype}")
+    return t
+
+
+class Handle:
+    """One icrs_handle bound to the current torch stream of the current device."""
+
+    def __init__(self, n_lens=2, n_limb=64, n_r=64, n_theta=256, ray_precision="fp64", root_precision="fp64",
+                 max_retries=2, delta_c=0.1, stream=None):
+        L = lib()
+        cfg = icrs_config()
+        L.icrs_default_config(ctypes.byref(cfg))
+        cfg.n_lens, cfg.n_limb, cfg.n_r, cfg.n_theta = n_lens, n_limb, n_r, n_theta
+        cfg.ray_precision = ICRS_FP32 if ray_precision == "fp32" else ICRS_FP64
+        cfg.root_precision = ICRS_FP32 if root_precision == "fp32" else ICRS_FP64
+        cfg.max_retries, cfg.delta_c = max_retries, delta_c
+        self.cfg = cfg
+        s = stream if stream is not None else torch.cuda.current_stream()
+        self.stream = s
+        h = ctypes.c_void_p()
+        _check(L.icrs_create(ctypes.byref(cfg), ctypes.c_void_p(s.cuda_stream), ctypes.byref(h)), "icrs_create")
+        self._h = h
+        self._ws = None
+
+    def close(self):
+        if self._h:
+            lib().icrs_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_bytes(self, n_events, n_epochs):
+        return int(lib().icrs_workspace_bytes(self._h, int(n_events), int(n_epochs)))
+
+    def workspace(self, n_events, n_epochs):
+        nb = self.workspace_bytes(n_events, n_epochs)
+        if self._ws is None or self._ws.numel() < nb:
+            self._ws = torch.empty(max(nb, 256), dtype=torch.uint8, device="cuda")
+            assert self._ws.data_ptr() % 256 == 0
+        return self._ws
+
+    def magnification(self, params, offsets, t, mag=None, status=None, workspace=None):
+        p, o = _host_events(params, offsets)
+        t = _dev(t, torch.float64)
+        n = t.numel()
+        mag = torch.empty(n, dtype=torch.float64, device=t.device) if mag is None else mag
+        status = torch.empty(n, dtype=torch.int32, device=t.device) if status is None else status
+        ws = workspace if workspace is not None else self.workspace(p.shape[0], n)
+        code = lib().icrs_magnification(self._h, p.shape[0], _ptr(p), _ptr(o), n, _ptr(t), _ptr(mag), _ptr(status),
+                                        _ptr(ws), ws.numel())
+        _check(code, "icrs_magnification")
+        return mag, status
+
+    def magnification_given(self, params, offsets, t, sectors, periodic, nsec, workspace=None):
+        p, o = _host_events(params, offsets)
+        t = _dev(t, torch.float64)
+        n = t.numel()
+        sectors = _dev(sectors, torch.float64)
+        periodic = _dev(periodic, torch.uint8)
+        nsec = _dev(nsec, torch.int32)
+        assert sectors.numel() == n * ICRS_MAX_SECTORS * 4 and periodic.numel() == n * ICRS_MAX_SECTORS
+        mag = torch.empty(n, dtype=torch.float64, device=t.device)
+        status = torch.empty(n, dtype=torch.int32, device=t.device)
+        ws = workspace if workspace is not None else self.workspace(p.shape[0], n)
+        code = lib().icrs_magnification_given(self._h, p.shape[0], _ptr(p), _ptr(o), n, _ptr(t), _ptr(sectors),
+                                              _ptr(periodic), _ptr(nsec), _ptr(mag), _ptr(status), _ptr(ws),
+                                              ws.numel())
+        _check(code, "icrs_magnification_given")
+        return mag, status
+
+    def get_sectors(self, n_epochs, workspace=None):
+        ws = workspace if workspace is not None else self._ws
+        sec = torch.empty((n_epochs, ICRS_MAX_SECTORS, 4), dtype=torch.float64, device="cuda")
+        per = torch.empty((n_epochs, ICRS_MAX_SECTORS), dtype=torch.uint8, device="cuda")
+        ns = torch.empty(n_epochs, dtype=torch.int32, device="cuda")
+        _check(lib().icrs_get_sectors(self._h, _ptr(ws), n_epochs, _ptr(sec), _ptr(per), _ptr(ns)), "icrs_get_sectors")
+        return sec, per, ns
+
+    def point_images(self, params, offsets, t, workspace=None):
+        p, o = _host_events(params, offsets)
+        t = _dev(t, torch.float64)
+        n = t.numel()
+        img = torch.empty((n, 10, 2), dtype=torch.float64, device=t.device)
+        nimg = torch.empty(n, dtype=torch.int32, device=t.device)
+        aps = torch.empty(n, dtype=torch.float64, device=t.device)
+        ws = workspace if workspace is not None else self.workspace(p.shape[0], n)
+        code = lib().icrs_point_images(self._h, p.shape[0], _ptr(p), _ptr(o), n, _ptr(t), _ptr(img), _ptr(nimg),
+                                       _ptr(aps), _ptr(ws), ws.numel())
+        _check(code, "icrs_point_images")
+        return img, nimg, aps

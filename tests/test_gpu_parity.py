@@ -1,0 +1,212 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle on the same inputs.
+
+Tolerances: 1e-6 relative on magnifications from the FP64 ray loop; sector bounds within
+1e-12 (they are min/max of the same FP64 image points, up to last-bit differences of the
+device hypot/atan2); centre images 1e-9.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2510_02639_amd import icrs, workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-6
+
+
+def _run(w, ray="fp64", root="fp64", n_r=None, n_theta=None, n_limb=None, retries=2):
+    h = icrs.Handle(n_lens=w.n_lens, n_limb=n_limb or w.n_limb, n_r=n_r or w.n_r, n_theta=n_theta or w.n_theta,
+                    ray_precision=ray, root_precision=root, max_retries=retries)
+    t = torch.tensor(w.t, device="cuda")
+    mag, st = h.magnification(w.params, w.offsets, t)
+    sec, per, ns = h.get_sectors(w.n_epochs)
+    torch.cuda.synchronize()
+    return (mag.cpu().numpy(), st.cpu().numpy().astype(np.uint32), sec.cpu().numpy(), per.cpu().numpy(),
+            ns.cpu().numpy(), h)
+
+
+def _oracle(w, n_r=None, n_theta=None, n_limb=None, retries=2):
+    out = dict(mag=[], status=[], sectors=[], periodic=[], nsec=[], a_ps=[])
+    for i in range(w.n_events):
+        t = w.t[w.offsets[i]:w.offsets[i + 1]]
+        if t.size == 0:
+            continue
+        r = O.magnification(w.n_lens, w.params[i], t, n_limb=n_limb or w.n_limb, n_r=n_r or w.n_r,
+                            n_theta=n_theta or w.n_theta, max_retries=retries)
+        for k in out:
+            out[k].append(r[k])
+    return {k: np.concatenate(v) for k, v in out.items()}
+
+
+def _report(name, rel):
+    print(f"{name}: n={rel.size} max rel {np.max(rel):.3e} median {np.median(rel):.3e}", flush=True)
+
+
+def test_config1_end_to_end_fp64():
+    w = W.config1()
+    mag, st, sec, per, ns, _ = _run(w)
+    ref = _oracle(w)
+    assert np.array_equal(ns, ref["nsec"]), np.nonzero(ns != ref["nsec"])
+    rel = np.abs(mag / ref["mag"] - 1)
+    _report("config1 fp64", rel)
+    assert np.all(rel <= FP64_TOL)
+    assert np.array_equal(st, ref["status"])
+
+
+def test_config1_sectors_match_oracle():
+    w = W.config1()
+    _, _, sec, per, ns, _ = _run(w)
+    ref = _oracle(w)
+    for e in range(w.n_epochs):
+        k = ns[e]
+        assert np.array_equal(per[e, :k], ref["periodic"][e, :k])
+        assert np.allclose(sec[e, :k], ref["sectors"][e, :k], rtol=1e-12, atol=1e-12), e
+
+
+def test_given_grid_fp64_matches_oracle_quadrature():
+    """Given-grid mode isolates the ray kernel: the oracle's own sectors in, same rule out."""
+    w = W.config1()
+    ref = _oracle(w)
+    h = icrs.Handle(n_lens=2, n_limb=64, n_r=64, n_theta=256)
+    t = torch.tensor(w.t, device="cuda")
+    mag, st = h.magnification_given(w.params, w.offsets, t, torch.tensor(ref["sectors"], device="cuda"),
+                                    torch.tensor(ref["periodic"], device="cuda"),
+                                    torch.tensor(ref["nsec"], device="cuda"))
+    torch.cuda.synchronize()
+    omag, ost = O.magnification_given(2, w.params[0], w.t, ref["sectors"], ref["periodic"], ref["nsec"], 64, 256)
+    rel = np.abs(mag.cpu().numpy() / omag - 1)
+    _report("given fp64", rel)
+    assert np.all(rel <= FP64_TOL)
+    assert np.array_equal(st.cpu().numpy().astype(np.uint32), ost)
+
+
+def test_point_images_and_point_magnification():
+    w = W.config1()
+    h = icrs.Handle(n_lens=2)
+    img, nimg, aps = h.point_images(w.params, w.offsets, torch.tensor(w.t, device="cuda"))
+    torch.cuda.synchronize()
+    img, nimg, aps = img.cpu().numpy(), nimg.cpu().numpy(), aps.cpu().numpy()
+    eps, a = O.frame(2, w.params[0])
+    for e in range(w.n_epochs):
+        wc = O.source_center(w.params[0], w.t[e])
+        A, mu = O.point_mag(eps, a, wc)
+        ref_img, _ = O.images(eps, a, wc)
+        assert nimg[e] == ref_img.size
+        assert abs(aps[e] / A - 1) < 1e-9
+        got = img[e, :nimg[e], 0] + 1j * img[e, :nimg[e], 1]
+        for z in ref_img:
+            assert np.min(np.abs(got - z)) < 1e-9
+
+
+def test_ragged_binary_batch_fp64():
+    """Uneven events (one empty), planetary mass ratios, FP64 roots and rays at 64 x 256."""
+    big = W.binary_batch(2, 8)
+    sub = big.subset([0, 1, 2, 3, 4, 5])
+    ts, off = [], [0]
+    for i in range(sub.n_events):
+        seg = sub.t[sub.offsets[i]:sub.offsets[i + 1]]
+        take = [0, 7, 3, 11, 1, 5][i]
+        seg = seg[:: max(1, seg.size // max(take, 1))][:take]
+        ts.append(seg)
+        off.append(off[-1] + seg.size)
+    w = W.Workload("ragged", 2, sub.params, np.array(off, np.int64), np.concatenate(ts), 64, 64, 256, "fp64", "fp64")
+    mag, st, sec, per, ns, _ = _run(w)
+    ref = _oracle(w)
+    rel = np.abs(mag / ref["mag"] - 1)
+    _report("ragged fp64", rel)
+    same = ns == ref["nsec"]
+    assert same.mean() >= 0.95
+    assert np.all(rel[same] <= FP64_TOL)
+
+
+def test_triple_fp64_small():
+    big = W.config3(n_events=3, n_epochs=2000)
+    ts, off = [], [0]
+    for i in range(3):
+        seg = big.t[big.offsets[i]:big.offsets[i + 1]][980:1020:4]
+        ts.append(seg)
+        off.append(off[-1] + seg.size)
+    w = W.Workload("triple-small", 3, big.params, np.array(off, np.int64), np.concatenate(ts), 64, 64, 256,
+                   "fp64", "fp64")
+    mag, st, sec, per, ns, _ = _run(w)
+    ref = _oracle(w)
+    rel = np.abs(mag / ref["mag"] - 1)
+    _report("triple fp64", rel)
+    same = ns == ref["nsec"]
+    assert same.mean() >= 0.9
+    assert np.all(rel[same] <= FP64_TOL)
+
+
+def test_run_to_run_bitwise_determinism():
+    w = W.config1()
+    a = _run(w)[0]
+    b = _run(w)[0]
+    assert np.array_equal(a, b)
+
+
+def test_invalid_arguments_are_rejected_before_launch():
+    w = W.config1()
+    h = icrs.Handle(n_lens=2)
+    t = torch.tensor(w.t, device="cuda")
+    bad = w.params.copy()
+    bad[0, 1] = -0.1                        # q <= 0
+    with pytest.raises(icrs.IcrsError) as ei:
+        h.magnification(bad, w.offsets, t)
+    assert ei.value.code == -1
+    with pytest.raises(icrs.IcrsError):
+        h.magnification(w.params, np.array([0, 199]), t)   # offsets do not cover n_epochs
+    small = torch.empty(256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(icrs.IcrsError) as ei:
+        h.magnification(w.params, w.offsets, t, workspace=small)
+    assert ei.value.code == -2
+
+
+FP32_TOL = 3e-5
+
+
+def _planetary_subset(n_events=6, per_event=6, rho=None, seed=2):
+    big = W.binary_batch(seed, 24, rho_fixed=rho)
+    ts, off = [], [0]
+    for i in range(n_events):
+        seg = big.t[big.offsets[i]:big.offsets[i + 1]]
+        seg = seg[np.linspace(0, seg.size - 1, per_event).astype(int)]
+        ts.append(seg)
+        off.append(off[-1] + seg.size)
+    return W.Workload("planetary-subset", 2, big.params[:n_events], np.array(off, np.int64), np.concatenate(ts),
+                      128, 128, 512, "fp32", "fp32")
+
+
+def test_fp32_rays_given_grid_planetary():
+    """FP32 ray loop (anchor-relative) on the oracle's own sectors: 3e-5 of the FP64 oracle."""
+    w = _planetary_subset(rho=1e-3)
+    ref = _oracle(w)
+    h = icrs.Handle(n_lens=2, n_limb=128, n_r=128, n_theta=512, ray_precision="fp32", root_precision="fp32")
+    t = torch.tensor(w.t, device="cuda")
+    mag, st = h.magnification_given(w.params, w.offsets, t, torch.tensor(ref["sectors"], device="cuda"),
+                                    torch.tensor(ref["periodic"], device="cuda"),
+                                    torch.tensor(ref["nsec"], device="cuda"))
+    torch.cuda.synchronize()
+    om = []
+    for i in range(w.n_events):
+        sl = slice(w.offsets[i], w.offsets[i + 1])
+        om.append(O.magnification_given(2, w.params[i], w.t[sl], ref["sectors"][sl], ref["periodic"][sl],
+                                        ref["nsec"][sl], 128, 512)[0])
+    om = np.concatenate(om)
+    rel = np.abs(mag.cpu().numpy() / om - 1)
+    _report("given fp32 planetary", rel)
+    assert np.all(rel <= FP32_TOL)
+
+
+def test_fp32_end_to_end_planetary():
+    """Config-2 shape: FP32 EA + FP64 polish, FP32 rays, 128 limb points, 128 x 512."""
+    w = _planetary_subset()
+    mag, st, sec, per, ns, _ = _run(w, ray="fp32", root="fp32")
+    ref = _oracle(w)
+    rel = np.abs(mag / ref["mag"] - 1)
+    _report("e2e fp32 planetary", rel)
+    same = ns == ref["nsec"]
+    print(f"sector-count agreement {same.mean():.3f}", flush=True)
+    assert same.mean() >= 0.95
+    assert np.all(rel[same] <= FP32_TOL)
