@@ -75,7 +75,7 @@ typedef struct icrs_config {
   int32_t n_lens;        /* 2 (binary, degree-5 polynomial) or 3 (triple, degree 10) */
   int32_t n_limb;        /* limb points per epoch for image finding, 8..256 (Sec. 3.2) */
   int32_t n_r;           /* radial grid nodes per sector, 4..4096 (Sec. 3.3) */
-  int32_t n_theta;       /* angular grid nodes per sector, multiple of 64, 64..4096 (Sec. 3.3) */
+  int32_t n_theta;       /* angular grid nodes per sector, 64..1024 (Sec. 3.3) */
   int32_t ray_precision; /* ICRS_FP64 or ICRS_FP32 (FP32 rays relative to an FP64 anchor) */
   int32_t root_precision;/* ICRS_FP64: FP64 Ehrlich-Aberth; ICRS_FP32: FP32 EA then FP64 polish */
   int32_t max_retries;   /* sector-widening retries after an edge touch, 0..4 */
@@ -134,6 +134,26 @@ icrs_status icrs_point_images(icrs_handle* h, int64_t n_events, const double* pa
                               const int64_t* epoch_offsets, int64_t n_epochs, const double* t,
                               double* images, int32_t* n_images, double* a_ps, void* workspace,
                               size_t workspace_bytes);
+
+/* Opt-in timing of the library's kernels (the benchmark's live measurement).  With
+ * profiling on, every call records HIP events around each kernel class on the handle's
+ * stream and waits for them at the end of the call; totals accumulate in the handle.
+ * n_sector_passes counts (epoch, sector) grids shot (each is n_r x n_theta rays), summed
+ * over the clip retries. */
+typedef struct icrs_profile {
+  double ms_centre;        /* centre images (point-source magnification)   */
+  double ms_limb_sectors;  /* limb images + sector construction            */
+  double ms_rays;          /* ray shooting + row quadrature                */
+  double ms_finalize;      /* sums, clip retries                           */
+  int64_t n_calls;
+  int64_t n_rays_launches;
+  int64_t n_sector_passes;
+  int64_t n_epochs;
+} icrs_profile;
+
+icrs_status icrs_set_profiling(icrs_handle* h, int on);
+/* Copy the accumulated totals into *out; reset them when reset != 0. */
+icrs_status icrs_get_profile(icrs_handle* h, icrs_profile* out, int reset);
 
 const char* icrs_status_string(icrs_status s);
 

@@ -26,6 +26,8 @@
 #include <cstring>
 #include <vector>
 
+#include <omp.h>
+
 using cplx = std::complex<double>;
 
 namespace {
@@ -798,6 +800,17 @@ double epoch_magnification(const Lens& L, const double* p, double t, const Confi
 extern "C" {
 
 int orc_abi_version() { return 1; }
+
+// Threads an OpenMP parallel region of the oracle will use.
+int orc_num_threads() {
+  int n = 1;
+#pragma omp parallel
+  {
+#pragma omp single
+    n = omp_get_num_threads();
+  }
+  return n;
+}
 
 void orc_frame(int n_lens, const double* params, double* eps, double* a) {
   const Lens L = make_lens(n_lens, params);

@@ -44,6 +44,7 @@ def lib():
         d, i, u8, u32, i32, i64 = (ctypes.c_double, ctypes.c_int, ctypes.c_uint8, ctypes.c_uint32,
                                     ctypes.c_int32, ctypes.c_int64)
         P = ctypes.POINTER
+        L.orc_num_threads.restype = i
         L.orc_frame.argtypes = [i, P(d), P(d), P(d)]
         L.orc_source_center.argtypes = [P(d), d, P(d)]
         L.orc_lens_map.argtypes = [i, P(d), P(d), P(d), P(d)]
@@ -71,6 +72,10 @@ def lib():
                                               P(u32)]
         _lib = L
     return _lib
+
+
+def num_threads():
+    return int(lib().orc_num_threads())
 
 
 def _p(a, ct=ctypes.c_double):

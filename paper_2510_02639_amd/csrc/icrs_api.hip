@@ -11,6 +11,9 @@
 struct icrs_handle {
   icrs_config cfg;
   hipStream_t stream;
+  int profiling;
+  hipEvent_t ev[16];
+  icrs_profile prof;
 };
 
 namespace {
@@ -23,7 +26,7 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
-  size_t params, offsets, epoch_event, sectors, periodic, nsec, partial, clip, list_a, list_b, counters, total;
+  size_t params, offsets, epoch_event, sectors, periodic, nsec, partial, clip, list_a, list_b, fallback, counters, total;
 };
 
 Layout layout_for(int64_t n_events, int64_t n_epochs) {
@@ -44,6 +47,7 @@ Layout layout_for(int64_t n_events, int64_t n_epochs) {
   L.epoch_event = take(E * sizeof(int32_t));
   L.list_a = take(E * sizeof(int32_t));
   L.list_b = take(E * sizeof(int32_t));
+  L.fallback = take(E * ICRS_MAX_SECTORS * sizeof(int32_t));
   L.counters = take(64);
   L.params = take(V * ICRS_N_PARAMS * sizeof(double));
   L.offsets = take((V + 1) * sizeof(int64_t));
@@ -93,6 +97,35 @@ bool events_ok(const icrs_config& c, int64_t n_events, const double* params, con
 
 icrs_status hip_status(hipError_t e) { return e == hipSuccess ? ICRS_OK : ICRS_EHIP; }
 
+// Event pair around one launch when profiling is on; elapsed time is added to *acc after
+// the stream has been waited for (Timer::flush).
+struct Timer {
+  icrs_handle* h;
+  int n = 0;
+  double* acc[8];
+  explicit Timer(icrs_handle* hh) : h(hh) {}
+  hipError_t begin() {
+    if (!h->profiling || n >= 8) return hipSuccess;
+    return hipEventRecord(h->ev[2 * n], h->stream);
+  }
+  hipError_t end(double* into) {
+    if (!h->profiling || n >= 8) return hipSuccess;
+    acc[n] = into;
+    return hipEventRecord(h->ev[2 * n++ + 1], h->stream);
+  }
+  hipError_t flush() {
+    if (!h->profiling) return hipSuccess;
+    hipError_t e = hipStreamSynchronize(h->stream);
+    for (int i = 0; i < n && e == hipSuccess; ++i) {
+      float ms = 0.f;
+      e = hipEventElapsedTime(&ms, h->ev[2 * i], h->ev[2 * i + 1]);
+      *acc[i] += ms;
+    }
+    n = 0;
+    return e;
+  }
+};
+
 #define ICRS_TRY(expr)                       \
   do {                                       \
     const hipError_t err_ = (expr);          \
@@ -106,7 +139,9 @@ struct Views {
   uint8_t* clip;
   int32_t* list_a;
   int32_t* list_b;
-  int32_t* counters;
+  int32_t* fallback;
+  int32_t* counters;   // [0] retry count, [4] FP64 fallback count, [8..9] int64 sector passes,
+                       // [12..13] int64 work queue
 };
 
 icrs_status prepare(icrs_handle* h, int64_t n_events, const double* params, const int64_t* off, int64_t n_epochs,
@@ -128,6 +163,7 @@ icrs_status prepare(icrs_handle* h, int64_t n_events, const double* params, cons
   v->clip = (uint8_t*)(base + L.clip);
   v->list_a = (int32_t*)(base + L.list_a);
   v->list_b = (int32_t*)(base + L.list_b);
+  v->fallback = (int32_t*)(base + L.fallback);
   v->counters = (int32_t*)(base + L.counters);
   if (n_events == 0) return ICRS_OK;
   ICRS_TRY(hipMemcpyAsync(base + L.params, params, (size_t)n_events * ICRS_N_PARAMS * sizeof(double),
@@ -142,24 +178,45 @@ icrs_status prepare(icrs_handle* h, int64_t n_events, const double* params, cons
 icrs_status run_rays(icrs_handle* h, const Views& v, int max_retries, double* mag, uint32_t* status,
                      uint32_t extra_status) {
   const icrs_config& c = h->cfg;
-  RayWork w{nullptr, v.b.n_epochs};
+  RayWork w;
+  w.n = v.b.n_epochs;
   int32_t* cur = v.list_a;
   int32_t* nxt = v.list_b;
+  unsigned long long* passes = (unsigned long long*)(v.counters + 8);
+  if (h->profiling) ICRS_TRY(icrs::launch_fill_i32(v.counters + 8, 2, 0, h->stream));
+  Timer tm(h);
   for (int attempt = 0;; ++attempt) {
+    ICRS_TRY(tm.begin());
     ICRS_TRY(icrs::launch_rays(c.n_lens, c.ray_precision, v.b, v.sec, w, c.n_r, c.n_theta, c.delta_c, v.partial,
-                               v.clip, h->stream));
+                               v.clip, (unsigned long long*)(v.counters + 12), v.fallback, v.counters + 4,
+                               h->stream));
+    ICRS_TRY(tm.end(&h->prof.ms_rays));
+    h->prof.n_rays_launches += 1;
     ICRS_TRY(icrs::launch_fill_i32(v.counters, 1, 0, h->stream));
+    ICRS_TRY(tm.begin());
     ICRS_TRY(icrs::launch_finalize(v.b, v.sec, w, v.partial, v.clip, attempt, max_retries, nxt, v.counters, mag,
-                                   status, extra_status, h->stream));
+                                   status, extra_status, h->profiling ? passes : nullptr, h->stream));
+    ICRS_TRY(tm.end(&h->prof.ms_finalize));
+    ICRS_TRY(tm.flush());
     if (attempt >= max_retries) break;
     int32_t count = 0;
     ICRS_TRY(hipMemcpyAsync(&count, v.counters, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
     ICRS_TRY(hipStreamSynchronize(h->stream));
     if (count == 0) break;
-    w = RayWork{nxt, count};
+    w = RayWork{};
+    w.list = nxt;
+    w.n = count;
     int32_t* tmp = cur;
     cur = nxt;
     nxt = tmp;
+  }
+  if (h->profiling) {
+    unsigned long long np = 0;
+    ICRS_TRY(hipMemcpyAsync(&np, passes, sizeof(np), hipMemcpyDeviceToHost, h->stream));
+    ICRS_TRY(hipStreamSynchronize(h->stream));
+    h->prof.n_sector_passes += (int64_t)np;
+    h->prof.n_epochs += v.b.n_epochs;
+    h->prof.n_calls += 1;
   }
   return ICRS_OK;
 }
@@ -188,11 +245,34 @@ icrs_status icrs_create(const icrs_config* cfg, void* hip_stream, icrs_handle** 
   if (!h) return ICRS_ENOMEM;
   h->cfg = *cfg;
   h->stream = (hipStream_t)hip_stream;
+  h->profiling = 0;
+  memset(&h->prof, 0, sizeof(h->prof));
+  for (auto& e : h->ev) e = nullptr;
   *out = h;
   return ICRS_OK;
 }
 
-void icrs_destroy(icrs_handle* h) { delete h; }
+void icrs_destroy(icrs_handle* h) {
+  if (!h) return;
+  for (auto& e : h->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete h;
+}
+
+icrs_status icrs_set_profiling(icrs_handle* h, int on) {
+  if (!h) return ICRS_EINVAL;
+  if (on && !h->ev[0])
+    for (auto& e : h->ev) ICRS_TRY(hipEventCreate(&e));
+  h->profiling = on ? 1 : 0;
+  return ICRS_OK;
+}
+
+icrs_status icrs_get_profile(icrs_handle* h, icrs_profile* out, int reset) {
+  if (!h || !out) return ICRS_EINVAL;
+  *out = h->prof;
+  if (reset) memset(&h->prof, 0, sizeof(h->prof));
+  return ICRS_OK;
+}
 
 size_t icrs_workspace_bytes(const icrs_handle* h, int64_t n_events, int64_t n_epochs) {
   (void)h;
@@ -210,8 +290,14 @@ icrs_status icrs_magnification(icrs_handle* h, int64_t n_events, const double* p
   if (ps != ICRS_OK || n_epochs == 0) return ps;
   const icrs_config& c = h->cfg;
   const int fp32_roots = c.root_precision == ICRS_FP32;
+  Timer tm(h);
+  ICRS_TRY(tm.begin());
   ICRS_TRY(icrs::launch_centre_images(c.n_lens, fp32_roots, v.b, nullptr, nullptr, nullptr, status, h->stream));
+  ICRS_TRY(tm.end(&h->prof.ms_centre));
+  ICRS_TRY(tm.begin());
   ICRS_TRY(icrs::launch_limb_sectors(c.n_lens, fp32_roots, c.n_limb, v.b, v.sec, status, h->stream));
+  ICRS_TRY(tm.end(&h->prof.ms_limb_sectors));
+  ICRS_TRY(tm.flush());
   return run_rays(h, v, c.max_retries, mag, status, 0u);
 }
 

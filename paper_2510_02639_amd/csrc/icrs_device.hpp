@@ -70,9 +70,18 @@ template <typename T>
 __device__ __forceinline__ T norm2(cx<T> a) {
   return a.x * a.x + a.y * a.y;
 }
+// Reciprocals from the hardware approximations (v_rcp_f64 is good to about 2^-24, v_rcp_f32
+// to 1 ulp) refined by one Newton step in FP64: relative error about 2^-48.
+__device__ __forceinline__ double rcp_fast(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  const double e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
+
 template <typename T>
 __device__ __forceinline__ cx<T> recip(cx<T> b) {
-  const T n = T(1) / norm2(b);
+  const T n = rcp_fast(norm2(b));
   return {b.x * n, -b.y * n};
 }
 template <typename T>
@@ -267,21 +276,24 @@ __device__ __forceinline__ void sincos_t(double a, double* s, double* c) { sinco
 __device__ __forceinline__ void sincos_t(float a, float* s, float* c) { sincosf(a, s, c); }
 
 template <typename T, int D>
-__device__ inline int ehrlich_aberth(const cx<T> (&b)[D + 1], cx<T> (&z)[D], int max_iter, bool* conv) {
+__device__ inline int ehrlich_aberth(const cx<T> (&b)[D + 1], cx<T> (&z)[D], int max_iter, bool* conv,
+                                     bool warm = false) {
   T absb[D + 1];
-  T R = T(0);
-  const T inv_lead = T(1) / sqrt(norm2(b[D]));
 #pragma unroll
   for (int j = 0; j <= D; ++j) absb[j] = sqrt(norm2(b[j]));
+  if (!warm) {
+    T R = T(0);
+    const T inv_lead = T(1) / absb[D];
 #pragma unroll
-  for (int j = 0; j < D; ++j) R = fmax(R, absb[j] * inv_lead);
-  R += T(1);
+    for (int j = 0; j < D; ++j) R = fmax(R, absb[j] * inv_lead);
+    R += T(1);
 #pragma unroll
-  for (int k = 0; k < D; ++k) {
-    T s, c;
-    const T ang = T(2) * T(kPi) * T(k) / T(D) + T(kPi) / T(2 * D);
-    sincos_t(ang, &s, &c);
-    z[k] = mk(R * c, R * s);
+    for (int k = 0; k < D; ++k) {
+      T s, c;
+      const T ang = T(2) * T(kPi) * T(k) / T(D) + T(kPi) / T(2 * D);
+      sincos_t(ang, &s, &c);
+      z[k] = mk(R * c, R * s);
+    }
   }
   uint32_t done = 0;
   constexpr uint32_t all = (1u << D) - 1u;
@@ -382,10 +394,20 @@ __device__ inline uint32_t find_images(const Lens<N>& L, c64 w, c64 (&img)[N * N
   cx<T> z[D];
   bool conv = true;
   ehrlich_aberth<T, D>(b, z, max_iter, &conv);
+  c64 zr[D];
+#pragma unroll
+  for (int k = 0; k < D; ++k) zr[k] = mk(double(z[k].x), double(z[k].y));
+  if constexpr (sizeof(T) == 4) {
+    // FP64 Ehrlich-Aberth from the FP32 roots: the repulsion keeps clustered roots next to
+    // a low-mass lens apart while they converge (FP32 alone cannot resolve them)
+    bool conv64 = true;
+    ehrlich_aberth<double, D>(P, zr, 50, &conv64, true);
+    conv = conv64;
+  }
   if (!conv) st |= kStRootNonconv;
   n_img = 0;
 #pragma unroll
-  for (int k = 0; k < D; ++k) accept_image<N, D>(L, w, mk(double(z[k].x), double(z[k].y)), img, n_img);
+  for (int k = 0; k < D; ++k) accept_image<N, D>(L, w, zr[k], img, n_img);
   if (!count_ok<N>(n_img)) {
     // leading-order image next to lens k: z = a_k - eps_k / conj(w' - a_k), with w'
     // shifted by the other lenses' deflection at a_k

@@ -33,19 +33,26 @@ hipError_t launch_limb_sectors(int n_lens, int root_fp32, int n_limb, const Batc
                                uint32_t* status, hipStream_t s);
 
 struct RayWork {
-  const int32_t* list;  // epochs to process, or nullptr = all epochs 0..n-1
-  int64_t n;            // number of epochs in the list
+  const int32_t* list = nullptr;    // epochs to process (all their sectors), or nullptr = 0..n-1
+  int64_t n = 0;                    // number of epochs in the list
+  const int32_t* items = nullptr;   // instead: single sectors 16 e + slot, count in *n_items
+  const int32_t* n_items = nullptr;
+  int32_t* fallback = nullptr;      // FP32 pass: sectors sent to the FP64 pass
+  int32_t* n_fallback = nullptr;
 };
 
+// persistent ray kernel; queue: 16 bytes of device scratch (zeroed here) for the work
+// counter; fallback/n_fallback: [n_epochs * 10] list + counter for FP32 -> FP64 sectors
 hipError_t launch_rays(int n_lens, int ray_fp32, const Batch& b, const SectorBuf& sec, const RayWork& w, int n_r,
-                       int n_theta, double delta_c, double* partial, uint8_t* clip, hipStream_t s);
+                       int n_theta, double delta_c, double* partial, uint8_t* clip, unsigned long long* queue,
+                       int32_t* fallback, int32_t* n_fallback, hipStream_t s);
 
 // sums sector fluxes into magnifications; epochs with edge touches and retries left get
 // widened sectors and are appended to next_list (count in *next_count)
 hipError_t launch_finalize(const Batch& b, const SectorBuf& sec, const RayWork& w, const double* partial,
                            const uint8_t* clip, int attempt, int max_retries, int32_t* next_list,
                            int32_t* next_count, double* mag, uint32_t* status, uint32_t extra_status,
-                           hipStream_t s);
+                           unsigned long long* passes, hipStream_t s);
 
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);

@@ -1,12 +1,13 @@
 // icrs_rays.hip -- inverse ray shooting and row quadrature (Sec. 3.3, App. A).
 //
-// One workgroup (4 wave64s) per (epoch, sector).  The sector's N_r x N_theta polar grid is
-// never stored: each wave owns every 4th row; lane l owns the columns l, l+64, l+128, ...
-// whose cos/sin stay in registers for the whole sector.  For one row a lane maps its nodes
-// through the lens equation, the wave takes ballots of chi = [d < rho] (one 64-bit mask per
-// 64 columns), and only lanes holding a boundary node read their neighbours' distances back
-// from a per-wave LDS row buffer to place the crossing on the cubic interpolant.  Row sums
-// stay in registers; each workgroup writes one partial flux per (epoch, sector).
+// Persistent kernel: a grid sized to the chip; each workgroup (4 wave64s) takes the next task
+// (all sectors of one epoch, or one (epoch, sector) item) from a device counter.  The
+// N_r x N_theta polar grid is never stored: each wave owns every 4th row, lane l owns the
+// columns l, l+64, l+128, ...  For one row a lane maps its nodes through the lens equation,
+// adds the brightness of its inside nodes, and the wave takes ballots of chi = [d < rho].
+// Inside nodes with an outside (or missing) neighbour are found with bit operations on the
+// ballot masks, handed out one per lane, and get their crossing and edge weight in a single
+// pass, reading neighbour distances back from a per-wave LDS row buffer.
 #include "icrs_device.hpp"
 #include "icrs_launch.hpp"
 
@@ -68,7 +69,13 @@ __device__ inline T crossing_t(T d0, T d1, T d2, T d3, bool cubic, T rho) {
   return t;
 }
 
-__device__ __forceinline__ int bit_of(uint64_t m, int b) { return (int)((m >> b) & 1ull); }
+// sqrt(c) for c >= 0 from the hardware reciprocal square root (one Newton step in FP64)
+__device__ __forceinline__ double sqrt_fast(double c) {
+  double y = __builtin_amdgcn_rsq(c);
+  y = y * fma(-0.5 * c * y, y, 1.5);
+  return c > 0.0 ? c * y : 0.0;
+}
+__device__ __forceinline__ float sqrt_fast(float c) { return __builtin_amdgcn_sqrtf(c); }
 
 // Node maps.  MapF64 evaluates eq. lens_eq directly in FP64.  MapF32 works relative to an
 // FP64 anchor z_a = r_i e^{i theta_a} on each row: with dz = z - z_a = r_i e^{i theta_a}
@@ -96,11 +103,11 @@ struct MapF64 {
 #pragma unroll
     for (int k = 0; k < N; ++k) {
       const double dx = x - L.a[k].x, dy = y - L.a[k].y;
-      const double inv = L.eps[k] / (dx * dx + dy * dy);
-      wx -= inv * dx;
-      wy -= inv * dy;
+      const double inv = L.eps[k] * rcp_fast(fma(dx, dx, dy * dy));
+      wx = fma(-inv, dx, wx);
+      wy = fma(-inv, dy, wy);
     }
-    return wx * wx + wy * wy;
+    return fma(wx, wx, wy * wy);
   }
 };
 
@@ -129,22 +136,22 @@ struct MapF32 {
     }
   }
   __device__ void init_row(double r_i) {
-    const c64 za = mk(r_i * ca, r_i * sa);
-    c64 w = za;
+    const double zx = r_i * ca, zy = r_i * sa;
+    double wx = zx - wc.x, wy = zy - wc.y;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-      const c64 d = za - L.a[k];
-      const double n = norm2(d);
-      w = w - mk(L.eps[k] * d.x / n, L.eps[k] * d.y / n);
-      ax[k] = (float)d.x;
-      ay[k] = (float)d.y;
-      const double s = L.eps[k] / n;  // eps/d = eps conj(d)/|d|^2
-      hx[k] = (float)(s * d.x);
-      hy[k] = (float)(-s * d.y);
+      const double dx = zx - L.a[k].x, dy = zy - L.a[k].y;
+      const double s = L.eps[k] * rcp_fast(fma(dx, dx, dy * dy));  // eps/d = eps conj(d)/|d|^2
+      wx = fma(-s, dx, wx);
+      wy = fma(-s, dy, wy);
+      ax[k] = (float)dx;
+      ay[k] = (float)dy;
+      hx[k] = (float)(s * dx);
+      hy[k] = (float)(-s * dy);
     }
     r = (float)r_i;
-    bx = (float)(w.x - wc.x);
-    by = (float)(w.y - wc.y);
+    bx = (float)wx;
+    by = (float)wy;
   }
   __device__ __forceinline__ float d2(int j) const {
     const float dzx = r * gx[j], dzy = r * gy[j];
@@ -152,135 +159,185 @@ struct MapF32 {
 #pragma unroll
     for (int k = 0; k < N; ++k) {
       const float ux = ax[k] + dzx, uy = ay[k] + dzy;
-      const float inv = __builtin_amdgcn_rcpf(ux * ux + uy * uy);
-      const float px = dzx * hx[k] - dzy * hy[k];
-      const float py = dzx * hy[k] + dzy * hx[k];
-      const float qx = px * ux + py * uy;  // p conj(u)
-      const float qy = py * ux - px * uy;
-      Dx += qx * inv;
-      Dy -= qy * inv;
+      const float inv = __builtin_amdgcn_rcpf(fmaf(ux, ux, uy * uy));
+      const float px = fmaf(dzx, hx[k], -dzy * hy[k]);
+      const float py = fmaf(dzx, hy[k], dzy * hx[k]);
+      const float qx = fmaf(px, ux, py * uy);  // p conj(u)
+      const float qy = fmaf(py, ux, -px * uy);
+      Dx = fmaf(qx, inv, Dx);
+      Dy = fmaf(-qy, inv, Dy);
     }
-    return Dx * Dx + Dy * Dy;
+    return fmaf(Dx, Dx, Dy * Dy);
   }
 };
 
+// Rounding bound of the FP32 map on one sector, relative to rho: the per-row anchor keeps
+// |dz| <= 2 r_hi sin(half angular width / 2), and each lens term is at most
+// eps_k |dz| / dist_k^2 with dist_k a lower bound of the lens' distance to the sector box.
+template <int N>
+__device__ inline double fp32_error_bound(const Lens<N>& L, const double* sp, bool per, double rho) {
+  const double r_lo = sp[0], r_hi = sp[1], th_lo = sp[2], th_hi = sp[3];
+  const double half = per ? kPi : 0.5 * (th_hi - th_lo);
+  const double dz = 2.0 * r_hi * sin(0.5 * fmin(half, kPi));
+  double amp = 1.0;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const double rk = sqrt(norm2(L.a[k]));
+    const double tk = atan2(L.a[k].y, L.a[k].x);
+    const double dr = fmax(fmax(r_lo - rk, rk - r_hi), 0.0);
+    double dth = 0.0;
+    if (!per) {  // circular distance from tk to [th_lo, th_hi]
+      const double off = remainder(tk - 0.5 * (th_lo + th_hi), 2.0 * kPi);
+      dth = fmax(fabs(off) - half, 0.0);
+    }
+    const double dist = fmax(dr, rk * (dth >= 0.5 * kPi ? 1.0 : sin(dth)));
+    amp += (dist > 0.0) ? L.eps[k] / (dist * dist) : 1e300;
+  }
+  return 5.96e-8 * (1.0 + dz * amp / rho);
+}
+constexpr double kFp32Budget = 6e-5;  // per-node distance error (relative to rho) allowed in FP32
+
+__device__ __forceinline__ int bit_of(uint64_t m, int b) { return (int)((m >> b) & 1ull); }
+
+template <typename T>
+__device__ __forceinline__ T brightness(T d2, T inv_rho2, T i_lin, T i_sqrt) {
+  const T c = fmax(fma(-d2, inv_rho2, T(1)), T(0));
+  return fma(i_sqrt, sqrt_fast(c), i_lin);  // I0 (1 - u1) + I0 u1 sqrt(1 - d^2/rho^2)
+}
+
+// One (epoch, sector) grid shot by the whole workgroup; the flux and clip bits end up in
+// thread 0.
 template <int N, int JMAX, typename MAP>
-__global__ __launch_bounds__(256) void rays_kernel(Batch b, SectorBuf sec, RayWork w, int n_r, int n_theta,
-                                                   double delta_c_d, double* __restrict__ partial,
-                                                   uint8_t* __restrict__ clip_out) {
+__device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L, c64 wc, double rho_d, double u1_d,
+                                    double delta_c_d, int n_r, int n_theta, typename MAP::T* rowbuf_all,
+                                    double* wsum, int* wclip, double* flux_out, int* clip_out_bits) {
   using T = typename MAP::T;
-  __shared__ T rowbuf[kWaves][JMAX * 64];
-  __shared__ double wsum[kWaves];
-  __shared__ int wclip[kWaves];
-
-  const int slot = blockIdx.x % kMaxSectors;
-  const int64_t widx = blockIdx.x / kMaxSectors;
-  const int64_t e = w.list ? (int64_t)w.list[widx] : widx;
-  if (slot >= sec.nsec[e]) return;
-
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const double* sp = sec.sectors + (e * kMaxSectors + slot) * 4;
   const double r_lo = sp[0], r_hi = sp[1], th_lo = sp[2], th_hi = sp[3];
-  const bool per = sec.periodic[e * kMaxSectors + slot] != 0;
-  const double* p = b.params + (int64_t)b.epoch_event[e] * kParams;
-  const double rho_d = p[6], u1_d = p[7];
   const T rho = (T)rho_d, u1 = (T)u1_d, delta_c = (T)delta_c_d;
   const T rho2 = (T)(rho_d * rho_d), inv_rho2 = (T)(1.0 / (rho_d * rho_d));
-  const T I0 = (T)(3.0 / (kPi * (3.0 - u1_d)));
+  const double I0d = 3.0 / (kPi * (3.0 - u1_d));
+  const T i_lin = (T)(I0d * (1.0 - u1_d)), i_sqrt = (T)(I0d * u1_d);
   const int J = (n_theta + 63) >> 6;
   const double dr = (r_hi - r_lo) / n_r;
   const double dth = (th_hi - th_lo) / n_theta;
   const T f_edge = edge_factor<T>(T(0.5), u1, delta_c) - T(1);  // neighbour beyond a sector edge
   const int last = n_theta - 1;
+  const int jl = last >> 6, bl = last & 63;
 
   MAP map;
-  map.init_sector(make_lens<N>(p), source_center(p, b.t[e]), th_lo, dth, 0.5 * (th_lo + th_hi), lane);
+  map.init_sector(L, wc, th_lo, dth, 0.5 * (th_lo + th_hi), lane);
 
   double acc = 0.0;
   int clip = 0;
-  T* buf = rowbuf[wave];
+  T* buf = rowbuf_all + wave * (JMAX * 64);
 
   for (int i = wave; i < n_r; i += kWaves) {
     const double r = r_lo + (i + 0.5) * dr;
     map.init_row(r);
-    T d2[JMAX];
     uint64_t m[JMAX];
     uint64_t any = 0;
+    T row = T(0);
 #pragma unroll
     for (int j = 0; j < JMAX; ++j) {
       m[j] = 0;
-      d2[j] = T(0);
       if (j < J) {
         const int l = lane + 64 * j;
-        d2[j] = (l < n_theta) ? map.d2(j) : T(__builtin_inf());
-        m[j] = __ballot(d2[j] < rho2);
+        const T d2 = (l < n_theta) ? map.d2(j) : T(__builtin_inf());
+        const bool in = d2 < rho2;
+        m[j] = __ballot(in);
         any |= m[j];
+        if (l < n_theta) buf[l] = d2;
+        const T I = brightness<T>(d2, inv_rho2, i_lin, i_sqrt);
+        row += in ? I : T(0);
       }
     }
-    if (any == 0) continue;  // wave-uniform
+    if (any == 0) continue;  // wave-uniform: the row misses the image
     if (i == 0 && r_lo > 0.0) clip |= 1;
     if (i == n_r - 1) clip |= 2;
     uint64_t m_last = 0;
 #pragma unroll
     for (int j = 0; j < JMAX; ++j)
-      if (j == (last >> 6)) m_last = m[j];
-    const int in_last = bit_of(m_last, last & 63);
+      if (j == jl) m_last = m[j];
+    const uint64_t in_last = (m_last >> bl) & 1ull;
     if (!per) {
       if (m[0] & 1ull) clip |= 4;
       if (in_last) clip |= 8;
     }
+    // boundary masks (wave-uniform): inside nodes whose left / right neighbour is outside
+    // or beyond a non-periodic edge
+    uint64_t bnd[JMAX], bL[JMAX], bR[JMAX];
+    int nb = 0;
 #pragma unroll
     for (int j = 0; j < JMAX; ++j) {
-      const int l = lane + 64 * j;
-      if (j < J && l < n_theta) buf[l] = d2[j];
+      bnd[j] = 0;
+      bL[j] = 0;
+      bR[j] = 0;
+      if (j < J) {
+        const uint64_t carry_l = (j > 0) ? (m[j > 0 ? j - 1 : 0] >> 63) : (per ? in_last : 0ull);
+        const uint64_t left = (m[j] << 1) | carry_l;
+        uint64_t right = (m[j] >> 1) | ((j + 1 < J) ? (m[j + 1 < JMAX ? j + 1 : j] << 63) : 0ull);
+        if (j == jl && per) right |= (m[0] & 1ull) << bl;
+        bL[j] = m[j] & ~left;
+        bR[j] = m[j] & ~right;
+        bnd[j] = bL[j] | bR[j];
+        nb += __popcll(bnd[j]);
+      }
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-
-    T row = T(0);
+    // one boundary node per lane
+    for (int base = 0; base < nb; base += 64) {
+      const int k = base + lane;
+      if (k < nb) {
+        int rem = k, l = 0;
+        bool has_l = false, has_r = false;
 #pragma unroll
-    for (int j = 0; j < JMAX; ++j) {
-      if (j >= J) continue;
-      const int l = lane + 64 * j;
-      if (!bit_of(m[j], lane)) continue;
-      // neighbour flags: -1 beyond a non-periodic edge, else inside (1) / outside (0)
-      int lin, rin;
-      if (l >= 1)
-        lin = lane ? bit_of(m[j], lane - 1) : bit_of(m[j > 0 ? j - 1 : 0], 63);
-      else
-        lin = per ? in_last : -1;
-      if (l + 1 < n_theta)
-        rin = (lane < 63) ? bit_of(m[j], lane + 1) : (int)(m[j + 1 < JMAX ? j + 1 : j] & 1ull);
-      else
-        rin = per ? (int)(m[0] & 1ull) : -1;
-      T W = T(1);
-      if (lin < 0) {
-        W += f_edge;
-      } else if (lin == 0) {  // crossing in (theta_{l-1}, theta_l): bracket p = l-1
-        const int pp = l - 1 < 0 ? last : l - 1;
-        const bool cubic = per || (l - 2 >= 0 && l + 1 <= last);
-        const int im1 = per ? (pp - 1 + n_theta) % n_theta : max(pp - 1, 0);
-        const int ip2 = per ? (pp + 2) % n_theta : min(pp + 2, last);
-        const int ip1 = (pp + 1) % n_theta;
-        const T t = crossing_t<T>(sqrt(buf[im1]), sqrt(buf[pp]), sqrt(buf[ip1]), sqrt(buf[ip2]), cubic, rho);
-        W += edge_factor<T>(T(1) - t, u1, delta_c) - T(1);
+        for (int j = 0; j < JMAX; ++j) {
+          const int pc = __popcll(bnd[j]);
+          if (rem >= 0 && rem < pc) {
+            uint64_t word = bnd[j];
+            for (int q = 0; q < rem; ++q) word &= word - 1ull;
+            const int bpos = __ffsll((unsigned long long)word) - 1;
+            l = 64 * j + bpos;
+            has_l = (bL[j] >> bpos) & 1ull;
+            has_r = (bR[j] >> bpos) & 1ull;
+          }
+          rem -= pc;
+        }
+        T corr = T(0);
+        if (has_l) {
+          if (l == 0 && !per) {
+            corr += f_edge;
+          } else {  // crossing in (theta_{l-1}, theta_l): bracket p = l-1
+            const int pp = l == 0 ? last : l - 1;
+            const bool cubic = per || (l - 2 >= 0 && l + 1 <= last);
+            const int im1 = per ? (pp - 1 + n_theta) % n_theta : max(pp - 1, 0);
+            const int ip2 = per ? (pp + 2) % n_theta : min(pp + 2, last);
+            const int ip1 = (pp + 1) % n_theta;
+            const T t =
+                crossing_t<T>(sqrt(buf[im1]), sqrt(buf[pp]), sqrt(buf[ip1]), sqrt(buf[ip2]), cubic, rho);
+            corr += edge_factor<T>(T(1) - t, u1, delta_c) - T(1);
+          }
+        }
+        if (has_r) {
+          if (l == last && !per) {
+            corr += f_edge;
+          } else {  // crossing in (theta_l, theta_{l+1}): bracket p = l
+            const int pp = l;
+            const bool cubic = per || (l - 1 >= 0 && l + 2 <= last);
+            const int im1 = per ? (pp - 1 + n_theta) % n_theta : max(pp - 1, 0);
+            const int ip2 = per ? (pp + 2) % n_theta : min(pp + 2, last);
+            const int ip1 = (pp + 1) % n_theta;
+            const T t =
+                crossing_t<T>(sqrt(buf[im1]), sqrt(buf[pp]), sqrt(buf[ip1]), sqrt(buf[ip2]), cubic, rho);
+            corr += edge_factor<T>(t, u1, delta_c) - T(1);
+          }
+        }
+        row += brightness<T>(buf[l], inv_rho2, i_lin, i_sqrt) * corr;
       }
-      if (rin < 0) {
-        W += f_edge;
-      } else if (rin == 0) {  // crossing in (theta_l, theta_{l+1}): bracket p = l
-        const int pp = l;
-        const bool cubic = per || (l - 1 >= 0 && l + 2 <= last);
-        const int im1 = per ? (pp - 1 + n_theta) % n_theta : max(pp - 1, 0);
-        const int ip2 = per ? (pp + 2) % n_theta : min(pp + 2, last);
-        const int ip1 = (pp + 1) % n_theta;
-        const T t = crossing_t<T>(sqrt(buf[im1]), sqrt(buf[pp]), sqrt(buf[ip1]), sqrt(buf[ip2]), cubic, rho);
-        W += edge_factor<T>(t, u1, delta_c) - T(1);
-      }
-      const T c = fmax(T(1) - d2[j] * inv_rho2, T(0));
-      const T I = I0 * (T(1) - u1 * (T(1) - sqrt(c)));
-      row += I * W;
     }
     acc += r * (double)row;
     __builtin_amdgcn_wave_barrier();
@@ -301,19 +358,87 @@ __global__ __launch_bounds__(256) void rays_kernel(Batch b, SectorBuf sec, RayWo
       tot += wsum[q];
       c |= wclip[q];
     }
-    partial[e * kMaxSectors + slot] = tot * dr * dth;
-    clip_out[e * kMaxSectors + slot] = (uint8_t)c;
+    *flux_out = tot * dr * dth;
+    *clip_out_bits = c;
+  }
+  __syncthreads();
+}
+
+// Persistent ray kernel.  Tasks come from a device counter: with w.items set, task k is the
+// single sector w.items[k] = 16 e + slot (k < *w.n_items); otherwise task k is every sector
+// of epoch w.list[k] (or k).  An FP32 pass sends sectors whose rounding bound exceeds the
+// budget to w.fallback for the FP64 pass.  Every workgroup leaves once the counter has
+// passed the end.
+template <int N, int JMAX, typename MAP>
+__global__ __launch_bounds__(256) void rays_kernel(Batch b, SectorBuf sec, RayWork w, int n_r, int n_theta,
+                                                   double delta_c, double* __restrict__ partial,
+                                                   uint8_t* __restrict__ clip_out,
+                                                   unsigned long long* __restrict__ queue) {
+  using T = typename MAP::T;
+  __shared__ T rowbuf[kWaves * JMAX * 64];
+  __shared__ double wsum[kWaves];
+  __shared__ int wclip[kWaves];
+  __shared__ unsigned long long next_sh;
+  __shared__ int skip_sh;
+
+  const unsigned long long total = w.items ? (unsigned long long)(*w.n_items) : (unsigned long long)w.n;
+  for (;;) {
+    if (threadIdx.x == 0) next_sh = atomicAdd(queue, 1ull);
+    __syncthreads();
+    const unsigned long long idx = next_sh;
+    __syncthreads();
+    if (idx >= total) break;
+    int64_t e;
+    int s0, s1;
+    if (w.items) {
+      const int32_t it = w.items[idx];
+      e = it >> 4;
+      s0 = it & 15;
+      s1 = s0 + 1;
+    } else {
+      e = w.list ? (int64_t)w.list[idx] : (int64_t)idx;
+      s0 = 0;
+      s1 = sec.nsec[e];
+    }
+    const double* p = b.params + (int64_t)b.epoch_event[e] * kParams;
+    const Lens<N> L = make_lens<N>(p);
+    const c64 wc = source_center(p, b.t[e]);
+    for (int slot = s0; slot < s1; ++slot) {
+      const double* sp = sec.sectors + (e * kMaxSectors + slot) * 4;
+      const bool per = sec.periodic[e * kMaxSectors + slot] != 0;
+      if constexpr (sizeof(T) == 4) {
+        if (w.fallback) {
+          if (threadIdx.x == 0) {
+            skip_sh = fp32_error_bound<N>(L, sp, per, p[6]) > kFp32Budget;
+            if (skip_sh) w.fallback[atomicAdd(w.n_fallback, 1)] = (int32_t)(e * 16 + slot);
+          }
+          __syncthreads();
+          const int skip = skip_sh;
+          __syncthreads();
+          if (skip) continue;
+        }
+      }
+      double flux = 0.0;
+      int c = 0;
+      shoot_sector<N, JMAX, MAP>(sp, per, L, wc, p[6], p[7], delta_c, n_r, n_theta, rowbuf, wsum, wclip, &flux, &c);
+      if (threadIdx.x == 0) {
+        partial[e * kMaxSectors + slot] = flux;
+        clip_out[e * kMaxSectors + slot] = (uint8_t)c;
+      }
+    }
   }
 }
 
 __global__ void finalize_kernel(Batch b, SectorBuf sec, RayWork w, const double* __restrict__ partial,
                                 const uint8_t* __restrict__ clip, int attempt, int max_retries,
                                 int32_t* __restrict__ next_list, int32_t* __restrict__ next_count,
-                                double* __restrict__ mag, uint32_t* __restrict__ status, uint32_t extra_status) {
+                                double* __restrict__ mag, uint32_t* __restrict__ status, uint32_t extra_status,
+                                unsigned long long* __restrict__ passes) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= w.n) return;
   const int64_t e = w.list ? (int64_t)w.list[idx] : idx;
   const int ns = sec.nsec[e];
+  if (passes && ns) atomicAdd(passes, (unsigned long long)ns);
   double flux = 0.0;
   int clips[kMaxSectors];
   int any = 0;
@@ -355,42 +480,75 @@ __global__ void finalize_kernel(Batch b, SectorBuf sec, RayWork w, const double*
   status[e] = st;
 }
 
+template <int N, int JMAX, template <int, int> class MAP>
+hipError_t launch_rays_j(const Batch& b, const SectorBuf& sec, const RayWork& w, int n_r, int n_theta,
+                         double delta_c, double* partial, uint8_t* clip, unsigned long long* queue, hipStream_t s) {
+  auto kern = rays_kernel<N, JMAX, MAP<N, JMAX>>;
+  int dev = 0, cus = 0, per_cu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kWaves * 64, 0);
+  if (e != hipSuccess) return e;
+  int64_t grid = (int64_t)cus * (per_cu > 0 ? per_cu : 1);
+  if (!w.items && w.n < grid) grid = w.n;
+  if (grid < 1) grid = 1;
+  e = launch_fill_i32((int32_t*)queue, 2, 0, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kWaves * 64), 0, s, b, sec, w, n_r, n_theta, delta_c, partial,
+                     clip, queue);
+  return hipGetLastError();
+}
+
 template <int N, template <int, int> class MAP>
 hipError_t launch_rays_n(const Batch& b, const SectorBuf& sec, const RayWork& w, int n_r, int n_theta,
-                         double delta_c, double* partial, uint8_t* clip, hipStream_t s) {
-  const dim3 g((unsigned)(w.n * kMaxSectors)), blk(kWaves * 64);
+                         double delta_c, double* partial, uint8_t* clip, unsigned long long* queue, hipStream_t s) {
   const int J = (n_theta + 63) / 64;
-  if (J <= 4)
-    hipLaunchKernelGGL((rays_kernel<N, 4, MAP<N, 4>>), g, blk, 0, s, b, sec, w, n_r, n_theta, delta_c, partial, clip);
-  else if (J <= 8)
-    hipLaunchKernelGGL((rays_kernel<N, 8, MAP<N, 8>>), g, blk, 0, s, b, sec, w, n_r, n_theta, delta_c, partial, clip);
-  else if (J <= 16)
-    hipLaunchKernelGGL((rays_kernel<N, 16, MAP<N, 16>>), g, blk, 0, s, b, sec, w, n_r, n_theta, delta_c, partial,
-                       clip);
-  else
-    return hipErrorInvalidValue;
-  return hipGetLastError();
+  if (J <= 4) return launch_rays_j<N, 4, MAP>(b, sec, w, n_r, n_theta, delta_c, partial, clip, queue, s);
+  if (J <= 8) return launch_rays_j<N, 8, MAP>(b, sec, w, n_r, n_theta, delta_c, partial, clip, queue, s);
+  if (J <= 16) return launch_rays_j<N, 16, MAP>(b, sec, w, n_r, n_theta, delta_c, partial, clip, queue, s);
+  return hipErrorInvalidValue;
+}
+
+template <int N>
+hipError_t launch_rays_lens(int ray_fp32, const Batch& b, const SectorBuf& sec, const RayWork& w, int n_r,
+                            int n_theta, double delta_c, double* partial, uint8_t* clip, unsigned long long* queue,
+                            int32_t* fallback, int32_t* n_fallback, hipStream_t s) {
+  if (!ray_fp32) return launch_rays_n<N, MapF64>(b, sec, w, n_r, n_theta, delta_c, partial, clip, queue, s);
+  // FP32 pass (sectors over the rounding budget are listed), then the FP64 pass on the list
+  hipError_t e = launch_fill_i32(n_fallback, 1, 0, s);
+  if (e != hipSuccess) return e;
+  RayWork w32 = w;
+  w32.fallback = fallback;
+  w32.n_fallback = n_fallback;
+  e = launch_rays_n<N, MapF32>(b, sec, w32, n_r, n_theta, delta_c, partial, clip, queue, s);
+  if (e != hipSuccess) return e;
+  RayWork w64{};
+  w64.items = fallback;
+  w64.n_items = n_fallback;
+  w64.n = 1;
+  return launch_rays_n<N, MapF64>(b, sec, w64, n_r, n_theta, delta_c, partial, clip, queue, s);
 }
 
 }  // namespace
 
 hipError_t launch_rays(int n_lens, int ray_fp32, const Batch& b, const SectorBuf& sec, const RayWork& w, int n_r,
-                       int n_theta, double delta_c, double* partial, uint8_t* clip, hipStream_t s) {
+                       int n_theta, double delta_c, double* partial, uint8_t* clip, unsigned long long* queue,
+                       int32_t* fallback, int32_t* n_fallback, hipStream_t s) {
   if (w.n == 0) return hipSuccess;
   if (n_lens == 2)
-    return ray_fp32 ? launch_rays_n<2, MapF32>(b, sec, w, n_r, n_theta, delta_c, partial, clip, s)
-                    : launch_rays_n<2, MapF64>(b, sec, w, n_r, n_theta, delta_c, partial, clip, s);
-  return ray_fp32 ? launch_rays_n<3, MapF32>(b, sec, w, n_r, n_theta, delta_c, partial, clip, s)
-                  : launch_rays_n<3, MapF64>(b, sec, w, n_r, n_theta, delta_c, partial, clip, s);
+    return launch_rays_lens<2>(ray_fp32, b, sec, w, n_r, n_theta, delta_c, partial, clip, queue, fallback, n_fallback,
+                               s);
+  return launch_rays_lens<3>(ray_fp32, b, sec, w, n_r, n_theta, delta_c, partial, clip, queue, fallback, n_fallback,
+                             s);
 }
 
 hipError_t launch_finalize(const Batch& b, const SectorBuf& sec, const RayWork& w, const double* partial,
                            const uint8_t* clip, int attempt, int max_retries, int32_t* next_list,
                            int32_t* next_count, double* mag, uint32_t* status, uint32_t extra_status,
-                           hipStream_t s) {
+                           unsigned long long* passes, hipStream_t s) {
   if (w.n == 0) return hipSuccess;
   hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)((w.n + 255) / 256)), dim3(256), 0, s, b, sec, w, partial, clip,
-                     attempt, max_retries, next_list, next_count, mag, status, extra_status);
+                     attempt, max_retries, next_list, next_count, mag, status, extra_status, passes);
   return hipGetLastError();
 }
 

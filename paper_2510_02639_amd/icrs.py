@@ -32,6 +32,15 @@ class IcrsError(RuntimeError):
         self.code = code
 
 
+class icrs_profile(ctypes.Structure):
+    _fields_ = [("ms_centre", ctypes.c_double), ("ms_limb_sectors", ctypes.c_double), ("ms_rays", ctypes.c_double),
+                ("ms_finalize", ctypes.c_double), ("n_calls", ctypes.c_int64), ("n_rays_launches", ctypes.c_int64),
+                ("n_sector_passes", ctypes.c_int64), ("n_epochs", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class icrs_config(ctypes.Structure):
     _fields_ = [("abi_version", ctypes.c_uint32), ("n_lens", ctypes.c_int32), ("n_limb", ctypes.c_int32),
                 ("n_r", ctypes.c_int32), ("n_theta", ctypes.c_int32), ("ray_precision", ctypes.c_int32),
@@ -64,6 +73,10 @@ def lib():
     L.icrs_get_sectors.restype = ctypes.c_int
     L.icrs_point_images.argtypes = [vp, i64, vp, vp, i64, vp, vp, vp, vp, vp, sz]
     L.icrs_point_images.restype = ctypes.c_int
+    L.icrs_set_profiling.argtypes = [vp, ctypes.c_int]
+    L.icrs_set_profiling.restype = ctypes.c_int
+    L.icrs_get_profile.argtypes = [vp, ctypes.POINTER(icrs_profile), ctypes.c_int]
+    L.icrs_get_profile.restype = ctypes.c_int
     L.icrs_status_string.argtypes = [ctypes.c_int]
     L.icrs_status_string.restype = ctypes.c_char_p
     _lib = L
@@ -71,7 +84,8 @@ def lib():
 
 
 EXPORTED = ["icrs_default_config", "icrs_create", "icrs_destroy", "icrs_workspace_bytes", "icrs_magnification",
-            "icrs_magnification_given", "icrs_get_sectors", "icrs_point_images", "icrs_status_string"]
+            "icrs_magnification_given", "icrs_get_sectors", "icrs_point_images", "icrs_set_profiling",
+            "icrs_get_profile", "icrs_status_string"]
 
 
 def _check(code, where):
@@ -129,6 +143,14 @@ class Handle:
             self.close()
         except Exception:
             pass
+
+    def set_profiling(self, on=True):
+        _check(lib().icrs_set_profiling(self._h, int(bool(on))), "icrs_set_profiling")
+
+    def get_profile(self, reset=False):
+        out = icrs_profile()
+        _check(lib().icrs_get_profile(self._h, ctypes.byref(out), int(bool(reset))), "icrs_get_profile")
+        return out.as_dict()
 
     def workspace_bytes(self, n_events, n_epochs):
         return int(lib().icrs_workspace_bytes(self._h, int(n_events), int(n_epochs)))

@@ -210,3 +210,19 @@ def test_fp32_end_to_end_planetary():
     print(f"sector-count agreement {same.mean():.3f}", flush=True)
     assert same.mean() >= 0.95
     assert np.all(rel[same] <= FP32_TOL)
+
+
+def test_fp32_rays_fall_back_to_fp64_next_to_a_planet():
+    """A sector that contains the low-mass lens: FP32 rounding near the planet exceeds the
+    budget, the sector goes to the FP64 pass, and the epoch stays within 3e-5 (planetary
+    event drawn by the rho = 1e-3 batch generator; epochs around its planetary-image epoch)."""
+    p = np.array([1.53866678e+00, 1.13826451e-04, 2.06074577e-01, 3.35158414e+00, 0.0, 20.0, 1e-3,
+                  4.97966683e-01, 0.0, 0.0, 0.0])
+    t = -17.391698122749006 + np.linspace(-0.02, 0.02, 9)
+    w = W.Workload("planet-sector", 2, p[None, :], np.array([0, t.size], np.int64), t, 128, 128, 512, "fp32", "fp32")
+    mag, st, sec, per, ns, _ = _run(w, ray="fp32", root="fp32")
+    ref = _oracle(w)
+    rel = np.abs(mag / ref["mag"] - 1)
+    _report("fp32 near planet", rel)
+    assert np.all(ns == ref["nsec"])
+    assert np.all(rel <= FP32_TOL)
