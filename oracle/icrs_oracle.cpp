@@ -24,6 +24,7 @@
 #include <complex>
 #include <cstdint>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include <omp.h>
@@ -793,6 +794,281 @@ double epoch_magnification(const Lens& L, const double* p, double t, const Confi
   return mag;
 }
 
+// ---------------------------------------------------------------------------------------
+// O13: gradients on the frozen structure (not in the paper, which uses forward-mode AD with
+// a sigmoid surrogate for chi).  The sector boxes, the inside/outside pattern chi, each
+// crossing's stencil and each edge factor's branch are taken from a reference evaluation;
+// with them fixed, the magnification is a smooth function of the parameters.  Its
+// derivative is computed by forward-mode dual numbers with one tangent per parameter; the
+// crossing position, found by bisection on values, gets its tangent from the implicit
+// function theorem on L(t) = rho:  dt = (drho - sum_j l_j(t) dd_j) / L'(t).
+constexpr int kNT = 11;
+
+struct Dual {
+  double v = 0.0;
+  double d[kNT] = {};
+  Dual() = default;
+  Dual(double x) : v(x) {}  // NOLINT: constants promote implicitly
+};
+Dual operator+(const Dual& a, const Dual& b) {
+  Dual r(a.v + b.v);
+  for (int k = 0; k < kNT; ++k) r.d[k] = a.d[k] + b.d[k];
+  return r;
+}
+Dual operator-(const Dual& a, const Dual& b) {
+  Dual r(a.v - b.v);
+  for (int k = 0; k < kNT; ++k) r.d[k] = a.d[k] - b.d[k];
+  return r;
+}
+Dual operator-(const Dual& a) { return Dual(0.0) - a; }
+Dual operator*(const Dual& a, const Dual& b) {
+  Dual r(a.v * b.v);
+  for (int k = 0; k < kNT; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k];
+  return r;
+}
+Dual operator/(const Dual& a, const Dual& b) {
+  Dual r(a.v / b.v);
+  for (int k = 0; k < kNT; ++k) r.d[k] = (a.d[k] * b.v - a.v * b.d[k]) / (b.v * b.v);
+  return r;
+}
+Dual dsqrt(const Dual& a) {
+  Dual r(std::sqrt(a.v));
+  for (int k = 0; k < kNT; ++k) r.d[k] = a.d[k] / (2.0 * r.v);
+  return r;
+}
+Dual dsin(const Dual& a) {
+  Dual r(std::sin(a.v));
+  for (int k = 0; k < kNT; ++k) r.d[k] = a.d[k] * std::cos(a.v);
+  return r;
+}
+Dual dcos(const Dual& a) {
+  Dual r(std::cos(a.v));
+  for (int k = 0; k < kNT; ++k) r.d[k] = -a.d[k] * std::sin(a.v);
+  return r;
+}
+double val(double x) { return x; }
+double val(const Dual& x) { return x.v; }
+double dsqrt(double x) { return std::sqrt(x); }
+double dsin(double x) { return std::sin(x); }
+double dcos(double x) { return std::cos(x); }
+
+template <class S>
+struct LensT {
+  int n = 0;
+  S eps[3];
+  S ax[3], ay[3];
+};
+
+// the frame of make_lens(), in scalar type S
+template <class S>
+LensT<S> make_lens_t(int n_lens, const S* p) {
+  LensT<S> L;
+  L.n = n_lens;
+  if (n_lens == 1) {
+    L.eps[0] = S(1.0);
+    L.ax[0] = S(0.0);
+    L.ay[0] = S(0.0);
+  } else if (n_lens >= 2) {
+    const S s = p[0], q = p[1];
+    const S q3 = (n_lens == 3) ? p[8] : S(0.0);
+    const S pair = S(1.0) + q;
+    const S m = pair + q3;
+    L.eps[0] = S(1.0) / m;
+    L.eps[1] = q / m;
+    L.ax[0] = -(q * s) / pair;
+    L.ax[1] = s / pair;
+    L.ay[0] = S(0.0);
+    L.ay[1] = S(0.0);
+    if (n_lens == 3) {
+      L.eps[2] = q3 / m;
+      const S mid = S(0.5) * (L.ax[0] + L.ax[1]);
+      L.ax[2] = mid + p[9] * dcos(p[10]);
+      L.ay[2] = p[9] * dsin(p[10]);
+    }
+  }
+  return L;
+}
+
+template <class S>
+void source_center_t(const S* p, double t, S* wx, S* wy) {
+  const S tau = (S(t) - p[4]) / p[5];
+  *wx = tau * dcos(p[3]) - p[2] * dsin(p[3]);
+  *wy = tau * dsin(p[3]) + p[2] * dcos(p[3]);
+}
+
+// d = |lens_map(z) - w_c| for a grid node z (no tangent)
+template <class S>
+S node_distance(const LensT<S>& L, double zx, double zy, const S& wx, const S& wy) {
+  S ux = S(zx) - wx, uy = S(zy) - wy;
+  for (int k = 0; k < L.n; ++k) {
+    const S dx = S(zx) - L.ax[k], dy = S(zy) - L.ay[k];
+    const S inv = L.eps[k] / (dx * dx + dy * dy);  // eps / conj(z - a) = eps (z - a) / |z - a|^2
+    ux = ux - inv * dx;
+    uy = uy - inv * dy;
+  }
+  return dsqrt(ux * ux + uy * uy);
+}
+
+template <class S>
+S brightness_t(const S& x, const S& u1) {
+  const S I0 = S(3.0) / (S(kPi) * (S(3.0) - u1));
+  S c = S(1.0) - x * x;
+  if (val(c) < 0.0) c = S(0.0);
+  return I0 * (S(1.0) - u1 * (S(1.0) - dsqrt(c)));
+}
+
+// f(delta) with its branch fixed: 0 uniform, 1 square-root branch, 2 linear branch
+template <class S>
+S edge_factor_fixed(const S& delta, int branch) {
+  if (branch == 0) return delta + S(0.5);
+  if (branch == 1) return (S(0.5) + delta) * S(2.0 / 3.0) * dsqrt(S(1.0) + S(1.0) / (S(2.0) * delta));
+  return S(2.0 / 3.0) * delta + S(0.5);
+}
+int edge_branch(double delta, double u1, double delta_c) {
+  if (u1 == 0.0) return 0;
+  return (delta >= delta_c && delta > 0.0) ? 1 : 2;
+}
+
+// Crossing on a frozen stencil.  Recording: bisection on values (as the primal), tangent by
+// implicit differentiation.  Frozen (t_ref given): the same interpolant solved by Newton from
+// the reference crossing without bracketing -- the smooth continuation of the reference
+// root when the perturbed values no longer bracket rho.
+template <class S>
+S crossing_t_frozen(const S d[4], int cubic, const S& rho, const double* t_ref) {
+  double dv[4] = {val(d[0]), val(d[1]), val(d[2]), val(d[3])};
+  double t;
+  if (!t_ref) {
+    t = crossing_t(dv, cubic, val(rho));
+  } else if (!cubic) {
+    t = (val(rho) - dv[1]) / (dv[2] - dv[1]);
+  } else {
+    t = *t_ref;
+    for (int it = 0; it < 50; ++it) {
+      const double g = lagrange4(dv, t) - val(rho);
+      const double h = 1e-7;
+      const double dg = (lagrange4(dv, t + h) - lagrange4(dv, t - h)) / (2.0 * h);
+      const double step = g / dg;
+      t -= step;
+      if (std::abs(step) < 1e-15) break;
+    }
+  }
+  if constexpr (std::is_same<S, double>::value) {
+    return t;
+  } else {
+    double l[4], dl[4];
+    if (cubic) {
+      const double tm1 = t + 1.0, t0 = t, t1 = t - 1.0, t2 = t - 2.0;
+      l[0] = -(t0 * t1 * t2) / 6.0;
+      l[1] = tm1 * t1 * t2 / 2.0;
+      l[2] = -(tm1 * t0 * t2) / 2.0;
+      l[3] = tm1 * t0 * t1 / 6.0;
+      dl[0] = -(t1 * t2 + t0 * t2 + t0 * t1) / 6.0;
+      dl[1] = (t1 * t2 + tm1 * t2 + tm1 * t1) / 2.0;
+      dl[2] = -(t0 * t2 + tm1 * t2 + tm1 * t0) / 2.0;
+      dl[3] = (t0 * t1 + tm1 * t1 + tm1 * t0) / 6.0;
+    } else {
+      l[0] = 0.0;
+      l[1] = 1.0 - t;
+      l[2] = t;
+      l[3] = 0.0;
+      dl[0] = 0.0;
+      dl[1] = -1.0;
+      dl[2] = 1.0;
+      dl[3] = 0.0;
+    }
+    double Lp = 0.0;
+    for (int j = 0; j < 4; ++j) Lp += dl[j] * dv[j];
+    S r(t);
+    for (int k = 0; k < kNT; ++k) {
+      double num = rho.d[k];
+      for (int j = 0; j < 4; ++j) num -= l[j] * d[j].d[k];
+      r.d[k] = num / Lp;
+    }
+    return r;
+  }
+}
+
+// Decisions of one sector: chi per node, the edge-factor branch and the crossing per
+// (node, side).
+struct Pattern {
+  std::vector<char> chi;     // [nr][nth]
+  std::vector<char> branch;  // [nr][nth][2]
+  std::vector<double> tref;  // [nr][nth][2]
+};
+
+// Flux of one sector in scalar type S.  With record != nullptr the decisions are taken
+// from the values computed here and stored; otherwise they are read from *frozen.
+template <class S>
+S sector_flux_t(const LensT<S>& L, const S& wx, const S& wy, const S& rho, const S& u1, double delta_c, int nr,
+                int nth, const Sector& Sc, Pattern* record, const Pattern* frozen) {
+  const double dr = (Sc.r_hi - Sc.r_lo) / nr;
+  const double dth = (Sc.th_hi - Sc.th_lo) / nth;
+  if (record) {
+    record->chi.assign((size_t)nr * nth, 0);
+    record->branch.assign((size_t)nr * nth * 2, 0);
+    record->tref.assign((size_t)nr * nth * 2, 0.0);
+  }
+  std::vector<S> d(nth);
+  S total(0.0);
+  for (int i = 0; i < nr; ++i) {
+    const double ri = Sc.r_lo + (i + 0.5) * dr;
+    for (int l = 0; l < nth; ++l) {
+      const double th = Sc.th_lo + (l + 0.5) * dth;
+      d[l] = node_distance(L, ri * std::cos(th), ri * std::sin(th), wx, wy);
+    }
+    auto inside = [&](int l) -> bool {
+      if (record) {
+        const bool in = val(d[l]) < val(rho);
+        record->chi[(size_t)i * nth + l] = in;
+        return in;
+      }
+      return frozen->chi[(size_t)i * nth + l] != 0;
+    };
+    std::vector<char> in(nth);
+    for (int l = 0; l < nth; ++l) in[l] = inside(l);
+    S row(0.0);
+    for (int l = 0; l < nth; ++l) {
+      if (!in[l]) continue;
+      S W(1.0);
+      for (int side = 0; side < 2; ++side) {
+        const bool at_edge = !Sc.periodic && (side == 0 ? l == 0 : l == nth - 1);
+        int br;
+        if (at_edge) {
+          br = record ? edge_branch(0.5, val(u1), delta_c) : frozen->branch[((size_t)i * nth + l) * 2 + side];
+          if (record) record->branch[((size_t)i * nth + l) * 2 + side] = (char)br;
+          W = W + edge_factor_fixed(S(0.5), br) - S(1.0);
+          continue;
+        }
+        const int nb = side == 0 ? (l - 1 + nth) % nth : (l + 1) % nth;
+        if (in[nb]) continue;
+        const int p = side == 0 ? nb : l;
+        S st[4];
+        int cubic = 1;
+        for (int j = -1; j <= 2; ++j) {
+          int idx = p + j;
+          if (Sc.periodic) {
+            idx = (idx % nth + nth) % nth;
+          } else if (idx < 0 || idx >= nth) {
+            cubic = 0;
+            idx = std::min(std::max(idx, 0), nth - 1);
+          }
+          st[j + 1] = d[idx];
+        }
+        const size_t slot = ((size_t)i * nth + l) * 2 + side;
+        const S t = crossing_t_frozen(st, cubic, rho, record ? nullptr : &frozen->tref[slot]);
+        if (record) record->tref[slot] = val(t);
+        const S delta = side == 0 ? S(1.0) - t : t;
+        br = record ? edge_branch(val(delta), val(u1), delta_c) : frozen->branch[((size_t)i * nth + l) * 2 + side];
+        if (record) record->branch[((size_t)i * nth + l) * 2 + side] = (char)br;
+        W = W + edge_factor_fixed(delta, br) - S(1.0);
+      }
+      row = row + brightness_t(d[l] / rho, u1) * W;
+    }
+    total = total + S(ri * dth * dr) * row;
+  }
+  return total;
+}
+
 }  // namespace
 
 // =======================================================================================
@@ -973,6 +1249,59 @@ void orc_magnification_given(int n_lens, const double* params, int64_t n_epochs,
     mag[e] = flux / (rho * rho);
     if (!std::isfinite(mag[e])) st |= ST_NAN;
     status[e] = st;
+  }
+}
+
+// Jacobian d mag / d params (all 11 entries; unused ones are 0) on caller-given sectors,
+// with the decisions of the evaluation at params itself (forward-mode dual numbers).
+void orc_jacobian_given(int n_lens, const double* params, int64_t n_epochs, const double* t, int n_r, int n_theta,
+                        double delta_c, int kmax, const double* sec, const uint8_t* periodic, const int32_t* nsec,
+                        double* mag, double* jac) {
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t e = 0; e < n_epochs; ++e) {
+    Dual p[kNT];
+    for (int k = 0; k < kNT; ++k) {
+      p[k] = Dual(params[k]);
+      p[k].d[k] = 1.0;
+    }
+    const LensT<Dual> L = make_lens_t(n_lens, p);
+    Dual wx, wy;
+    source_center_t(p, t[e], &wx, &wy);
+    Dual flux(0.0);
+    for (int s = 0; s < nsec[e]; ++s) {
+      const double* g = sec + (e * kmax + s) * 4;
+      Sector S{g[0], g[1], g[2], g[3], periodic[e * kmax + s] != 0};
+      Pattern pat;
+      flux = flux + sector_flux_t(L, wx, wy, p[6], p[7], delta_c, n_r, n_theta, S, &pat, nullptr);
+    }
+    const Dual m = flux / (p[6] * p[6]);
+    mag[e] = m.v;
+    for (int k = 0; k < kNT; ++k) jac[e * kNT + k] = m.d[k];
+  }
+}
+
+// Magnification at params_eval with every decision taken from params_ref (frozen
+// structure), on caller-given sectors: the function whose central differences check the
+// Jacobian.
+void orc_magnification_frozen(int n_lens, const double* params_eval, const double* params_ref, int64_t n_epochs,
+                              const double* t, int n_r, int n_theta, double delta_c, int kmax, const double* sec,
+                              const uint8_t* periodic, const int32_t* nsec, double* mag) {
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t e = 0; e < n_epochs; ++e) {
+    const LensT<double> Lr = make_lens_t(n_lens, params_ref);
+    const LensT<double> Le = make_lens_t(n_lens, params_eval);
+    double wxr, wyr, wxe, wye;
+    source_center_t(params_ref, t[e], &wxr, &wyr);
+    source_center_t(params_eval, t[e], &wxe, &wye);
+    double flux = 0.0;
+    for (int s = 0; s < nsec[e]; ++s) {
+      const double* g = sec + (e * kmax + s) * 4;
+      Sector S{g[0], g[1], g[2], g[3], periodic[e * kmax + s] != 0};
+      Pattern pat;
+      sector_flux_t(Lr, wxr, wyr, params_ref[6], params_ref[7], delta_c, n_r, n_theta, S, &pat, nullptr);
+      flux += sector_flux_t(Le, wxe, wye, params_eval[6], params_eval[7], delta_c, n_r, n_theta, S, nullptr, &pat);
+    }
+    mag[e] = flux / (params_eval[6] * params_eval[6]);
   }
 }
 

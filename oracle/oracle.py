@@ -70,6 +70,8 @@ def lib():
                                         P(i32), P(d)]
         L.orc_magnification_given.argtypes = [i, P(d), i64, P(d), i, i, d, i, P(d), P(u8), P(i32), P(d),
                                               P(u32)]
+        L.orc_jacobian_given.argtypes = [i, P(d), i64, P(d), i, i, d, i, P(d), P(u8), P(i32), P(d), P(d)]
+        L.orc_magnification_frozen.argtypes = [i, P(d), P(d), i64, P(d), i, i, d, i, P(d), P(u8), P(i32), P(d)]
         _lib = L
     return _lib
 
@@ -231,3 +233,34 @@ def magnification_given(n_lens, p, t, sectors, periodic, nsec, n_r=64, n_theta=2
                                   _p(periodic, ctypes.c_uint8), _p(nsec, ctypes.c_int32), _p(mag),
                                   _p(st, ctypes.c_uint32))
     return mag, st
+
+
+def jacobian_given(n_lens, p, t, sectors, periodic, nsec, n_r=64, n_theta=256, delta_c=0.1):
+    """Magnifications and d mag / d params [n_epochs, 11] on given sectors, frozen structure."""
+    p = _dbl(p)
+    t = _dbl(np.atleast_1d(t))
+    n = t.size
+    sectors = _dbl(sectors)
+    kmax = sectors.shape[1]
+    periodic = np.ascontiguousarray(periodic, dtype=np.uint8)
+    nsec = np.ascontiguousarray(nsec, dtype=np.int32)
+    mag = np.zeros(n)
+    jac = np.zeros((n, N_PARAMS))
+    lib().orc_jacobian_given(n_lens, _p(p), n, _p(t), n_r, n_theta, delta_c, kmax, _p(sectors),
+                             _p(periodic, ctypes.c_uint8), _p(nsec, ctypes.c_int32), _p(mag), _p(jac))
+    return mag, jac
+
+
+def magnification_frozen(n_lens, p_eval, p_ref, t, sectors, periodic, nsec, n_r=64, n_theta=256, delta_c=0.1):
+    """Magnification at p_eval with every decision (chi, edge branches) taken at p_ref."""
+    pe, pr = _dbl(p_eval), _dbl(p_ref)
+    t = _dbl(np.atleast_1d(t))
+    n = t.size
+    sectors = _dbl(sectors)
+    kmax = sectors.shape[1]
+    periodic = np.ascontiguousarray(periodic, dtype=np.uint8)
+    nsec = np.ascontiguousarray(nsec, dtype=np.int32)
+    mag = np.zeros(n)
+    lib().orc_magnification_frozen(n_lens, _p(pe), _p(pr), n, _p(t), n_r, n_theta, delta_c, kmax, _p(sectors),
+                                   _p(periodic, ctypes.c_uint8), _p(nsec, ctypes.c_int32), _p(mag))
+    return mag

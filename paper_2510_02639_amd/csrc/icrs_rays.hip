@@ -22,10 +22,12 @@ struct Num;
 template <>
 struct Num<double> {
   static constexpr double newton_tol = 1e-15;
+  static constexpr int newton_iter = 8;
 };
 template <>
 struct Num<float> {
   static constexpr float newton_tol = 1e-7f;
+  static constexpr int newton_iter = 6;
 };
 
 // f(delta) of App. A.2 (u1 > 0) or delta + 1/2 (uniform source, App. A.1)
@@ -46,14 +48,14 @@ __device__ inline T crossing_t(T d0, T d1, T d2, T d3, bool cubic, T rho) {
   T t = (den == T(0)) ? T(0.5) : (rho - d1) / den;
   t = fmin(fmax(t, T(0)), T(1));
   if (!cubic) return t;
-  const T c0 = d1;
+  const T c0 = d1 - rho;
   const T c1 = -d0 * T(1.0 / 3.0) - T(0.5) * d1 + d2 - d3 * T(1.0 / 6.0);
   const T c2 = T(0.5) * d0 - d1 + T(0.5) * d2;
   const T c3 = (d3 - d0) * T(1.0 / 6.0) + T(0.5) * (d1 - d2);
-  const bool in0 = (d1 - rho) < T(0);
+  const bool in0 = c0 < T(0);
   T a = T(0), b = T(1);
-  for (int it = 0; it < 16; ++it) {
-    const T g = ((c3 * t + c2) * t + c1) * t + c0 - rho;
+  for (int it = 0; it < Num<T>::newton_iter; ++it) {
+    const T g = ((c3 * t + c2) * t + c1) * t + c0;
     if (g == T(0)) break;
     if ((g < T(0)) == in0)
       a = t;
@@ -77,11 +79,24 @@ __device__ __forceinline__ double sqrt_fast(double c) {
 }
 __device__ __forceinline__ float sqrt_fast(float c) { return __builtin_amdgcn_sqrtf(c); }
 
-// Node maps.  MapF64 evaluates eq. lens_eq directly in FP64.  MapF32 works relative to an
-// FP64 anchor z_a = r_i e^{i theta_a} on each row: with dz = z - z_a = r_i e^{i theta_a}
-// (e^{i dtheta_l} - 1), u_k = z - a_k and h_k = eps_k / (z_a - a_k),
-//   w - w_c = (w(z_a) - w_c) + dz + sum_k conj(dz h_k / u_k),
-// an identity with no cancellation, so FP32 rounding scales with |dz| instead of |z|.
+// e^{i x} - 1 without cancellation: (-2 sin^2(x/2), sin x)
+__device__ __forceinline__ c64 expm1_i(double x) {
+  double s, c;
+  sincos(0.5 * x, &s, &c);
+  return mk(-2.0 * s * s, 2.0 * s * c);
+}
+
+// Node maps.  Column phases come from one sincos per lane and a rotation recurrence
+// across the lane's columns (64 apart).
+//
+// MapF64 evaluates eq. lens_eq directly in FP64.
+//
+// MapF32 works relative to the sector's FP64 anchor z_s = r_s e^{i theta_s} (box centre):
+// with dz = z - z_s = r e^{i theta_s}(e^{i dtheta} - 1) + (r - r_s) e^{i theta_s},
+// u_k = z - a_k and h_k = eps_k/(z_s - a_k),
+//   w - w_c = (w(z_s) - w_c) + dz + sum_k conj(dz h_k / u_k),
+// an identity with no cancellation, so FP32 rounding scales with |dz| (the sector's size)
+// instead of |z|.
 template <int N, int JMAX>
 struct MapF64 {
   using T = double;
@@ -89,14 +104,26 @@ struct MapF64 {
   Lens<N> L;
   c64 wc;
   double r;
-  __device__ void init_sector(const Lens<N>& lens, c64 w_c, double th_lo, double dth, double th_a, int lane) {
+  __device__ void init_sector(const Lens<N>& lens, c64 w_c, const double* sp, int n_r, int n_theta, int lane) {
     L = lens;
     wc = w_c;
-    (void)th_a;
+    (void)n_r;
+    const double dth = (sp[3] - sp[2]) / n_theta;
+    double s0, c0;
+    sincos(sp[2] + (lane + 0.5) * dth, &s0, &c0);
+    const c64 rot = expm1_i(64.0 * dth);  // e^{i 64 dtheta} - 1
+    c64 e = mk(c0, s0);
 #pragma unroll
-    for (int j = 0; j < JMAX; ++j) sincos(th_lo + (lane + 64 * j + 0.5) * dth, &sn[j], &cs[j]);
+    for (int j = 0; j < JMAX; ++j) {
+      cs[j] = e.x;
+      sn[j] = e.y;
+      e = e + e * rot;
+    }
   }
-  __device__ void init_row(double r_i) { r = r_i; }
+  __device__ void init_row(double r_i, double dr_i) {
+    (void)dr_i;
+    r = r_i;
+  }
   __device__ __forceinline__ double d2(int j) const {
     const double x = r * cs[j], y = r * sn[j];
     double wx = x - wc.x, wy = y - wc.y;
@@ -114,29 +141,19 @@ struct MapF64 {
 template <int N, int JMAX>
 struct MapF32 {
   using T = float;
-  float gx[JMAX], gy[JMAX];  // e^{i theta_a} (e^{i dtheta_l} - 1) per owned column
-  Lens<N> L;
-  c64 wc;
-  double ca, sa;             // e^{i theta_a}
-  float r, bx, by;           // row: r_i, w(z_a) - w_c
+  float gx[JMAX], gy[JMAX];  // e^{i theta_s} (e^{i dtheta_l} - 1) per owned column
+  float ux0, uy0;            // e^{i theta_s}
+  float bx, by;              // w(z_s) - w_c
   float ax[N], ay[N], hx[N], hy[N];
-  __device__ void init_sector(const Lens<N>& lens, c64 w_c, double th_lo, double dth, double th_a, int lane) {
-    L = lens;
-    wc = w_c;
-    sincos(th_a, &sa, &ca);
-#pragma unroll
-    for (int j = 0; j < JMAX; ++j) {
-      const double dt = th_lo + (lane + 64 * j + 0.5) * dth - th_a;
-      double sd, cd;
-      sincos(dt, &sd, &cd);
-      const double sh = sin(0.5 * dt);
-      const double ex = -2.0 * sh * sh, ey = sd;  // e^{i dt} - 1 without cancellation
-      gx[j] = (float)(ca * ex - sa * ey);
-      gy[j] = (float)(ca * ey + sa * ex);
-    }
-  }
-  __device__ void init_row(double r_i) {
-    const double zx = r_i * ca, zy = r_i * sa;
+  float r, ex, ey;           // row: r_i, (r_i - r_s) e^{i theta_s}
+  __device__ void init_sector(const Lens<N>& L, c64 wc, const double* sp, int n_r, int n_theta, int lane) {
+    (void)n_r;
+    const double r_s = 0.5 * (sp[0] + sp[1]);
+    const double th_s = 0.5 * (sp[2] + sp[3]);
+    const double dth = (sp[3] - sp[2]) / n_theta;
+    double sa, ca;
+    sincos(th_s, &sa, &ca);
+    const double zx = r_s * ca, zy = r_s * sa;
     double wx = zx - wc.x, wy = zy - wc.y;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
@@ -149,12 +166,27 @@ struct MapF32 {
       hx[k] = (float)(s * dx);
       hy[k] = (float)(-s * dy);
     }
-    r = (float)r_i;
     bx = (float)wx;
     by = (float)wy;
+    ux0 = (float)ca;
+    uy0 = (float)sa;
+    // E_j = e^{i dt_j} - 1 with dt_j = (l + 1/2 - N_theta/2) dtheta, l = lane + 64 j
+    const c64 f = expm1_i(64.0 * dth);
+    c64 e = expm1_i((lane + 0.5 - 0.5 * n_theta) * dth);
+#pragma unroll
+    for (int j = 0; j < JMAX; ++j) {
+      gx[j] = (float)(ca * e.x - sa * e.y);
+      gy[j] = (float)(ca * e.y + sa * e.x);
+      e = e + f + e * f;
+    }
+  }
+  __device__ void init_row(double r_i, double dr_i) {
+    r = (float)r_i;
+    ex = (float)dr_i * ux0;
+    ey = (float)dr_i * uy0;
   }
   __device__ __forceinline__ float d2(int j) const {
-    const float dzx = r * gx[j], dzy = r * gy[j];
+    const float dzx = fmaf(r, gx[j], ex), dzy = fmaf(r, gy[j], ey);
     float Dx = bx + dzx, Dy = by + dzy;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
@@ -171,14 +203,14 @@ struct MapF32 {
   }
 };
 
-// Rounding bound of the FP32 map on one sector, relative to rho: the per-row anchor keeps
-// |dz| <= 2 r_hi sin(half angular width / 2), and each lens term is at most
+// Rounding bound of the FP32 map on one sector, relative to rho: |dz| is at most the chord
+// of the half angular width plus half the radial extent, and each lens term is at most
 // eps_k |dz| / dist_k^2 with dist_k a lower bound of the lens' distance to the sector box.
 template <int N>
 __device__ inline double fp32_error_bound(const Lens<N>& L, const double* sp, bool per, double rho) {
   const double r_lo = sp[0], r_hi = sp[1], th_lo = sp[2], th_hi = sp[3];
   const double half = per ? kPi : 0.5 * (th_hi - th_lo);
-  const double dz = 2.0 * r_hi * sin(0.5 * fmin(half, kPi));
+  const double dz = 2.0 * r_hi * sin(0.5 * fmin(half, kPi)) + 0.5 * (r_hi - r_lo);
   double amp = 1.0;
 #pragma unroll
   for (int k = 0; k < N; ++k) {
@@ -197,37 +229,49 @@ __device__ inline double fp32_error_bound(const Lens<N>& L, const double* sp, bo
 }
 constexpr double kFp32Budget = 6e-5;  // per-node distance error (relative to rho) allowed in FP32
 
-__device__ __forceinline__ int bit_of(uint64_t m, int b) { return (int)((m >> b) & 1ull); }
-
 template <typename T>
 __device__ __forceinline__ T brightness(T d2, T inv_rho2, T i_lin, T i_sqrt) {
   const T c = fmax(fma(-d2, inv_rho2, T(1)), T(0));
   return fma(i_sqrt, sqrt_fast(c), i_lin);  // I0 (1 - u1) + I0 u1 sqrt(1 - d^2/rho^2)
 }
 
+// Wave-uniform boundary words of chunk j: inside nodes whose left (side 0) or right
+// (side 1) neighbour is outside or beyond a non-periodic edge.
+template <int JMAX>
+__device__ __forceinline__ uint64_t boundary_word(const uint64_t (&m)[JMAX], int j, int J, int side, bool per,
+                                                  uint64_t in_last, int jl, int bl) {
+  if (side == 0) {
+    const uint64_t carry = (j > 0) ? (m[j > 0 ? j - 1 : 0] >> 63) : (per ? in_last : 0ull);
+    return m[j] & ~((m[j] << 1) | carry);
+  }
+  uint64_t right = (m[j] >> 1) | ((j + 1 < J) ? (m[j + 1 < JMAX ? j + 1 : j] << 63) : 0ull);
+  if (j == jl && per) right |= (m[0] & 1ull) << bl;
+  return m[j] & ~right;
+}
+
 // One (epoch, sector) grid shot by the whole workgroup; the flux and clip bits end up in
-// thread 0.
-template <int N, int JMAX, typename MAP>
+// thread 0.  EXACT: n_theta == 64 * JMAX (no partial column chunk).
+template <int N, int JMAX, bool EXACT, typename MAP>
 __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L, c64 wc, double rho_d, double u1_d,
                                     double delta_c_d, int n_r, int n_theta, typename MAP::T* rowbuf_all,
                                     double* wsum, int* wclip, double* flux_out, int* clip_out_bits) {
   using T = typename MAP::T;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const double r_lo = sp[0], r_hi = sp[1], th_lo = sp[2], th_hi = sp[3];
+  const double r_lo = sp[0], r_hi = sp[1];
   const T rho = (T)rho_d, u1 = (T)u1_d, delta_c = (T)delta_c_d;
   const T rho2 = (T)(rho_d * rho_d), inv_rho2 = (T)(1.0 / (rho_d * rho_d));
   const double I0d = 3.0 / (kPi * (3.0 - u1_d));
   const T i_lin = (T)(I0d * (1.0 - u1_d)), i_sqrt = (T)(I0d * u1_d);
-  const int J = (n_theta + 63) >> 6;
+  const int J = EXACT ? JMAX : (n_theta + 63) >> 6;
   const double dr = (r_hi - r_lo) / n_r;
-  const double dth = (th_hi - th_lo) / n_theta;
+  const double dth = (sp[3] - sp[2]) / n_theta;
   const T f_edge = edge_factor<T>(T(0.5), u1, delta_c) - T(1);  // neighbour beyond a sector edge
   const int last = n_theta - 1;
   const int jl = last >> 6, bl = last & 63;
 
   MAP map;
-  map.init_sector(L, wc, th_lo, dth, 0.5 * (th_lo + th_hi), lane);
+  map.init_sector(L, wc, sp, n_r, n_theta, lane);
 
   double acc = 0.0;
   int clip = 0;
@@ -235,22 +279,21 @@ __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L
 
   for (int i = wave; i < n_r; i += kWaves) {
     const double r = r_lo + (i + 0.5) * dr;
-    map.init_row(r);
+    map.init_row(r, (i + 0.5 - 0.5 * n_r) * dr);
     uint64_t m[JMAX];
     uint64_t any = 0;
     T row = T(0);
 #pragma unroll
     for (int j = 0; j < JMAX; ++j) {
       m[j] = 0;
-      if (j < J) {
-        const int l = lane + 64 * j;
-        const T d2 = (l < n_theta) ? map.d2(j) : T(__builtin_inf());
+      if (EXACT || j < J) {
+        T d2 = map.d2(j);
+        if (!EXACT) d2 = (lane + 64 * j < n_theta) ? d2 : T(__builtin_inf());
         const bool in = d2 < rho2;
         m[j] = __ballot(in);
         any |= m[j];
-        if (l < n_theta) buf[l] = d2;
-        const T I = brightness<T>(d2, inv_rho2, i_lin, i_sqrt);
-        row += in ? I : T(0);
+        if (EXACT || lane + 64 * j < n_theta) buf[lane + 64 * j] = d2;
+        if (m[j]) row += in ? brightness<T>(d2, inv_rho2, i_lin, i_sqrt) : T(0);
       }
     }
     if (any == 0) continue;  // wave-uniform: the row misses the image
@@ -265,76 +308,56 @@ __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L
       if (m[0] & 1ull) clip |= 4;
       if (in_last) clip |= 8;
     }
-    // boundary masks (wave-uniform): inside nodes whose left / right neighbour is outside
-    // or beyond a non-periodic edge
-    uint64_t bnd[JMAX], bL[JMAX], bR[JMAX];
-    int nb = 0;
+    int n_left = 0, n_all = 0;
 #pragma unroll
     for (int j = 0; j < JMAX; ++j) {
-      bnd[j] = 0;
-      bL[j] = 0;
-      bR[j] = 0;
-      if (j < J) {
-        const uint64_t carry_l = (j > 0) ? (m[j > 0 ? j - 1 : 0] >> 63) : (per ? in_last : 0ull);
-        const uint64_t left = (m[j] << 1) | carry_l;
-        uint64_t right = (m[j] >> 1) | ((j + 1 < J) ? (m[j + 1 < JMAX ? j + 1 : j] << 63) : 0ull);
-        if (j == jl && per) right |= (m[0] & 1ull) << bl;
-        bL[j] = m[j] & ~left;
-        bR[j] = m[j] & ~right;
-        bnd[j] = bL[j] | bR[j];
-        nb += __popcll(bnd[j]);
+      if (EXACT || j < J) {
+        n_left += __popcll(boundary_word<JMAX>(m, j, J, 0, per, in_last, jl, bl));
+        n_all += __popcll(boundary_word<JMAX>(m, j, J, 1, per, in_last, jl, bl));
       }
     }
+    n_all += n_left;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // one boundary node per lane
-    for (int base = 0; base < nb; base += 64) {
+    // one crossing (node, side) per lane
+    for (int base = 0; base < n_all; base += 64) {
       const int k = base + lane;
-      if (k < nb) {
-        int rem = k, l = 0;
-        bool has_l = false, has_r = false;
+      if (k < n_all) {
+        const int side = k >= n_left ? 1 : 0;
+        int rem = side ? k - n_left : k;
+        uint64_t word = 0;
+        int jw = 0;
 #pragma unroll
         for (int j = 0; j < JMAX; ++j) {
-          const int pc = __popcll(bnd[j]);
-          if (rem >= 0 && rem < pc) {
-            uint64_t word = bnd[j];
-            for (int q = 0; q < rem; ++q) word &= word - 1ull;
-            const int bpos = __ffsll((unsigned long long)word) - 1;
-            l = 64 * j + bpos;
-            has_l = (bL[j] >> bpos) & 1ull;
-            has_r = (bR[j] >> bpos) & 1ull;
-          }
-          rem -= pc;
-        }
-        T corr = T(0);
-        if (has_l) {
-          if (l == 0 && !per) {
-            corr += f_edge;
-          } else {  // crossing in (theta_{l-1}, theta_l): bracket p = l-1
-            const int pp = l == 0 ? last : l - 1;
-            const bool cubic = per || (l - 2 >= 0 && l + 1 <= last);
-            const int im1 = per ? (pp - 1 + n_theta) % n_theta : max(pp - 1, 0);
-            const int ip2 = per ? (pp + 2) % n_theta : min(pp + 2, last);
-            const int ip1 = (pp + 1) % n_theta;
-            const T t =
-                crossing_t<T>(sqrt(buf[im1]), sqrt(buf[pp]), sqrt(buf[ip1]), sqrt(buf[ip2]), cubic, rho);
-            corr += edge_factor<T>(T(1) - t, u1, delta_c) - T(1);
+          if (EXACT || j < J) {
+            const uint64_t w0 = boundary_word<JMAX>(m, j, J, 0, per, in_last, jl, bl);
+            const uint64_t w1 = boundary_word<JMAX>(m, j, J, 1, per, in_last, jl, bl);
+            const uint64_t wd = side ? w1 : w0;
+            const int pc = __popcll(wd);
+            if (rem >= 0 && rem < pc) {
+              word = wd;
+              jw = j;
+            }
+            if (rem >= 0) rem -= (rem < pc) ? (1 << 30) : pc;
           }
         }
-        if (has_r) {
-          if (l == last && !per) {
-            corr += f_edge;
-          } else {  // crossing in (theta_l, theta_{l+1}): bracket p = l
-            const int pp = l;
-            const bool cubic = per || (l - 1 >= 0 && l + 2 <= last);
-            const int im1 = per ? (pp - 1 + n_theta) % n_theta : max(pp - 1, 0);
-            const int ip2 = per ? (pp + 2) % n_theta : min(pp + 2, last);
-            const int ip1 = (pp + 1) % n_theta;
-            const T t =
-                crossing_t<T>(sqrt(buf[im1]), sqrt(buf[pp]), sqrt(buf[ip1]), sqrt(buf[ip2]), cubic, rho);
-            corr += edge_factor<T>(t, u1, delta_c) - T(1);
-          }
+        rem += 1 << 30;  // rank of the node inside its word (< 64 whenever k < n_all)
+        for (int q = 0; q < rem && q < 64; ++q) word &= word - 1ull;
+        const int l = 64 * jw + __ffsll((unsigned long long)word) - 1;
+        T corr;
+        if ((side == 0 && l == 0 && !per) || (side == 1 && l == last && !per)) {
+          corr = f_edge;
+        } else {
+          // side 0: crossing in (theta_{l-1}, theta_l), bracket p = l-1, delta = 1 - t
+          // side 1: crossing in (theta_l, theta_{l+1}), bracket p = l,   delta = t
+          const int pp = side ? l : (l == 0 ? last : l - 1);
+          const bool cubic = per || (pp - 1 >= 0 && pp + 2 <= last);
+          const int im1 = per ? (pp - 1 + n_theta) % n_theta : max(pp - 1, 0);
+          const int ip2 = per ? (pp + 2) % n_theta : min(pp + 2, last);
+          const int ip1 = (pp + 1) % n_theta;
+          const T t = crossing_t<T>(sqrt(buf[im1]), sqrt(buf[pp]), sqrt(buf[ip1]), sqrt(buf[ip2]), cubic, rho);
+          corr = edge_factor<T>(side ? t : T(1) - t, u1, delta_c) - T(1);
         }
         row += brightness<T>(buf[l], inv_rho2, i_lin, i_sqrt) * corr;
       }
@@ -369,7 +392,7 @@ __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L
 // of epoch w.list[k] (or k).  An FP32 pass sends sectors whose rounding bound exceeds the
 // budget to w.fallback for the FP64 pass.  Every workgroup leaves once the counter has
 // passed the end.
-template <int N, int JMAX, typename MAP>
+template <int N, int JMAX, bool EXACT, typename MAP>
 __global__ __launch_bounds__(256) void rays_kernel(Batch b, SectorBuf sec, RayWork w, int n_r, int n_theta,
                                                    double delta_c, double* __restrict__ partial,
                                                    uint8_t* __restrict__ clip_out,
@@ -420,7 +443,8 @@ __global__ __launch_bounds__(256) void rays_kernel(Batch b, SectorBuf sec, RayWo
       }
       double flux = 0.0;
       int c = 0;
-      shoot_sector<N, JMAX, MAP>(sp, per, L, wc, p[6], p[7], delta_c, n_r, n_theta, rowbuf, wsum, wclip, &flux, &c);
+      shoot_sector<N, JMAX, EXACT, MAP>(sp, per, L, wc, p[6], p[7], delta_c, n_r, n_theta, rowbuf, wsum, wclip, &flux,
+                                        &c);
       if (threadIdx.x == 0) {
         partial[e * kMaxSectors + slot] = flux;
         clip_out[e * kMaxSectors + slot] = (uint8_t)c;
@@ -480,10 +504,10 @@ __global__ void finalize_kernel(Batch b, SectorBuf sec, RayWork w, const double*
   status[e] = st;
 }
 
-template <int N, int JMAX, template <int, int> class MAP>
+template <int N, int JMAX, bool EXACT, template <int, int> class MAP>
 hipError_t launch_rays_j(const Batch& b, const SectorBuf& sec, const RayWork& w, int n_r, int n_theta,
                          double delta_c, double* partial, uint8_t* clip, unsigned long long* queue, hipStream_t s) {
-  auto kern = rays_kernel<N, JMAX, MAP<N, JMAX>>;
+  auto kern = rays_kernel<N, JMAX, EXACT, MAP<N, JMAX>>;
   int dev = 0, cus = 0, per_cu = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -503,9 +527,17 @@ template <int N, template <int, int> class MAP>
 hipError_t launch_rays_n(const Batch& b, const SectorBuf& sec, const RayWork& w, int n_r, int n_theta,
                          double delta_c, double* partial, uint8_t* clip, unsigned long long* queue, hipStream_t s) {
   const int J = (n_theta + 63) / 64;
-  if (J <= 4) return launch_rays_j<N, 4, MAP>(b, sec, w, n_r, n_theta, delta_c, partial, clip, queue, s);
-  if (J <= 8) return launch_rays_j<N, 8, MAP>(b, sec, w, n_r, n_theta, delta_c, partial, clip, queue, s);
-  if (J <= 16) return launch_rays_j<N, 16, MAP>(b, sec, w, n_r, n_theta, delta_c, partial, clip, queue, s);
+  const bool exact = (n_theta % 64) == 0;
+#define ICRS_RAYS_J(JJ)                                                                                   \
+  if (J <= JJ) {                                                                                          \
+    if (exact && J == JJ)                                                                                 \
+      return launch_rays_j<N, JJ, true, MAP>(b, sec, w, n_r, n_theta, delta_c, partial, clip, queue, s);  \
+    return launch_rays_j<N, JJ, false, MAP>(b, sec, w, n_r, n_theta, delta_c, partial, clip, queue, s);   \
+  }
+  ICRS_RAYS_J(4)
+  ICRS_RAYS_J(8)
+  ICRS_RAYS_J(16)
+#undef ICRS_RAYS_J
   return hipErrorInvalidValue;
 }
 

@@ -371,3 +371,62 @@ def test_sectors_overlap_merge_and_cap():
     sec, _, st = O.build_sectors(np.full(th.size, 1.0), th, rho, 5)
     assert sec.shape[0] == 5 and st & O.ST_CAP_OVERFLOW
     assert np.all(np.diff(sec[:, 2]) >= 0)
+
+
+# --- O13: frozen-structure gradients ---------------------------------------------------
+
+def _fd_rel_err(n_lens, p, t, r, k, h):
+    pp, pm = p.copy(), p.copy()
+    pp[k] += h
+    pm[k] -= h
+    args = (t, r["sectors"], r["periodic"], r["nsec"])
+    fd = (O.magnification_frozen(n_lens, pp, p, *args) - O.magnification_frozen(n_lens, pm, p, *args)) / (2 * h)
+    return fd
+
+
+@pytest.mark.parametrize("u1,hs,tol", [(0.5, 1e-9, 3e-5), (0.0, 1e-7, 3e-5)])
+def test_dual_jacobian_matches_frozen_central_differences(u1, hs, tol):
+    """The dual-number Jacobian is the derivative of the frozen-structure primal: central
+    differences of that primal converge to it as the step shrinks (limb-darkened sources
+    need tiny steps: nodes just inside the limb have sqrt(1 - x^2) brightness)."""
+    p = O.params(s=0.9, q=0.1, u0=0.05, alpha=0.6, t0=0, tE=20, rho=1e-2, u1=u1)
+    t = np.array([-3.0, 0.0, 16.5, 25.0])
+    r = O.magnification(2, p, t)
+    mag, jac = O.jacobian_given(2, p, t, r["sectors"], r["periodic"], r["nsec"])
+    assert np.allclose(mag, r["mag"], rtol=1e-13, atol=0)
+    for k in range(8 if u1 > 0 else 7):
+        h = hs * abs(p[k]) if k in (0, 1, 6) else hs * max(abs(p[k]), 1.0)
+        fd = _fd_rel_err(2, p, t, r, k, h)
+        scale = np.abs(jac[:, k]).max()
+        assert np.max(np.abs(jac[:, k] - fd)) <= tol * scale, (k, np.max(np.abs(jac[:, k] - fd)) / scale)
+
+
+def test_triple_jacobian_matches_frozen_central_differences():
+    p = O.params(s=1.1, q=0.5, u0=0.02, alpha=np.radians(60), t0=0, tE=10, rho=0.02, u1=0.0, q3=0.03, r3=1.24,
+                 psi=np.radians(76))
+    t = np.array([-1.0, 0.3])
+    r = O.magnification(3, p, t, n_r=48, n_theta=192)
+    mag, jac = O.jacobian_given(3, p, t, r["sectors"], r["periodic"], r["nsec"], n_r=48, n_theta=192)
+    for k in [0, 1, 2, 3, 4, 5, 6, 8, 9, 10]:
+        h = 1e-8 * (abs(p[k]) if k in (0, 1, 6, 8, 9) else max(abs(p[k]), 1.0))
+        pp, pm = p.copy(), p.copy()
+        pp[k] += h
+        pm[k] -= h
+        args = (t, r["sectors"], r["periodic"], r["nsec"], 48, 192)
+        fd = (O.magnification_frozen(3, pp, p, *args) - O.magnification_frozen(3, pm, p, *args)) / (2 * h)
+        assert np.max(np.abs(jac[:, k] - fd)) <= 3e-5 * np.abs(jac[:, k]).max(), k
+
+
+def test_frozen_gradient_normalisation_term():
+    """Identity map: A = flux/rho^2 with the source disk's own flux; with chi frozen the
+    rho-derivative is the normalisation -2A/rho plus the boundary and brightness terms,
+    and for the uniform rule the magnification is 1 for every rho, so dA/drho -> 0 as the
+    grid refines."""
+    p = O.params(u0=0.8, alpha=0.3, t0=0.0, tE=10.0, rho=0.05, u1=0.0)
+    t = np.array([0.0])
+    vals = []
+    for nr, nth in [(64, 256), (256, 1024)]:
+        r = O.magnification(0, p, t, n_r=nr, n_theta=nth)
+        mag, jac = O.jacobian_given(0, p, t, r["sectors"], r["periodic"], r["nsec"], n_r=nr, n_theta=nth)
+        vals.append(abs(jac[0, 6]) * p[6] / mag[0])
+    assert vals[1] < vals[0] and vals[1] < 2e-2
