@@ -109,6 +109,20 @@ icrs_status icrs_magnification(icrs_handle* h, int64_t n_events, const double* p
                                double* mag, uint32_t* status, void* workspace,
                                size_t workspace_bytes);
 
+/* The plain path split for stream capture (hipGraph) and repeated runs over one batch:
+ * icrs_prepare() checks and uploads the events (host arrays as for icrs_magnification)
+ * into the workspace and records the batch in the handle; icrs_run() then enqueues the whole
+ * path on the handle's stream with no host synchronisation and no host-memory access, so it
+ * can be captured into a graph and replayed.  Every clip-retry pass is enqueued; its work
+ * list size is read on the device, and an empty pass ends at once.  t, mag, status as for
+ * icrs_magnification (n_epochs given to icrs_prepare()); workspace must be the one passed
+ * to icrs_prepare().  Profiling does not apply to icrs_run(). */
+icrs_status icrs_prepare(icrs_handle* h, int64_t n_events, const double* params,
+                         const int64_t* epoch_offsets, int64_t n_epochs, void* workspace,
+                         size_t workspace_bytes);
+icrs_status icrs_run(icrs_handle* h, const double* t, double* mag, uint32_t* status,
+                     void* workspace, size_t workspace_bytes);
+
 /* The same quadrature on caller-given sectors: one pass, no retries (status gets
  * ICRS_ST_GIVEN, plus ICRS_ST_CLIP if inside rays touch an edge).  sectors: DEVICE
  * [n_epochs][ICRS_MAX_SECTORS][4] doubles (r_lo, r_hi, theta_lo, theta_hi) with
@@ -121,6 +135,24 @@ icrs_status icrs_magnification_given(icrs_handle* h, int64_t n_events, const dou
                                      const uint8_t* periodic, const int32_t* n_sectors,
                                      double* mag, uint32_t* status, void* workspace,
                                      size_t workspace_bytes);
+
+/* Derivatives of the magnification on a frozen structure (the adjoint of the plain path):
+ * the caller-given sectors (normally those icrs_get_sectors() returns after
+ * icrs_magnification()), and the inside/outside pattern, crossing stencils and edge-factor
+ * branches of the primal evaluation on them, are held fixed; the rays are recomputed in FP64
+ * and differentiated exactly (crossings by implicit differentiation of the cubic
+ * interpolant, App. A).  This replaces the paper's forward-mode AD (Sec. 3.5), which needs
+ * a sigmoid surrogate for chi and cannot run in reverse mode (Sec. 6).
+ * Inputs as icrs_magnification_given(); cotangent: DEVICE [n_epochs] (may be NULL when grad
+ * is NULL).  Outputs (DEVICE, any may be NULL but not all): grad [n_events][ICRS_N_PARAMS]
+ * = sum over the event's epochs of cotangent[e] * dA_e/dparams; jac [n_epochs][ICRS_N_PARAMS]
+ * = dA_e/dparams; mag [n_epochs] = A_e.  Parameter order as in params; entries that do not
+ * apply (q3, r3, psi for binaries) are 0.  n_theta must be <= 1024. */
+icrs_status icrs_magnification_vjp(icrs_handle* h, int64_t n_events, const double* params,
+                                   const int64_t* epoch_offsets, int64_t n_epochs, const double* t,
+                                   const double* sectors, const uint8_t* periodic,
+                                   const int32_t* n_sectors, const double* cotangent, double* grad,
+                                   double* jac, double* mag, void* workspace, size_t workspace_bytes);
 
 /* Copy the final sectors of the last icrs_magnification() on this workspace into DEVICE
  * arrays laid out as in icrs_magnification_given(). */

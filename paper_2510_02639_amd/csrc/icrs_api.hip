@@ -14,6 +14,8 @@ struct icrs_handle {
   int profiling;
   hipEvent_t ev[16];
   icrs_profile prof;
+  int64_t prep_events, prep_epochs;  // batch uploaded by icrs_prepare()
+  const void* prep_ws;
 };
 
 namespace {
@@ -26,7 +28,8 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
-  size_t params, offsets, epoch_event, sectors, periodic, nsec, partial, clip, list_a, list_b, fallback, counters, total;
+  size_t params, offsets, epoch_event, sectors, periodic, nsec, partial, clip, list_a, list_b, fallback, jac, counters,
+      total;
 };
 
 Layout layout_for(int64_t n_events, int64_t n_epochs) {
@@ -48,6 +51,7 @@ Layout layout_for(int64_t n_events, int64_t n_epochs) {
   L.list_a = take(E * sizeof(int32_t));
   L.list_b = take(E * sizeof(int32_t));
   L.fallback = take(E * ICRS_MAX_SECTORS * sizeof(int32_t));
+  L.jac = take(E * ICRS_N_PARAMS * sizeof(double));
   L.counters = take(64);
   L.params = take(V * ICRS_N_PARAMS * sizeof(double));
   L.offsets = take((V + 1) * sizeof(int64_t));
@@ -140,6 +144,7 @@ struct Views {
   int32_t* list_a;
   int32_t* list_b;
   int32_t* fallback;
+  double* jac;
   int32_t* counters;   // [0] retry count, [4] FP64 fallback count, [8..9] int64 sector passes,
                        // [12..13] int64 work queue
 };
@@ -164,6 +169,7 @@ icrs_status prepare(icrs_handle* h, int64_t n_events, const double* params, cons
   v->list_a = (int32_t*)(base + L.list_a);
   v->list_b = (int32_t*)(base + L.list_b);
   v->fallback = (int32_t*)(base + L.fallback);
+  v->jac = (double*)(base + L.jac);
   v->counters = (int32_t*)(base + L.counters);
   if (n_events == 0) return ICRS_OK;
   ICRS_TRY(hipMemcpyAsync(base + L.params, params, (size_t)n_events * ICRS_N_PARAMS * sizeof(double),
@@ -221,6 +227,34 @@ icrs_status run_rays(icrs_handle* h, const Views& v, int max_retries, double* ma
   return ICRS_OK;
 }
 
+// The whole plain path with no host synchronisation: every retry pass is launched and
+// finds its work list size on the device (an empty pass ends at once).
+icrs_status run_plain_device(icrs_handle* h, const Views& v, double* mag, uint32_t* status) {
+  const icrs_config& c = h->cfg;
+  const int fp32_roots = c.root_precision == ICRS_FP32;
+  ICRS_TRY(icrs::launch_centre_images(c.n_lens, fp32_roots, v.b, nullptr, nullptr, nullptr, status, h->stream));
+  ICRS_TRY(icrs::launch_limb_sectors(c.n_lens, fp32_roots, c.n_limb, v.b, v.sec, status, h->stream));
+  RayWork w;
+  w.n = v.b.n_epochs;
+  int32_t* lists[2] = {v.list_a, v.list_b};
+  int32_t* counts[2] = {v.counters + 0, v.counters + 1};
+  for (int attempt = 0; attempt <= c.max_retries; ++attempt) {
+    ICRS_TRY(icrs::launch_rays(c.n_lens, c.ray_precision, v.b, v.sec, w, c.n_r, c.n_theta, c.delta_c, v.partial,
+                               v.clip, (unsigned long long*)(v.counters + 12), v.fallback, v.counters + 4,
+                               h->stream));
+    int32_t* nxt = lists[attempt & 1];
+    int32_t* ncount = counts[attempt & 1];
+    ICRS_TRY(icrs::launch_fill_i32(ncount, 1, 0, h->stream));
+    ICRS_TRY(icrs::launch_finalize(v.b, v.sec, w, v.partial, v.clip, attempt, c.max_retries, nxt, ncount, mag,
+                                   status, 0u, nullptr, h->stream));
+    w = RayWork{};
+    w.list = nxt;
+    w.n = v.b.n_epochs;
+    w.n_dev = ncount;
+  }
+  return ICRS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -247,6 +281,8 @@ icrs_status icrs_create(const icrs_config* cfg, void* hip_stream, icrs_handle** 
   h->stream = (hipStream_t)hip_stream;
   h->profiling = 0;
   memset(&h->prof, 0, sizeof(h->prof));
+  h->prep_events = h->prep_epochs = 0;
+  h->prep_ws = nullptr;
   for (auto& e : h->ev) e = nullptr;
   *out = h;
   return ICRS_OK;
@@ -301,6 +337,46 @@ icrs_status icrs_magnification(icrs_handle* h, int64_t n_events, const double* p
   return run_rays(h, v, c.max_retries, mag, status, 0u);
 }
 
+icrs_status icrs_prepare(icrs_handle* h, int64_t n_events, const double* params, const int64_t* epoch_offsets,
+                         int64_t n_epochs, void* workspace, size_t workspace_bytes) {
+  if (!h || !events_ok(h->cfg, n_events, params, epoch_offsets, n_epochs)) return ICRS_EINVAL;
+  Views v;
+  const icrs_status ps = prepare(h, n_events, params, epoch_offsets, n_epochs, nullptr, workspace, workspace_bytes, &v);
+  if (ps != ICRS_OK) return ps;
+  h->prep_events = n_events;
+  h->prep_epochs = n_epochs;
+  h->prep_ws = workspace;
+  return ICRS_OK;
+}
+
+icrs_status icrs_run(icrs_handle* h, const double* t, double* mag, uint32_t* status, void* workspace,
+                     size_t workspace_bytes) {
+  if (!h || !workspace || workspace != h->prep_ws) return ICRS_EINVAL;
+  if (h->prep_epochs > 0 && (!t || !mag || !status)) return ICRS_EINVAL;
+  const Layout L = layout_for(h->prep_events, h->prep_epochs);
+  if (workspace_bytes < L.total) return ICRS_ENOMEM;
+  if (h->prep_epochs == 0) return ICRS_OK;
+  char* base = (char*)workspace;
+  Views v;
+  v.b.params = (const double*)(base + L.params);
+  v.b.offsets = (const int64_t*)(base + L.offsets);
+  v.b.epoch_event = (const int32_t*)(base + L.epoch_event);
+  v.b.t = t;
+  v.b.n_events = h->prep_events;
+  v.b.n_epochs = h->prep_epochs;
+  v.sec.sectors = (double*)(base + L.sectors);
+  v.sec.periodic = (uint8_t*)(base + L.periodic);
+  v.sec.nsec = (int32_t*)(base + L.nsec);
+  v.partial = (double*)(base + L.partial);
+  v.clip = (uint8_t*)(base + L.clip);
+  v.list_a = (int32_t*)(base + L.list_a);
+  v.list_b = (int32_t*)(base + L.list_b);
+  v.fallback = (int32_t*)(base + L.fallback);
+  v.jac = (double*)(base + L.jac);
+  v.counters = (int32_t*)(base + L.counters);
+  return run_plain_device(h, v, mag, status);
+}
+
 icrs_status icrs_magnification_given(icrs_handle* h, int64_t n_events, const double* params,
                                      const int64_t* epoch_offsets, int64_t n_epochs, const double* t,
                                      const double* sectors, const uint8_t* periodic, const int32_t* n_sectors,
@@ -317,6 +393,29 @@ icrs_status icrs_magnification_given(icrs_handle* h, int64_t n_events, const dou
   ICRS_TRY(hipMemcpyAsync(v.sec.nsec, n_sectors, E * sizeof(int32_t), hipMemcpyDeviceToDevice, h->stream));
   ICRS_TRY(icrs::launch_fill_u32(status, n_epochs, 0u, h->stream));
   return run_rays(h, v, 0, mag, status, ICRS_ST_GIVEN);
+}
+
+icrs_status icrs_magnification_vjp(icrs_handle* h, int64_t n_events, const double* params,
+                                   const int64_t* epoch_offsets, int64_t n_epochs, const double* t,
+                                   const double* sectors, const uint8_t* periodic, const int32_t* n_sectors,
+                                   const double* cotangent, double* grad, double* jac, double* mag, void* workspace,
+                                   size_t workspace_bytes) {
+  if (!h || !events_ok(h->cfg, n_events, params, epoch_offsets, n_epochs)) return ICRS_EINVAL;
+  if (n_epochs > 0 && (!t || !sectors || !periodic || !n_sectors)) return ICRS_EINVAL;
+  if ((grad && !cotangent) || (!grad && !jac && !mag)) return ICRS_EINVAL;
+  if (h->cfg.n_theta > 1024) return ICRS_EUNSUPPORTED;
+  Views v;
+  const icrs_status ps = prepare(h, n_events, params, epoch_offsets, n_epochs, t, workspace, workspace_bytes, &v);
+  if (ps != ICRS_OK || n_epochs == 0) return ps;
+  const size_t E = (size_t)n_epochs;
+  ICRS_TRY(hipMemcpyAsync(v.sec.sectors, sectors, E * ICRS_MAX_SECTORS * 4 * sizeof(double),
+                          hipMemcpyDeviceToDevice, h->stream));
+  ICRS_TRY(hipMemcpyAsync(v.sec.periodic, periodic, E * ICRS_MAX_SECTORS, hipMemcpyDeviceToDevice, h->stream));
+  ICRS_TRY(hipMemcpyAsync(v.sec.nsec, n_sectors, E * sizeof(int32_t), hipMemcpyDeviceToDevice, h->stream));
+  double* J = jac ? jac : v.jac;
+  return hip_status(icrs::launch_adjoint(h->cfg.n_lens, v.b, v.sec, h->cfg.n_r, h->cfg.n_theta, h->cfg.delta_c,
+                                         cotangent, J, grad, mag, (unsigned long long*)(v.counters + 12),
+                                         h->stream));
 }
 
 icrs_status icrs_get_sectors(icrs_handle* h, const void* workspace, int64_t n_epochs, double* sectors,

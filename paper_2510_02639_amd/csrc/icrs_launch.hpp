@@ -34,7 +34,8 @@ hipError_t launch_limb_sectors(int n_lens, int root_fp32, int n_limb, const Batc
 
 struct RayWork {
   const int32_t* list = nullptr;    // epochs to process (all their sectors), or nullptr = 0..n-1
-  int64_t n = 0;                    // number of epochs in the list
+  int64_t n = 0;                    // number of epochs in the list (an upper bound with n_dev)
+  const int32_t* n_dev = nullptr;   // device-side count of the list, when only the device knows it
   const int32_t* items = nullptr;   // instead: single sectors 16 e + slot, count in *n_items
   const int32_t* n_items = nullptr;
   int32_t* fallback = nullptr;      // FP32 pass: sectors sent to the FP64 pass
@@ -53,6 +54,12 @@ hipError_t launch_finalize(const Batch& b, const SectorBuf& sec, const RayWork& 
                            const uint8_t* clip, int attempt, int max_retries, int32_t* next_list,
                            int32_t* next_count, double* mag, uint32_t* status, uint32_t extra_status,
                            unsigned long long* passes, hipStream_t s);
+
+// frozen-structure Jacobian jac[n_epochs][11] (and mag if non-null) on the given sectors;
+// with cot and grad non-null also grad[n_events][11] = sum_e cot[e] jac[e]
+hipError_t launch_adjoint(int n_lens, const Batch& b, const SectorBuf& sec, int n_r, int n_theta, double delta_c,
+                          const double* cot, double* jac, double* grad, double* mag, unsigned long long* queue,
+                          hipStream_t s);
 
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);

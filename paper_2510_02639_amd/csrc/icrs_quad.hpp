@@ -1,0 +1,123 @@
+// icrs_quad.hpp -- row-quadrature pieces shared by the ray and adjoint kernels (App. A).
+#pragma once
+
+#include "icrs_device.hpp"
+
+namespace icrs {
+
+template <typename T>
+struct Num;
+// Crossing solver limits: the safeguarded Newton usually stops after 3-4 steps; the cap
+// only matters when steps leave the bracket and bisection takes over.
+template <>
+struct Num<double> {
+  static constexpr double newton_tol = 1e-12;
+  static constexpr int newton_iter = 16;
+};
+template <>
+struct Num<float> {
+  static constexpr float newton_tol = 1e-6f;
+  static constexpr int newton_iter = 12;
+};
+
+// f(delta) of App. A.2 (u1 > 0) or delta + 1/2 (uniform source, App. A.1)
+template <typename T>
+__device__ __forceinline__ T edge_factor(T delta, T u1, T delta_c) {
+  if (u1 == T(0)) return delta + T(0.5);
+  if (delta >= delta_c && delta > T(0)) return (T(0.5) + delta) * T(2.0 / 3.0) * sqrt(T(1) + T(1) / (T(2) * delta));
+  return T(2.0 / 3.0) * delta + T(0.5);
+}
+
+// Crossing of the cubic Lagrange interpolant through (t, d) = (-1,d0), (0,d1), (1,d2),
+// (2,d3) with rho on the bracket [0,1] (d1, d2 on opposite sides of rho); linear between
+// d1 and d2 when cubic is false.  Safeguarded Newton from the linear estimate: the bracket
+// shrinks on every step and a step leaving it is replaced by bisection.
+template <typename T>
+__device__ inline T crossing_t(T d0, T d1, T d2, T d3, bool cubic, T rho) {
+  const T den = d2 - d1;
+  T t = (den == T(0)) ? T(0.5) : (rho - d1) / den;
+  t = fmin(fmax(t, T(0)), T(1));
+  if (!cubic) return t;
+  const T c0 = d1 - rho;
+  const T c1 = -d0 * T(1.0 / 3.0) - T(0.5) * d1 + d2 - d3 * T(1.0 / 6.0);
+  const T c2 = T(0.5) * d0 - d1 + T(0.5) * d2;
+  const T c3 = (d3 - d0) * T(1.0 / 6.0) + T(0.5) * (d1 - d2);
+  const bool in0 = c0 < T(0);
+  T a = T(0), b = T(1);
+  for (int it = 0; it < Num<T>::newton_iter; ++it) {
+    const T g = ((c3 * t + c2) * t + c1) * t + c0;
+    if (g == T(0)) break;
+    if ((g < T(0)) == in0)
+      a = t;
+    else
+      b = t;
+    const T dg = (T(3) * c3 * t + T(2) * c2) * t + c1;
+    const T step = g / dg;
+    T tn = t - step;
+    // converged: accept before the safeguard (t sits on a bracket end by now, and a
+    // roundoff-sized step may land just outside it)
+    if (fabs(step) <= Num<T>::newton_tol) {
+      t = fmin(fmax(tn, a), b);
+      break;
+    }
+    if (!(tn >= a && tn <= b)) tn = T(0.5) * (a + b);
+    t = tn;
+  }
+  return t;
+}
+
+// sqrt(c) for c >= 0 from the hardware reciprocal square root (one Newton step in FP64)
+__device__ __forceinline__ double sqrt_fast(double c) {
+  double y = __builtin_amdgcn_rsq(c);
+  y = y * fma(-0.5 * c * y, y, 1.5);
+  return c > 0.0 ? c * y : 0.0;
+}
+__device__ __forceinline__ float sqrt_fast(float c) { return __builtin_amdgcn_sqrtf(c); }
+
+// e^{i x} - 1 without cancellation: (-2 sin^2(x/2), sin x)
+__device__ __forceinline__ c64 expm1_i(double x) {
+  double s, c;
+  sincos(0.5 * x, &s, &c);
+  return mk(-2.0 * s * s, 2.0 * s * c);
+}
+
+template <typename T>
+__device__ __forceinline__ T brightness(T d2, T inv_rho2, T i_lin, T i_sqrt) {
+  const T c = fmax(fma(-d2, inv_rho2, T(1)), T(0));
+  return fma(i_sqrt, sqrt_fast(c), i_lin);  // I0 (1 - u1) + I0 u1 sqrt(1 - d^2/rho^2)
+}
+
+// Lagrange basis of the crossing interpolant at t and the interpolant's slope L'(t):
+// cubic through t = -1, 0, 1, 2, or linear between t = 0 and 1.
+template <typename T>
+__device__ inline T crossing_basis(T d0, T d1, T d2, T d3, bool cubic, T t, T (&l)[4]) {
+  if (!cubic) {
+    l[0] = T(0);
+    l[1] = T(1) - t;
+    l[2] = t;
+    l[3] = T(0);
+    return d2 - d1;
+  }
+  const T tm1 = t + T(1), t1 = t - T(1), t2 = t - T(2);
+  l[0] = -(t * t1 * t2) * T(1.0 / 6.0);
+  l[1] = tm1 * t1 * t2 * T(0.5);
+  l[2] = -(tm1 * t * t2) * T(0.5);
+  l[3] = tm1 * t * t1 * T(1.0 / 6.0);
+  const T c1 = -d0 * T(1.0 / 3.0) - T(0.5) * d1 + d2 - d3 * T(1.0 / 6.0);
+  const T c2 = T(0.5) * d0 - d1 + T(0.5) * d2;
+  const T c3 = (d3 - d0) * T(1.0 / 6.0) + T(0.5) * (d1 - d2);
+  return (T(3) * c3 * t + T(2) * c2) * t + c1;
+}
+
+// d f / d delta on the branch that f(delta) takes
+template <typename T>
+__device__ __forceinline__ T edge_factor_slope(T delta, T u1, T delta_c) {
+  if (u1 == T(0)) return T(1);
+  if (delta >= delta_c && delta > T(0)) {
+    const T B = sqrt(T(1) + T(1) / (T(2) * delta));
+    return T(2.0 / 3.0) * (B - (T(0.5) + delta) / (T(4) * delta * delta * B));
+  }
+  return T(2.0 / 3.0);
+}
+
+}  // namespace icrs

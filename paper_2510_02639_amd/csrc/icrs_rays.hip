@@ -10,81 +10,13 @@
 // pass, reading neighbour distances back from a per-wave LDS row buffer.
 #include "icrs_device.hpp"
 #include "icrs_launch.hpp"
+#include "icrs_quad.hpp"
 
 namespace icrs {
 
 namespace {
 
 constexpr int kWaves = 4;
-
-template <typename T>
-struct Num;
-template <>
-struct Num<double> {
-  static constexpr double newton_tol = 1e-15;
-  static constexpr int newton_iter = 8;
-};
-template <>
-struct Num<float> {
-  static constexpr float newton_tol = 1e-7f;
-  static constexpr int newton_iter = 6;
-};
-
-// f(delta) of App. A.2 (u1 > 0) or delta + 1/2 (uniform source, App. A.1)
-template <typename T>
-__device__ __forceinline__ T edge_factor(T delta, T u1, T delta_c) {
-  if (u1 == T(0)) return delta + T(0.5);
-  if (delta >= delta_c && delta > T(0)) return (T(0.5) + delta) * T(2.0 / 3.0) * sqrt(T(1) + T(1) / (T(2) * delta));
-  return T(2.0 / 3.0) * delta + T(0.5);
-}
-
-// Crossing of the cubic Lagrange interpolant through (t, d) = (-1,d0), (0,d1), (1,d2),
-// (2,d3) with rho on the bracket [0,1] (d1, d2 on opposite sides of rho); linear between
-// d1 and d2 when cubic is false.  Safeguarded Newton from the linear estimate: the bracket
-// shrinks on every step and a step leaving it is replaced by bisection.
-template <typename T>
-__device__ inline T crossing_t(T d0, T d1, T d2, T d3, bool cubic, T rho) {
-  const T den = d2 - d1;
-  T t = (den == T(0)) ? T(0.5) : (rho - d1) / den;
-  t = fmin(fmax(t, T(0)), T(1));
-  if (!cubic) return t;
-  const T c0 = d1 - rho;
-  const T c1 = -d0 * T(1.0 / 3.0) - T(0.5) * d1 + d2 - d3 * T(1.0 / 6.0);
-  const T c2 = T(0.5) * d0 - d1 + T(0.5) * d2;
-  const T c3 = (d3 - d0) * T(1.0 / 6.0) + T(0.5) * (d1 - d2);
-  const bool in0 = c0 < T(0);
-  T a = T(0), b = T(1);
-  for (int it = 0; it < Num<T>::newton_iter; ++it) {
-    const T g = ((c3 * t + c2) * t + c1) * t + c0;
-    if (g == T(0)) break;
-    if ((g < T(0)) == in0)
-      a = t;
-    else
-      b = t;
-    const T dg = (T(3) * c3 * t + T(2) * c2) * t + c1;
-    T tn = t - g / dg;
-    if (!(tn > a && tn < b)) tn = T(0.5) * (a + b);
-    const bool done = fabs(tn - t) <= Num<T>::newton_tol;
-    t = tn;
-    if (done) break;
-  }
-  return t;
-}
-
-// sqrt(c) for c >= 0 from the hardware reciprocal square root (one Newton step in FP64)
-__device__ __forceinline__ double sqrt_fast(double c) {
-  double y = __builtin_amdgcn_rsq(c);
-  y = y * fma(-0.5 * c * y, y, 1.5);
-  return c > 0.0 ? c * y : 0.0;
-}
-__device__ __forceinline__ float sqrt_fast(float c) { return __builtin_amdgcn_sqrtf(c); }
-
-// e^{i x} - 1 without cancellation: (-2 sin^2(x/2), sin x)
-__device__ __forceinline__ c64 expm1_i(double x) {
-  double s, c;
-  sincos(0.5 * x, &s, &c);
-  return mk(-2.0 * s * s, 2.0 * s * c);
-}
 
 // Node maps.  Column phases come from one sincos per lane and a rotation recurrence
 // across the lane's columns (64 apart).
@@ -228,12 +160,6 @@ __device__ inline double fp32_error_bound(const Lens<N>& L, const double* sp, bo
   return 5.96e-8 * (1.0 + dz * amp / rho);
 }
 constexpr double kFp32Budget = 6e-5;  // per-node distance error (relative to rho) allowed in FP32
-
-template <typename T>
-__device__ __forceinline__ T brightness(T d2, T inv_rho2, T i_lin, T i_sqrt) {
-  const T c = fmax(fma(-d2, inv_rho2, T(1)), T(0));
-  return fma(i_sqrt, sqrt_fast(c), i_lin);  // I0 (1 - u1) + I0 u1 sqrt(1 - d^2/rho^2)
-}
 
 // Wave-uniform boundary words of chunk j: inside nodes whose left (side 0) or right
 // (side 1) neighbour is outside or beyond a non-periodic edge.
@@ -404,7 +330,9 @@ __global__ __launch_bounds__(256) void rays_kernel(Batch b, SectorBuf sec, RayWo
   __shared__ unsigned long long next_sh;
   __shared__ int skip_sh;
 
-  const unsigned long long total = w.items ? (unsigned long long)(*w.n_items) : (unsigned long long)w.n;
+  const unsigned long long total = w.items   ? (unsigned long long)(*w.n_items)
+                                   : w.n_dev ? (unsigned long long)(*w.n_dev)
+                                             : (unsigned long long)w.n;
   for (;;) {
     if (threadIdx.x == 0) next_sh = atomicAdd(queue, 1ull);
     __syncthreads();
@@ -459,7 +387,7 @@ __global__ void finalize_kernel(Batch b, SectorBuf sec, RayWork w, const double*
                                 double* __restrict__ mag, uint32_t* __restrict__ status, uint32_t extra_status,
                                 unsigned long long* __restrict__ passes) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= w.n) return;
+  if (idx >= (w.n_dev ? (int64_t)(*w.n_dev) : w.n)) return;
   const int64_t e = w.list ? (int64_t)w.list[idx] : idx;
   const int ns = sec.nsec[e];
   if (passes && ns) atomicAdd(passes, (unsigned long long)ns);

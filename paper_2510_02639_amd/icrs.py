@@ -73,6 +73,12 @@ def lib():
     L.icrs_get_sectors.restype = ctypes.c_int
     L.icrs_point_images.argtypes = [vp, i64, vp, vp, i64, vp, vp, vp, vp, vp, sz]
     L.icrs_point_images.restype = ctypes.c_int
+    L.icrs_magnification_vjp.argtypes = [vp, i64, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz]
+    L.icrs_magnification_vjp.restype = ctypes.c_int
+    L.icrs_prepare.argtypes = [vp, i64, vp, vp, i64, vp, sz]
+    L.icrs_prepare.restype = ctypes.c_int
+    L.icrs_run.argtypes = [vp, vp, vp, vp, vp, sz]
+    L.icrs_run.restype = ctypes.c_int
     L.icrs_set_profiling.argtypes = [vp, ctypes.c_int]
     L.icrs_set_profiling.restype = ctypes.c_int
     L.icrs_get_profile.argtypes = [vp, ctypes.POINTER(icrs_profile), ctypes.c_int]
@@ -84,7 +90,8 @@ def lib():
 
 
 EXPORTED = ["icrs_default_config", "icrs_create", "icrs_destroy", "icrs_workspace_bytes", "icrs_magnification",
-            "icrs_magnification_given", "icrs_get_sectors", "icrs_point_images", "icrs_set_profiling",
+            "icrs_magnification_given", "icrs_magnification_vjp", "icrs_get_sectors", "icrs_point_images",
+            "icrs_prepare", "icrs_run", "icrs_set_profiling",
             "icrs_get_profile", "icrs_status_string"]
 
 
@@ -174,6 +181,20 @@ class Handle:
         _check(code, "icrs_magnification")
         return mag, status
 
+    def prepare(self, params, offsets, n_epochs, workspace=None):
+        """Upload a batch once (icrs_prepare); run() then needs no host work (capturable)."""
+        p, o = _host_events(params, offsets)
+        ws = workspace if workspace is not None else self.workspace(p.shape[0], n_epochs)
+        _check(lib().icrs_prepare(self._h, p.shape[0], _ptr(p), _ptr(o), int(n_epochs), _ptr(ws), ws.numel()),
+               "icrs_prepare")
+        self._prep_ws = ws
+        return ws
+
+    def run(self, t, mag, status):
+        """icrs_run on the prepared batch: device work only, safe inside stream capture."""
+        ws = self._prep_ws
+        _check(lib().icrs_run(self._h, _ptr(t), _ptr(mag), _ptr(status), _ptr(ws), ws.numel()), "icrs_run")
+
     def magnification_given(self, params, offsets, t, sectors, periodic, nsec, workspace=None):
         p, o = _host_events(params, offsets)
         t = _dev(t, torch.float64)
@@ -190,6 +211,29 @@ class Handle:
                                               ws.numel())
         _check(code, "icrs_magnification_given")
         return mag, status
+
+    def magnification_vjp(self, params, offsets, t, sectors, periodic, nsec, cotangent=None, jac=False, mag=False,
+                          workspace=None):
+        """Frozen-structure derivatives on the given sectors: returns (grad [V, 11] or None,
+        jac [E, 11] or None, mag [E] or None), all CUDA float64."""
+        p, o = _host_events(params, offsets)
+        t = _dev(t, torch.float64)
+        n = t.numel()
+        sectors = _dev(sectors, torch.float64)
+        periodic = _dev(periodic, torch.uint8)
+        nsec = _dev(nsec, torch.int32)
+        grad = None
+        if cotangent is not None:
+            cotangent = _dev(cotangent, torch.float64)
+            grad = torch.empty((p.shape[0], ICRS_N_PARAMS), dtype=torch.float64, device=t.device)
+        J = torch.empty((n, ICRS_N_PARAMS), dtype=torch.float64, device=t.device) if jac else None
+        M = torch.empty(n, dtype=torch.float64, device=t.device) if mag else None
+        ws = workspace if workspace is not None else self.workspace(p.shape[0], n)
+        code = lib().icrs_magnification_vjp(self._h, p.shape[0], _ptr(p), _ptr(o), n, _ptr(t), _ptr(sectors),
+                                            _ptr(periodic), _ptr(nsec), _ptr(cotangent), _ptr(grad), _ptr(J),
+                                            _ptr(M), _ptr(ws), ws.numel())
+        _check(code, "icrs_magnification_vjp")
+        return grad, J, M
 
     def get_sectors(self, n_epochs, workspace=None):
         ws = workspace if workspace is not None else self._ws
@@ -211,3 +255,28 @@ class Handle:
                                        _ptr(aps), _ptr(ws), ws.numel())
         _check(code, "icrs_point_images")
         return img, nimg, aps
+
+
+class ICRSFunction(torch.autograd.Function):
+    """mag = ICRSFunction.apply(params, handle, offsets, t): plain ICRS light curves with a
+    reverse-mode gradient for params (CPU float64 [n_events, 11]).  The backward pass keeps
+    the forward's sectors and differentiates on that frozen structure with the library's
+    adjoint (FP64 rays recomputed, nothing stored per ray)."""
+
+    @staticmethod
+    def forward(ctx, params, handle, offsets, t):
+        p = params.detach().cpu().numpy()
+        mag, status = handle.magnification(p, offsets, t)
+        ctx.frozen = handle.get_sectors(t.numel())
+        ctx.handle, ctx.offsets, ctx.t = handle, offsets, t
+        ctx.save_for_backward(params)
+        ctx.status = status
+        return mag
+
+    @staticmethod
+    def backward(ctx, grad_mag):
+        (params,) = ctx.saved_tensors
+        sec, per, ns = ctx.frozen
+        grad, _, _ = ctx.handle.magnification_vjp(params.detach().cpu().numpy(), ctx.offsets, ctx.t, sec, per, ns,
+                                                  cotangent=grad_mag.contiguous().to(torch.float64))
+        return grad.to(params.device), None, None, None
