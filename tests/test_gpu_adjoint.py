@@ -1,6 +1,5 @@
 """GPU adjoint (frozen-structure reverse mode) against the oracle's dual-number Jacobian and
-against central differences of the GPU's own FP64 forward (uniform source, where the
-quadrature is continuous in the parameters)."""
+against central differences of the GPU's own FP64 forward."""
 import numpy as np
 import pytest
 import torch
@@ -83,38 +82,42 @@ def test_adjoint_matches_oracle_jacobian_triple():
         assert np.abs(jac[:, k] - oj[:, k]).max() <= 1e-6 * scale + 1e-12, k
 
 
-def test_adjoint_against_gpu_central_differences_uniform_source():
-    """Uniform source: the quadrature is continuous across chi flips, so central differences
-    of the plain FP64 forward (same sectors) must match the adjoint to 1e-4 of
-    S_p = sum_e |c_e dA_e/dp|.  Step 1e-8 relative: near caustic crossings the second
-    derivatives are so large that 1e-6 steps carry ~1e-2 truncation error."""
-    w = _fit_subset(n_events=6, per_event=4)
-    w.params[:, 7] = 0.0
-    om, oj, sec, per, ns = _oracle_frozen(w, 128, 512)
-    cot = np.random.default_rng(41).normal(size=w.n_epochs)
-    grad, jac, _ = _gpu_vjp(w, sec, per, ns, cot, 128, 512)
-    h = icrs.Handle(n_lens=2, n_limb=128, n_r=128, n_theta=512)
-    t = torch.tensor(w.t, device="cuda")
-    args = [torch.tensor(x, device="cuda") for x in (sec, per, ns)]
-    ev = np.repeat(np.arange(w.n_events), np.diff(w.offsets))
-    worst = []
-    for k in range(7):
-        base = w.params[:, k]
-        hs = 1e-8 * (np.abs(base) if k in (0, 1, 6) else np.maximum(np.abs(base), 1.0))
-        pp, pm = w.params.copy(), w.params.copy()
-        pp[:, k] += hs
-        pm[:, k] -= hs
-        mp, _ = h.magnification_given(pp, w.offsets, t, *args)
-        mm, _ = h.magnification_given(pm, w.offsets, t, *args)
-        fd_e = (mp.cpu().numpy() - mm.cpu().numpy()) / (2 * hs[ev])
-        fd = np.zeros(w.n_events)
-        np.add.at(fd, ev, cot * fd_e)
-        S = np.zeros(w.n_events)
-        np.add.at(S, ev, np.abs(cot * jac[:, k]))
-        err = np.abs(grad[:, k] - fd) / S
-        print(f"param {k}: max |g - fd| / S_p = {err.max():.2e}", flush=True)
-        worst.append(err.max())
-    assert max(worst) <= 1e-4, worst
+def test_adjoint_against_gpu_central_differences():
+    """Central differences of the GPU's own FP64 forward on the same sectors, in a regime
+    where they are meaningful: the config-1 lens (s=0.9, q=0.1, rho=1e-2) at epochs at
+    least 1 d from every caustic crossing, 64 x 256 grids.  Near caustics at rho=1e-3 the
+    quadrature's kinks (a node's chi flipping changes which stencil places a crossing) lie
+    closer together than any step that survives rounding, so there the adjoint is held to
+    the oracle's exact dual-number Jacobian instead (test above).  Parameters 0-6 use a
+    uniform source (step 1e-7 relative); the limb-darkening coefficient, which moves no
+    node across the limb, uses u = 0.5 and a 1e-6 step.  Bar: |g - fd| <= 1e-4 S_p with
+    S_p = sum_e |c_e dA_e/dp|, and per epoch 1e-4 of the largest |dA/dp|."""
+    t_np = np.array([-20.0, -10.0, -6.0, -1.5, 1.5, 8.0, 12.0, 24.0])
+    n_r, n_theta = 64, 256
+    cot = np.random.default_rng(41).normal(size=t_np.size)
+    off = np.array([0, t_np.size], np.int64)
+    t = torch.tensor(t_np, device="cuda")
+    h = icrs.Handle(n_lens=2, n_limb=64, n_r=n_r, n_theta=n_theta)
+    for u_ld, ks, hrel in ((0.0, range(7), 1e-7), (0.5, [7], 1e-6)):
+        p = np.array([[0.9, 0.1, 0.05, 0.6, 0.0, 20.0, 1e-2, u_ld, 0.0, 0.0, 0.0]])
+        r = O.magnification(2, p[0], t_np, n_limb=64, n_r=n_r, n_theta=n_theta)
+        sec, per, ns = r["sectors"], r["periodic"], r["nsec"]
+        args = [torch.tensor(x, device="cuda") for x in (sec, per, ns)]
+        grad, jac, _ = h.magnification_vjp(p, off, t, *args, cotangent=torch.tensor(cot, device="cuda"), jac=True)
+        grad, jac = grad.cpu().numpy()[0], jac.cpu().numpy()
+        for k in ks:
+            step = hrel * (abs(p[0, k]) if k in (0, 1, 6) else max(abs(p[0, k]), 1.0))
+            pp, pm = p.copy(), p.copy()
+            pp[0, k] += step
+            pm[0, k] -= step
+            mp, _ = h.magnification_given(pp, off, t, *args)
+            mm, _ = h.magnification_given(pm, off, t, *args)
+            fd_e = (mp.cpu().numpy() - mm.cpu().numpy()) / (2 * step)
+            S = np.sum(np.abs(cot * jac[:, k]))
+            err = abs(grad[k] - np.sum(cot * fd_e)) / S
+            err_e = np.abs(jac[:, k] - fd_e).max() / np.abs(jac[:, k]).max()
+            print(f"param {k}: |g - fd| / S_p = {err:.2e}, per-epoch {err_e:.2e}", flush=True)
+            assert err <= 1e-4 and err_e <= 1e-4, k
 
 
 def test_autograd_function_backward_equals_vjp():
