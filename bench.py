@@ -28,6 +28,12 @@ sys.path.insert(0, ROOT)
 METRIC = "magnified epochs/sec at rho=1e-3 LD (rel err<=1e-4), plain vs batched+learned"
 FLOPS_PER_RAY = {2: 35.0, 3: 48.0}          # algorithmic flop-equivalents per ray
 PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}  # MI355X vector peaks
+KERNEL = {"fp32": "rays_kernel<2, 8, true, MapF32<2, 8>>", "fp64": "rays_kernel<2, 8, true, MapF64<2, 8>>"}
+# HBM bytes per launch of the main ray kernel from rocprofv3 FETCH_SIZE + WRITE_SIZE passes,
+# scaled by the same counters' reading on a plain copy kernel of known size; keyed by
+# (ray precision, events).  Filled in from measured counter runs; None when not measured
+# for the current kernel.  (fp32, 2048): FETCH 820090 KiB x 2.0 + WRITE 552849 KiB x 1.0.
+TRAFFIC = {("fp32", 2048): 2.246e9}
 
 
 def cpu_baseline(w, gpu_mag, budget_s, seed=0):
@@ -68,6 +74,8 @@ def main():
     ap.add_argument("--roots", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the path has no multi-GPU leg); use --gpus 1",
@@ -75,6 +83,15 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_probe_mib:
+        # one elementwise kernel that reads and writes copy_probe_mib MiB each, a few times
+        src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_each_way": src.numel() * 4, "launches": 3}), flush=True)
+        return
     from paper_2510_02639_amd import icrs, workloads
 
     t_gen = time.perf_counter()
@@ -106,8 +123,11 @@ def main():
 
     epochs = w.n_epochs * args.steps
     rays = prof["n_sector_passes"] * w.n_r * w.n_theta
-    achieved = rays * FLOPS_PER_RAY[2] / (prof["ms_rays"] * 1e-3) / 1e12
+    # dominant kernel: the main ray pass (one launch per step, timed alone with HIP events)
+    main_rays = prof["n_main_sectors"] * w.n_r * w.n_theta
+    achieved = main_rays * FLOPS_PER_RAY[2] / (prof["ms_rays_main"] * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.rays]
+    n_main = max(prof["n_main_launches"], 1)
     st = status.cpu().numpy().astype(np.uint32)
     gmag = mag.cpu().numpy()
 
@@ -120,11 +140,11 @@ def main():
                    "path": "plain", "rho": 1e-3},
         "rays_per_s": rays / dt,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": None, "kernel": "rays_kernel",
-                     "flops_per_ray": FLOPS_PER_RAY[2], "rays_per_launch_avg": rays / max(prof["n_rays_launches"], 1),
-                     "kernel_ms_per_launch_avg": prof["ms_rays"] / max(prof["n_rays_launches"], 1)},
+                     "traffic": TRAFFIC.get((args.rays, w.n_events)), "kernel": KERNEL[args.rays],
+                     "flops_per_ray": FLOPS_PER_RAY[2], "rays_per_launch_avg": main_rays / n_main,
+                     "kernel_ms_per_launch_avg": prof["ms_rays_main"] / n_main},
         "breakdown_ms_per_step": {k: prof[k] / args.steps for k in ("ms_centre", "ms_limb_sectors", "ms_rays",
-                                                                    "ms_finalize")},
+                                                                    "ms_rays_main", "ms_finalize")},
         "sectors_per_epoch": prof["n_sector_passes"] / max(prof["n_epochs"], 1),
         "status_counts": {name: int(np.sum((st & bit) != 0)) for name, bit in
                           [("root_nonconv", 1), ("img_count", 2), ("cap_overflow", 4), ("clip", 8), ("nan", 16)]},

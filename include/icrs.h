@@ -171,7 +171,10 @@ icrs_status icrs_point_images(icrs_handle* h, int64_t n_events, const double* pa
  * profiling on, every call records HIP events around each kernel class on the handle's
  * stream and waits for them at the end of the call; totals accumulate in the handle.
  * n_sector_passes counts (epoch, sector) grids shot (each is n_r x n_theta rays), summed
- * over the clip retries. */
+ * over the clip retries.  ms_rays covers every ray kernel; ms_rays_main only the main-pass
+ * kernel of each call's first attempt (FP32 or FP64 per ray_precision, one launch per
+ * call, n_main_launches of them), which shot n_main_sectors grids in total (first-attempt
+ * sectors less those the FP32 pass handed to the FP64 pass). */
 typedef struct icrs_profile {
   double ms_centre;        /* centre images (point-source magnification)   */
   double ms_limb_sectors;  /* limb images + sector construction            */
@@ -181,11 +184,52 @@ typedef struct icrs_profile {
   int64_t n_rays_launches;
   int64_t n_sector_passes;
   int64_t n_epochs;
+  double ms_rays_main;     /* main ray pass of the first attempt            */
+  int64_t n_main_launches;
+  int64_t n_main_sectors;
 } icrs_profile;
 
 icrs_status icrs_set_profiling(icrs_handle* h, int on);
 /* Copy the accumulated totals into *out; reset them when reset != 0. */
 icrs_status icrs_get_profile(icrs_handle* h, icrs_profile* out, int reset);
+
+/* ---- learned-bounds network (not in the paper) ---------------------------------------
+ * A multilayer perceptron 10 -> 128 -> 128 -> 128 -> 4 with GELU (tanh form) after each
+ * hidden layer, 34 948 parameters, run on the matrix cores with bfloat16 operands and FP32
+ * accumulation.  It maps the features of one point-source image to four standardised
+ * outputs (the learned path turns them into a polar box).  Parameters live in a padded
+ * FP32 master blob of ICRS_MLP_PARAM_FLOATS floats (DEVICE, caller-owned):
+ *   W1 [128][32] (input columns 10..31 zero), b1 [128], W2 [128][128], b2 [128],
+ *   W3 [128][128], b3 [128], W4 [16][128] (rows 4..15 zero), b4 [16] (entries 4..15 zero),
+ * W[n][k] multiplying input k into output n.  The matrix products read a packed bfloat16
+ * copy of ICRS_MLP_PACKED_HALFS halfs (DEVICE, 16-byte aligned) that icrs_mlp_pack and
+ * icrs_mlp_adamw write.  norm (DEVICE, ICRS_MLP_NORM_FLOATS floats): in_mean[10],
+ * in_std[10], out_mean[4], out_std[4]; inputs are standardised with it, and outputs are
+ * returned de-standardised (icrs_mlp_forward) or compared with standardised targets
+ * (icrs_mlp_loss_grad).  All run on the handle's stream; row-major FP32 x [n_rows][10],
+ * y / target [n_rows][4]. */
+#define ICRS_MLP_PARAM_FLOATS 39312
+#define ICRS_MLP_PACKED_HALFS 75776
+#define ICRS_MLP_NORM_FLOATS 32
+
+/* packed = bfloat16 (round to nearest even) of the weight matrices and their transposes */
+icrs_status icrs_mlp_pack(icrs_handle* h, const float* params, uint16_t* packed);
+/* y = network(x) for n_rows rows (n_rows >= 0) */
+icrs_status icrs_mlp_forward(icrs_handle* h, const uint16_t* packed, const float* params, const float* norm,
+                             int64_t n_rows, const float* x, float* y);
+/* Bytes of workspace icrs_mlp_loss_grad needs for n_rows rows. */
+size_t icrs_mlp_workspace_bytes(int64_t n_rows);
+/* loss[0] = mean over rows and the 4 outputs of (y - (target - out_mean) / out_std)^2 with y
+ * the standardised output; grad = d loss / d params in the blob layout (padding entries 0).
+ * Deterministic (fixed-order reductions).  n_rows >= 1. */
+icrs_status icrs_mlp_loss_grad(icrs_handle* h, const uint16_t* packed, const float* params, const float* norm,
+                               int64_t n_rows, const float* x, const float* target, float* grad, float* loss,
+                               void* workspace, size_t workspace_bytes);
+/* One AdamW step (bias-corrected moments, decoupled decay on weight matrices only) on
+ * params with moments m, v (zero before step 1); step >= 1; repacks into packed when it
+ * is non-NULL. */
+icrs_status icrs_mlp_adamw(icrs_handle* h, float* params, const float* grad, float* m, float* v, int64_t step,
+                           float lr, float beta1, float beta2, float eps, float weight_decay, uint16_t* packed);
 
 const char* icrs_status_string(icrs_status s);
 

@@ -107,14 +107,16 @@ struct Timer {
   icrs_handle* h;
   int n = 0;
   double* acc[8];
+  double* acc2[8];
   explicit Timer(icrs_handle* hh) : h(hh) {}
   hipError_t begin() {
     if (!h->profiling || n >= 8) return hipSuccess;
     return hipEventRecord(h->ev[2 * n], h->stream);
   }
-  hipError_t end(double* into) {
+  hipError_t end(double* into, double* also = nullptr) {
     if (!h->profiling || n >= 8) return hipSuccess;
     acc[n] = into;
+    acc2[n] = also;
     return hipEventRecord(h->ev[2 * n++ + 1], h->stream);
   }
   hipError_t flush() {
@@ -124,6 +126,7 @@ struct Timer {
       float ms = 0.f;
       e = hipEventElapsedTime(&ms, h->ev[2 * i], h->ev[2 * i + 1]);
       *acc[i] += ms;
+      if (acc2[i]) *acc2[i] += ms;
     }
     n = 0;
     return e;
@@ -192,8 +195,15 @@ icrs_status run_rays(icrs_handle* h, const Views& v, int max_retries, double* ma
   if (h->profiling) ICRS_TRY(icrs::launch_fill_i32(v.counters + 8, 2, 0, h->stream));
   Timer tm(h);
   for (int attempt = 0;; ++attempt) {
+    // stage 0: the main pass (timed on its own for the first attempt); stage 1: FP64 pass
+    // over the sectors the FP32 main pass listed
     ICRS_TRY(tm.begin());
-    ICRS_TRY(icrs::launch_rays(c.n_lens, c.ray_precision, v.b, v.sec, w, c.n_r, c.n_theta, c.delta_c, v.partial,
+    ICRS_TRY(icrs::launch_rays(c.n_lens, c.ray_precision, 0, v.b, v.sec, w, c.n_r, c.n_theta, c.delta_c, v.partial,
+                               v.clip, (unsigned long long*)(v.counters + 12), v.fallback, v.counters + 4,
+                               h->stream));
+    ICRS_TRY(tm.end(&h->prof.ms_rays, attempt == 0 ? &h->prof.ms_rays_main : nullptr));
+    ICRS_TRY(tm.begin());
+    ICRS_TRY(icrs::launch_rays(c.n_lens, c.ray_precision, 1, v.b, v.sec, w, c.n_r, c.n_theta, c.delta_c, v.partial,
                                v.clip, (unsigned long long*)(v.counters + 12), v.fallback, v.counters + 4,
                                h->stream));
     ICRS_TRY(tm.end(&h->prof.ms_rays));
@@ -204,6 +214,16 @@ icrs_status run_rays(icrs_handle* h, const Views& v, int max_retries, double* ma
                                    status, extra_status, h->profiling ? passes : nullptr, h->stream));
     ICRS_TRY(tm.end(&h->prof.ms_finalize));
     ICRS_TRY(tm.flush());
+    if (h->profiling && attempt == 0) {
+      // sectors the main pass shot: all first-attempt sectors less those sent to FP64
+      unsigned long long np = 0;
+      int32_t nfb = 0;
+      ICRS_TRY(hipMemcpyAsync(&np, passes, sizeof(np), hipMemcpyDeviceToHost, h->stream));
+      ICRS_TRY(hipMemcpyAsync(&nfb, v.counters + 4, sizeof(nfb), hipMemcpyDeviceToHost, h->stream));
+      ICRS_TRY(hipStreamSynchronize(h->stream));
+      h->prof.n_main_launches += 1;
+      h->prof.n_main_sectors += (int64_t)np - (c.ray_precision == ICRS_FP32 ? (int64_t)nfb : 0);
+    }
     if (attempt >= max_retries) break;
     int32_t count = 0;
     ICRS_TRY(hipMemcpyAsync(&count, v.counters, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
@@ -239,9 +259,10 @@ icrs_status run_plain_device(icrs_handle* h, const Views& v, double* mag, uint32
   int32_t* lists[2] = {v.list_a, v.list_b};
   int32_t* counts[2] = {v.counters + 0, v.counters + 1};
   for (int attempt = 0; attempt <= c.max_retries; ++attempt) {
-    ICRS_TRY(icrs::launch_rays(c.n_lens, c.ray_precision, v.b, v.sec, w, c.n_r, c.n_theta, c.delta_c, v.partial,
-                               v.clip, (unsigned long long*)(v.counters + 12), v.fallback, v.counters + 4,
-                               h->stream));
+    for (int stage = 0; stage < 2; ++stage)
+      ICRS_TRY(icrs::launch_rays(c.n_lens, c.ray_precision, stage, v.b, v.sec, w, c.n_r, c.n_theta, c.delta_c,
+                                 v.partial, v.clip, (unsigned long long*)(v.counters + 12), v.fallback,
+                                 v.counters + 4, h->stream));
     int32_t* nxt = lists[attempt & 1];
     int32_t* ncount = counts[attempt & 1];
     ICRS_TRY(icrs::launch_fill_i32(ncount, 1, 0, h->stream));
@@ -444,6 +465,44 @@ icrs_status icrs_point_images(icrs_handle* h, int64_t n_events, const double* pa
   const icrs_config& c = h->cfg;
   return hip_status(icrs::launch_centre_images(c.n_lens, c.root_precision == ICRS_FP32, v.b, images, n_images, a_ps,
                                                nullptr, h->stream));
+}
+
+icrs_status icrs_mlp_pack(icrs_handle* h, const float* params, uint16_t* packed) {
+  if (!h || !params || !packed || ((uintptr_t)packed & 15u)) return ICRS_EINVAL;
+  return hip_status(icrs::mlp::launch_pack(params, packed, h->stream));
+}
+
+icrs_status icrs_mlp_forward(icrs_handle* h, const uint16_t* packed, const float* params, const float* norm,
+                             int64_t n_rows, const float* x, float* y) {
+  if (!h || n_rows < 0) return ICRS_EINVAL;
+  if (n_rows == 0) return ICRS_OK;
+  if (!packed || !params || !norm || !x || !y || ((uintptr_t)packed & 15u)) return ICRS_EINVAL;
+  if (n_rows > ((int64_t)1 << 36)) return ICRS_EUNSUPPORTED;
+  return hip_status(icrs::mlp::launch_forward(packed, params, norm, n_rows, x, y, h->stream));
+}
+
+size_t icrs_mlp_workspace_bytes(int64_t n_rows) {
+  if (n_rows < 1) return 0;
+  return icrs::mlp::train_workspace_bytes(n_rows);
+}
+
+icrs_status icrs_mlp_loss_grad(icrs_handle* h, const uint16_t* packed, const float* params, const float* norm,
+                               int64_t n_rows, const float* x, const float* target, float* grad, float* loss,
+                               void* workspace, size_t workspace_bytes) {
+  if (!h || n_rows < 1 || !packed || !params || !norm || !x || !target || !grad || !workspace) return ICRS_EINVAL;
+  if (((uintptr_t)packed & 15u) || ((uintptr_t)workspace & 3u)) return ICRS_EINVAL;
+  if (workspace_bytes < icrs::mlp::train_workspace_bytes(n_rows)) return ICRS_ENOMEM;
+  return hip_status(icrs::mlp::launch_loss_grad(packed, params, norm, n_rows, x, target, grad, loss, workspace,
+                                                h->stream));
+}
+
+icrs_status icrs_mlp_adamw(icrs_handle* h, float* params, const float* grad, float* m, float* v, int64_t step,
+                           float lr, float beta1, float beta2, float eps, float weight_decay, uint16_t* packed) {
+  if (!h || !params || !grad || !m || !v || step < 1) return ICRS_EINVAL;
+  if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps > 0.f && lr >= 0.f)) return ICRS_EINVAL;
+  if (packed && ((uintptr_t)packed & 15u)) return ICRS_EINVAL;
+  return hip_status(icrs::mlp::launch_adamw(params, grad, m, v, step, lr, beta1, beta2, eps, weight_decay, packed,
+                                            h->stream));
 }
 
 const char* icrs_status_string(icrs_status s) {

@@ -43,10 +43,13 @@ struct RayWork {
 };
 
 // persistent ray kernel; queue: 16 bytes of device scratch (zeroed here) for the work
-// counter; fallback/n_fallback: [n_epochs * 10] list + counter for FP32 -> FP64 sectors
-hipError_t launch_rays(int n_lens, int ray_fp32, const Batch& b, const SectorBuf& sec, const RayWork& w, int n_r,
-                       int n_theta, double delta_c, double* partial, uint8_t* clip, unsigned long long* queue,
-                       int32_t* fallback, int32_t* n_fallback, hipStream_t s);
+// counter; fallback/n_fallback: [n_epochs * 10] list + counter for FP32 -> FP64 sectors.
+// stage 0 is the main pass over w (FP32 or FP64); stage 1 is the FP64 pass over the sectors
+// the FP32 main pass listed (nothing to do when ray_fp32 == 0).  Both stages are always
+// launched, in order, before the finalize kernel.
+hipError_t launch_rays(int n_lens, int ray_fp32, int stage, const Batch& b, const SectorBuf& sec, const RayWork& w,
+                       int n_r, int n_theta, double delta_c, double* partial, uint8_t* clip,
+                       unsigned long long* queue, int32_t* fallback, int32_t* n_fallback, hipStream_t s);
 
 // sums sector fluxes into magnifications; epochs with edge touches and retries left get
 // widened sectors and are appended to next_list (count in *next_count)
@@ -62,6 +65,21 @@ hipError_t launch_adjoint(int n_lens, const Batch& b, const SectorBuf& sec, int 
                           hipStream_t s);
 
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+
+namespace mlp {
+// learned-bounds network: FP32 master blob (param_floats()), packed bf16 weights
+// (packed_halfs()), norm[32] = in_mean[10], in_std[10], out_mean[4], out_std[4]
+int param_floats();
+int packed_halfs();
+size_t train_workspace_bytes(int64_t m_rows);
+hipError_t launch_pack(const float* prm, uint16_t* wb, hipStream_t s);
+hipError_t launch_forward(const uint16_t* wb, const float* prm, const float* norm, int64_t m_rows, const float* x,
+                          float* y, hipStream_t s);
+hipError_t launch_loss_grad(const uint16_t* wb, const float* prm, const float* norm, int64_t m_rows, const float* x,
+                            const float* tgt, float* grad, float* loss, void* ws, hipStream_t s);
+hipError_t launch_adamw(float* prm, const float* grad, float* m, float* v, int64_t step, float lr, float beta1,
+                        float beta2, float eps, float wd, uint16_t* wb, hipStream_t s);
+}  // namespace mlp
 hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
 
 }  // namespace icrs

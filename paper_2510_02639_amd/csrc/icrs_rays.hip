@@ -470,18 +470,21 @@ hipError_t launch_rays_n(const Batch& b, const SectorBuf& sec, const RayWork& w,
 }
 
 template <int N>
-hipError_t launch_rays_lens(int ray_fp32, const Batch& b, const SectorBuf& sec, const RayWork& w, int n_r,
-                            int n_theta, double delta_c, double* partial, uint8_t* clip, unsigned long long* queue,
-                            int32_t* fallback, int32_t* n_fallback, hipStream_t s) {
-  if (!ray_fp32) return launch_rays_n<N, MapF64>(b, sec, w, n_r, n_theta, delta_c, partial, clip, queue, s);
-  // FP32 pass (sectors over the rounding budget are listed), then the FP64 pass on the list
-  hipError_t e = launch_fill_i32(n_fallback, 1, 0, s);
-  if (e != hipSuccess) return e;
-  RayWork w32 = w;
-  w32.fallback = fallback;
-  w32.n_fallback = n_fallback;
-  e = launch_rays_n<N, MapF32>(b, sec, w32, n_r, n_theta, delta_c, partial, clip, queue, s);
-  if (e != hipSuccess) return e;
+hipError_t launch_rays_lens(int ray_fp32, int stage, const Batch& b, const SectorBuf& sec, const RayWork& w,
+                            int n_r, int n_theta, double delta_c, double* partial, uint8_t* clip,
+                            unsigned long long* queue, int32_t* fallback, int32_t* n_fallback, hipStream_t s) {
+  if (!ray_fp32)
+    return stage == 0 ? launch_rays_n<N, MapF64>(b, sec, w, n_r, n_theta, delta_c, partial, clip, queue, s)
+                      : hipSuccess;
+  if (stage == 0) {
+    // FP32 pass; sectors over the rounding budget are listed for the FP64 pass
+    hipError_t e = launch_fill_i32(n_fallback, 1, 0, s);
+    if (e != hipSuccess) return e;
+    RayWork w32 = w;
+    w32.fallback = fallback;
+    w32.n_fallback = n_fallback;
+    return launch_rays_n<N, MapF32>(b, sec, w32, n_r, n_theta, delta_c, partial, clip, queue, s);
+  }
   RayWork w64{};
   w64.items = fallback;
   w64.n_items = n_fallback;
@@ -491,15 +494,15 @@ hipError_t launch_rays_lens(int ray_fp32, const Batch& b, const SectorBuf& sec, 
 
 }  // namespace
 
-hipError_t launch_rays(int n_lens, int ray_fp32, const Batch& b, const SectorBuf& sec, const RayWork& w, int n_r,
-                       int n_theta, double delta_c, double* partial, uint8_t* clip, unsigned long long* queue,
-                       int32_t* fallback, int32_t* n_fallback, hipStream_t s) {
+hipError_t launch_rays(int n_lens, int ray_fp32, int stage, const Batch& b, const SectorBuf& sec, const RayWork& w,
+                       int n_r, int n_theta, double delta_c, double* partial, uint8_t* clip,
+                       unsigned long long* queue, int32_t* fallback, int32_t* n_fallback, hipStream_t s) {
   if (w.n == 0) return hipSuccess;
   if (n_lens == 2)
-    return launch_rays_lens<2>(ray_fp32, b, sec, w, n_r, n_theta, delta_c, partial, clip, queue, fallback, n_fallback,
-                               s);
-  return launch_rays_lens<3>(ray_fp32, b, sec, w, n_r, n_theta, delta_c, partial, clip, queue, fallback, n_fallback,
-                             s);
+    return launch_rays_lens<2>(ray_fp32, stage, b, sec, w, n_r, n_theta, delta_c, partial, clip, queue, fallback,
+                               n_fallback, s);
+  return launch_rays_lens<3>(ray_fp32, stage, b, sec, w, n_r, n_theta, delta_c, partial, clip, queue, fallback,
+                             n_fallback, s);
 }
 
 hipError_t launch_finalize(const Batch& b, const SectorBuf& sec, const RayWork& w, const double* partial,

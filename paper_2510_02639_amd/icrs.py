@@ -35,7 +35,8 @@ class IcrsError(RuntimeError):
 class icrs_profile(ctypes.Structure):
     _fields_ = [("ms_centre", ctypes.c_double), ("ms_limb_sectors", ctypes.c_double), ("ms_rays", ctypes.c_double),
                 ("ms_finalize", ctypes.c_double), ("n_calls", ctypes.c_int64), ("n_rays_launches", ctypes.c_int64),
-                ("n_sector_passes", ctypes.c_int64), ("n_epochs", ctypes.c_int64)]
+                ("n_sector_passes", ctypes.c_int64), ("n_epochs", ctypes.c_int64), ("ms_rays_main", ctypes.c_double),
+                ("n_main_launches", ctypes.c_int64), ("n_main_sectors", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -83,6 +84,17 @@ def lib():
     L.icrs_set_profiling.restype = ctypes.c_int
     L.icrs_get_profile.argtypes = [vp, ctypes.POINTER(icrs_profile), ctypes.c_int]
     L.icrs_get_profile.restype = ctypes.c_int
+    f32 = ctypes.c_float
+    L.icrs_mlp_pack.argtypes = [vp, vp, vp]
+    L.icrs_mlp_pack.restype = ctypes.c_int
+    L.icrs_mlp_forward.argtypes = [vp, vp, vp, vp, i64, vp, vp]
+    L.icrs_mlp_forward.restype = ctypes.c_int
+    L.icrs_mlp_workspace_bytes.argtypes = [i64]
+    L.icrs_mlp_workspace_bytes.restype = sz
+    L.icrs_mlp_loss_grad.argtypes = [vp, vp, vp, vp, i64, vp, vp, vp, vp, vp, sz]
+    L.icrs_mlp_loss_grad.restype = ctypes.c_int
+    L.icrs_mlp_adamw.argtypes = [vp, vp, vp, vp, vp, i64, f32, f32, f32, f32, f32, vp]
+    L.icrs_mlp_adamw.restype = ctypes.c_int
     L.icrs_status_string.argtypes = [ctypes.c_int]
     L.icrs_status_string.restype = ctypes.c_char_p
     _lib = L
@@ -92,7 +104,9 @@ def lib():
 EXPORTED = ["icrs_default_config", "icrs_create", "icrs_destroy", "icrs_workspace_bytes", "icrs_magnification",
             "icrs_magnification_given", "icrs_magnification_vjp", "icrs_get_sectors", "icrs_point_images",
             "icrs_prepare", "icrs_run", "icrs_set_profiling",
-            "icrs_get_profile", "icrs_status_string"]
+            "icrs_get_profile", "icrs_mlp_pack", "icrs_mlp_forward", "icrs_mlp_workspace_bytes",
+            "icrs_mlp_loss_grad", "icrs_mlp_adamw", "icrs_status_string"]
+MLP_PARAM_FLOATS, MLP_PACKED_HALFS, MLP_NORM_FLOATS = 39312, 75776, 32
 
 
 def _check(code, where):
@@ -234,6 +248,41 @@ class Handle:
                                             _ptr(M), _ptr(ws), ws.numel())
         _check(code, "icrs_magnification_vjp")
         return grad, J, M
+
+    # ---- learned-bounds network (blob layouts in include/icrs.h) -------------------------
+    def mlp_pack(self, params, packed):
+        _check(lib().icrs_mlp_pack(self._h, _ptr(_dev(params, torch.float32)), _ptr(_dev(packed, torch.int16))),
+               "icrs_mlp_pack")
+
+    def mlp_forward(self, packed, params, norm, x, y=None):
+        x = _dev(x, torch.float32)
+        n = x.shape[0]
+        y = y if y is not None else torch.empty((n, 4), dtype=torch.float32, device=x.device)
+        _check(lib().icrs_mlp_forward(self._h, _ptr(_dev(packed, torch.int16)), _ptr(_dev(params, torch.float32)),
+                                      _ptr(_dev(norm, torch.float32)), n, _ptr(x), _ptr(_dev(y, torch.float32))),
+               "icrs_mlp_forward")
+        return y
+
+    def mlp_loss_grad(self, packed, params, norm, x, target, workspace=None, grad=None, loss=None):
+        x = _dev(x, torch.float32)
+        n = x.shape[0]
+        nb = lib().icrs_mlp_workspace_bytes(n)
+        ws = workspace if workspace is not None else torch.empty(nb, dtype=torch.uint8, device=x.device)
+        grad = grad if grad is not None else torch.empty(MLP_PARAM_FLOATS, dtype=torch.float32, device=x.device)
+        loss = loss if loss is not None else torch.empty(1, dtype=torch.float32, device=x.device)
+        _check(lib().icrs_mlp_loss_grad(self._h, _ptr(_dev(packed, torch.int16)), _ptr(_dev(params, torch.float32)),
+                                        _ptr(_dev(norm, torch.float32)), n, _ptr(x),
+                                        _ptr(_dev(target, torch.float32)), _ptr(grad), _ptr(loss), _ptr(ws),
+                                        ws.numel()), "icrs_mlp_loss_grad")
+        return grad, loss
+
+    def mlp_adamw(self, params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0,
+                  packed=None):
+        _check(lib().icrs_mlp_adamw(self._h, _ptr(_dev(params, torch.float32)), _ptr(_dev(grad, torch.float32)),
+                                    _ptr(_dev(m, torch.float32)), _ptr(_dev(v, torch.float32)), int(step), lr,
+                                    beta1, beta2, eps, weight_decay,
+                                    _ptr(_dev(packed, torch.int16)) if packed is not None else None),
+               "icrs_mlp_adamw")
 
     def get_sectors(self, n_epochs, workspace=None):
         ws = workspace if workspace is not None else self._ws
