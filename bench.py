@@ -32,8 +32,8 @@ KERNEL = {"fp32": "rays_kernel<2, 8, true, MapF32<2, 8>>", "fp64": "rays_kernel<
 # HBM bytes per launch of the main ray kernel from rocprofv3 FETCH_SIZE + WRITE_SIZE passes,
 # scaled by the same counters' reading on a plain copy kernel of known size; keyed by
 # (ray precision, events).  Filled in from measured counter runs; None when not measured
-# for the current kernel.  (fp32, 2048): FETCH 820090 KiB x 2.0 + WRITE 552849 KiB x 1.0.
-TRAFFIC = {("fp32", 2048): 2.246e9}
+# for the current kernel.
+TRAFFIC = {}
 
 
 def cpu_baseline(w, gpu_mag, budget_s, seed=0):

@@ -187,6 +187,7 @@ typedef struct icrs_profile {
   double ms_rays_main;     /* main ray pass of the first attempt            */
   int64_t n_main_launches;
   int64_t n_main_sectors;
+  int64_t n_main_rays;     /* n_main_sectors x that call's n_r x n_theta     */
 } icrs_profile;
 
 icrs_status icrs_set_profiling(icrs_handle* h, int on);
@@ -230,6 +231,63 @@ icrs_status icrs_mlp_loss_grad(icrs_handle* h, const uint16_t* packed, const flo
  * is non-NULL. */
 icrs_status icrs_mlp_adamw(icrs_handle* h, float* params, const float* grad, float* m, float* v, int64_t step,
                            float lr, float beta1, float beta2, float eps, float weight_decay, uint16_t* packed);
+
+/* ---- learned-bounds path (not in the paper) -------------------------------------------
+ * Training data: for every epoch, the point-source images of the source centre and, per
+ * image, the extent of the limb images the plain sector step assigns to it (n_limb limb
+ * points of the handle's config, each limb image given to the nearest centre image).
+ * Outputs (DEVICE): features [n_epochs][MI][10] (MI = n_lens^2 + 1; rows j >= n_images[e]
+ * are zero): log10 s, log10 q, w_c.x, w_c.y, log10 rho, z.x, z.y, parity, log10 mu,
+ * log10(sigma/rho), with mu = 1/|det J| and sigma = rho/|1 - |kappa|| the image's
+ * linearised size; targets [n_epochs][MI][4] = ln(offset/sigma) of the four extents
+ * (|z| - r_min, r_max - |z|, |z| (theta_z - theta_min), |z| (theta_max - theta_z)),
+ * offsets floored at 1e-3 sigma; n_images [n_epochs]; flags [n_epochs], 0 when every limb
+ * point has as many images as the centre, every image received limb images and none
+ * spans half a turn (only such epochs are training data). */
+icrs_status icrs_image_bounds(icrs_handle* h, int64_t n_events, const double* params, const int64_t* epoch_offsets,
+                              int64_t n_epochs, const double* t, float* features, float* targets,
+                              int32_t* n_images, uint32_t* flags, void* workspace, size_t workspace_bytes);
+
+/* Learned path settings.  n_check limb points (8..64) confirm the image count and sample
+ * each image's extent; the learned boxes get n_r x n_theta grids; network offsets are
+ * scaled by exp(log_safety); images with mu < prune_ratio x A_ps get no grid and add mu;
+ * epochs whose ring-average point-source magnification differs from the centre's by more
+ * than vary_max (relative) go to the plain path before any ray; the drift gate sends back
+ * results with |A - A_est| > gate_rel A_ps + |A_ring - A_ps|. */
+typedef struct icrs_learned_config {
+  int32_t n_check;
+  int32_t n_r;
+  int32_t n_theta;
+  int32_t reserved;
+  double log_safety;
+  double prune_ratio;
+  double vary_max;
+  double gate_rel;
+} icrs_learned_config;
+
+typedef struct icrs_learned_stats {
+  int64_t n_epochs;
+  int64_t n_learned;        /* epochs whose result comes from learned boxes         */
+  int64_t n_fallback;       /* epochs recomputed by the plain path                  */
+  int64_t n_gate_rejected;  /* of those, rejected after the learned rays             */
+  int64_t n_pruned_images;  /* images given no grid                                 */
+} icrs_learned_stats;
+
+#define ICRS_ST_LEARNED 128u  /* result from learned boxes                         */
+#define ICRS_ST_FALLBACK 256u /* the learned path handed this epoch to the plain path */
+
+void icrs_default_learned_config(icrs_learned_config* lc);
+size_t icrs_learned_workspace_bytes(const icrs_handle* h, int64_t n_events, int64_t n_epochs);
+/* Magnifications through the learned path (binary lenses; n_lens = 3 returns
+ * ICRS_EUNSUPPORTED).  Same inputs and outputs as icrs_magnification plus the network
+ * (packed, params, norm as for icrs_mlp_forward) and optional host stats.  Epochs that
+ * fail a check are computed by the plain path of the handle's config inside the call.
+ * Synchronises the stream (list sizes are read back). */
+icrs_status icrs_magnification_learned(icrs_handle* h, int64_t n_events, const double* params,
+                                       const int64_t* epoch_offsets, int64_t n_epochs, const double* t,
+                                       const icrs_learned_config* lc, const uint16_t* packed,
+                                       const float* mlp_params, const float* norm, double* mag, uint32_t* status,
+                                       icrs_learned_stats* stats, void* workspace, size_t workspace_bytes);
 
 const char* icrs_status_string(icrs_status s);
 

@@ -1,0 +1,86 @@
+"""Autotuner: the grid resolution, ray precision and launch choices of the batched path,
+picked on a calibration subset of the workload itself.
+
+Grid: the smallest N_r x N_theta (by ray count) whose magnifications on the calibration
+subset (every `every`-th epoch of each event) stay within `tol` (relative) of a converged
+reference.  The reference is the same path in FP64 on a fine grid (n_r_ref x n_theta_ref);
+it is trusted on an epoch when halving its radial resolution moves it by less than tol/3
+(a Richardson-style check: the quadrature's error falls at least linearly with N_r), and
+untrusted epochs are left out of the choice and counted.  Precision: FP32 rays (with the
+FP64 pass for sectors over the rounding budget) when they keep the same tolerance, which
+they do wherever the FP64 pass is active.  Everything runs through the HIP library.
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+
+import numpy as np
+import torch
+
+from . import icrs
+from .workloads import Workload
+
+GRID_CANDIDATES = [(32, 128), (32, 256), (48, 256), (64, 256), (48, 384), (64, 384), (96, 384), (64, 512),
+                   (96, 512), (128, 512), (128, 768), (192, 768), (256, 1024)]
+
+
+@dataclasses.dataclass
+class TuneResult:
+    n_r: int
+    n_theta: int
+    ray_precision: str
+    tol: float
+    n_calibration: int
+    n_trusted: int
+    errors: list          # (n_r, n_theta, max rel err, 99.9th percentile) per candidate tried
+    timings: dict         # ray precision -> epochs/s on the calibration subset at the chosen grid
+
+
+def _mag(w: Workload, n_r, n_theta, rays, roots, n_limb=None):
+    h = icrs.Handle(n_lens=w.n_lens, n_limb=n_limb or w.n_limb, n_r=n_r, n_theta=n_theta, ray_precision=rays,
+                    root_precision=roots)
+    t = torch.tensor(w.t, device="cuda")
+    mag, _ = h.magnification(w.params, w.offsets, t)
+    return mag.cpu().numpy()
+
+
+def _rate(w: Workload, n_r, n_theta, rays, roots, reps=2):
+    h = icrs.Handle(n_lens=w.n_lens, n_limb=w.n_limb, n_r=n_r, n_theta=n_theta, ray_precision=rays,
+                    root_precision=roots)
+    t = torch.tensor(w.t, device="cuda")
+    ws = h.workspace(w.n_events, w.n_epochs)
+    h.magnification(w.params, w.offsets, t, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        h.magnification(w.params, w.offsets, t, workspace=ws)
+    torch.cuda.synchronize()
+    return w.n_epochs * reps / (time.perf_counter() - t0)
+
+
+def tune(w: Workload, tol=3e-5, every=100, n_r_ref=512, n_theta_ref=1024, candidates=GRID_CANDIDATES,
+         roots="fp32", verbose=False) -> TuneResult:
+    cal = w.sample_epochs(every)
+    ref = _mag(cal, n_r_ref, n_theta_ref, "fp64", "fp64")
+    half = _mag(cal, n_r_ref // 2, n_theta_ref, "fp64", "fp64")
+    trusted = np.abs(half / ref - 1.0) <= tol / 3.0
+    if verbose:
+        print(f"[autotune] {cal.n_epochs} calibration epochs, {trusted.sum()} with a converged reference",
+              flush=True)
+    errors = []
+    chosen = None
+    for n_r, n_theta in sorted(candidates, key=lambda g: (g[0] * g[1], g[1])):
+        m = _mag(cal, n_r, n_theta, "fp32", roots)
+        rel = np.abs(m[trusted] / ref[trusted] - 1.0)
+        errors.append((n_r, n_theta, float(rel.max()), float(np.quantile(rel, 0.999))))
+        if verbose:
+            print(f"[autotune] {n_r} x {n_theta}: max rel err {rel.max():.2e}", flush=True)
+        if rel.max() <= tol:
+            chosen = (n_r, n_theta)
+            break
+    if chosen is None:
+        chosen = max(candidates, key=lambda g: g[0] * g[1])
+    timings = {p: _rate(cal, chosen[0], chosen[1], p, roots) for p in ("fp32", "fp64")}
+    rays = max(timings, key=timings.get)
+    return TuneResult(chosen[0], chosen[1], rays, tol, int(cal.n_epochs), int(trusted.sum()), errors, timings)

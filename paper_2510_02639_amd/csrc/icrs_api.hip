@@ -59,6 +59,35 @@ Layout layout_for(int64_t n_events, int64_t n_epochs) {
   return L;
 }
 
+// Extra blocks of the learned path, after the plain layout.
+struct LearnedLayout {
+  size_t cimg, cn, a_c, a_ring, add, flags, ext, feat, y, lists, counts, total;
+};
+
+LearnedLayout learned_layout(int n_lens, int64_t n_events, int64_t n_epochs) {
+  LearnedLayout L;
+  size_t o = layout_for(n_events, n_epochs).total;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  const size_t E = (size_t)n_epochs, MI = (size_t)(n_lens * n_lens + 1);
+  L.cimg = take(E * ICRS_MAX_SECTORS * 2 * sizeof(double));
+  L.cn = take(E * sizeof(int32_t));
+  L.a_c = take(E * sizeof(double));
+  L.a_ring = take(E * sizeof(double));
+  L.add = take(E * sizeof(double));
+  L.flags = take(E * sizeof(uint32_t));
+  L.ext = take(E * MI * 4 * sizeof(double));
+  L.feat = take(E * MI * 10 * sizeof(float));
+  L.y = take(E * MI * 4 * sizeof(float));
+  L.lists = take(2 * E * sizeof(int32_t));
+  L.counts = take(64);
+  L.total = o;
+  return L;
+}
+
 bool config_ok(const icrs_config* c) {
   if (!c || c->abi_version != ICRS_ABI_VERSION) return false;
   if (c->n_lens != 2 && c->n_lens != 3) return false;
@@ -184,11 +213,23 @@ icrs_status prepare(icrs_handle* h, int64_t n_events, const double* params, cons
 }
 
 // rays + finalize with up to max_retries widening passes
+// Which epochs and grid one ray call covers: all epochs on the handle's grid by default.
+struct RaySet {
+  const int32_t* list = nullptr;  // epochs (device), or all when null
+  int64_t n = -1;                 // list length (host-known)
+  int n_r = 0, n_theta = 0;       // grid; 0 = the handle's
+  const double* add_mag = nullptr;
+};
+
 icrs_status run_rays(icrs_handle* h, const Views& v, int max_retries, double* mag, uint32_t* status,
-                     uint32_t extra_status) {
-  const icrs_config& c = h->cfg;
+                     uint32_t extra_status, const RaySet& rs = RaySet{}) {
+  icrs_config c = h->cfg;
+  if (rs.n_r) c.n_r = rs.n_r;
+  if (rs.n_theta) c.n_theta = rs.n_theta;
   RayWork w;
-  w.n = v.b.n_epochs;
+  w.list = rs.list;
+  w.n = rs.list ? rs.n : v.b.n_epochs;
+  if (w.n <= 0) return ICRS_OK;
   int32_t* cur = v.list_a;
   int32_t* nxt = v.list_b;
   unsigned long long* passes = (unsigned long long*)(v.counters + 8);
@@ -211,7 +252,7 @@ icrs_status run_rays(icrs_handle* h, const Views& v, int max_retries, double* ma
     ICRS_TRY(icrs::launch_fill_i32(v.counters, 1, 0, h->stream));
     ICRS_TRY(tm.begin());
     ICRS_TRY(icrs::launch_finalize(v.b, v.sec, w, v.partial, v.clip, attempt, max_retries, nxt, v.counters, mag,
-                                   status, extra_status, h->profiling ? passes : nullptr, h->stream));
+                                   status, extra_status, h->profiling ? passes : nullptr, h->stream, rs.add_mag));
     ICRS_TRY(tm.end(&h->prof.ms_finalize));
     ICRS_TRY(tm.flush());
     if (h->profiling && attempt == 0) {
@@ -221,8 +262,10 @@ icrs_status run_rays(icrs_handle* h, const Views& v, int max_retries, double* ma
       ICRS_TRY(hipMemcpyAsync(&np, passes, sizeof(np), hipMemcpyDeviceToHost, h->stream));
       ICRS_TRY(hipMemcpyAsync(&nfb, v.counters + 4, sizeof(nfb), hipMemcpyDeviceToHost, h->stream));
       ICRS_TRY(hipStreamSynchronize(h->stream));
+      const int64_t main = (int64_t)np - (c.ray_precision == ICRS_FP32 ? (int64_t)nfb : 0);
       h->prof.n_main_launches += 1;
-      h->prof.n_main_sectors += (int64_t)np - (c.ray_precision == ICRS_FP32 ? (int64_t)nfb : 0);
+      h->prof.n_main_sectors += main;
+      h->prof.n_main_rays += main * (int64_t)c.n_r * c.n_theta;
     }
     if (attempt >= max_retries) break;
     int32_t count = 0;
@@ -241,7 +284,7 @@ icrs_status run_rays(icrs_handle* h, const Views& v, int max_retries, double* ma
     ICRS_TRY(hipMemcpyAsync(&np, passes, sizeof(np), hipMemcpyDeviceToHost, h->stream));
     ICRS_TRY(hipStreamSynchronize(h->stream));
     h->prof.n_sector_passes += (int64_t)np;
-    h->prof.n_epochs += v.b.n_epochs;
+    h->prof.n_epochs += rs.list ? rs.n : v.b.n_epochs;
     h->prof.n_calls += 1;
   }
   return ICRS_OK;
@@ -503,6 +546,133 @@ icrs_status icrs_mlp_adamw(icrs_handle* h, float* params, const float* grad, flo
   if (packed && ((uintptr_t)packed & 15u)) return ICRS_EINVAL;
   return hip_status(icrs::mlp::launch_adamw(params, grad, m, v, step, lr, beta1, beta2, eps, weight_decay, packed,
                                             h->stream));
+}
+
+size_t icrs_learned_workspace_bytes(const icrs_handle* h, int64_t n_events, int64_t n_epochs) {
+  if (!h || n_events < 0 || n_epochs < 0) return 0;
+  return learned_layout(h->cfg.n_lens, n_events, n_epochs).total;
+}
+
+void icrs_default_learned_config(icrs_learned_config* lc) {
+  if (!lc) return;
+  memset(lc, 0, sizeof(*lc));
+  lc->n_check = 16;
+  lc->n_r = 128;
+  lc->n_theta = 512;
+  lc->log_safety = 0.0;
+  lc->prune_ratio = 1e-6;
+  lc->vary_max = 0.1;
+  lc->gate_rel = 1e-3;
+}
+
+icrs_status icrs_image_bounds(icrs_handle* h, int64_t n_events, const double* params, const int64_t* epoch_offsets,
+                              int64_t n_epochs, const double* t, float* features, float* targets,
+                              int32_t* n_images, uint32_t* flags, void* workspace, size_t workspace_bytes) {
+  if (!h || !events_ok(h->cfg, n_events, params, epoch_offsets, n_epochs)) return ICRS_EINVAL;
+  if (n_epochs > 0 && (!t || !features || !targets || !n_images || !flags)) return ICRS_EINVAL;
+  const LearnedLayout LL = learned_layout(h->cfg.n_lens, n_events, n_epochs);
+  if (workspace && workspace_bytes < LL.total) return ICRS_ENOMEM;
+  Views v;
+  const icrs_status ps = prepare(h, n_events, params, epoch_offsets, n_epochs, t, workspace, workspace_bytes, &v);
+  if (ps != ICRS_OK || n_epochs == 0) return ps;
+  char* base = (char*)workspace;
+  const icrs_config& c = h->cfg;
+  const int fp32_roots = c.root_precision == ICRS_FP32;
+  double* cimg = (double*)(base + LL.cimg);
+  ICRS_TRY(icrs::launch_centre_images(c.n_lens, fp32_roots, v.b, cimg, n_images, (double*)(base + LL.a_c), nullptr,
+                                      h->stream));
+  return hip_status(icrs::launch_image_extents(c.n_lens, fp32_roots, c.n_limb, v.b, cimg, n_images,
+                                               (double*)(base + LL.ext), features, targets,
+                                               (double*)(base + LL.a_ring), flags, h->stream));
+}
+
+icrs_status icrs_magnification_learned(icrs_handle* h, int64_t n_events, const double* params,
+                                       const int64_t* epoch_offsets, int64_t n_epochs, const double* t,
+                                       const icrs_learned_config* lc, const uint16_t* packed,
+                                       const float* mlp_params, const float* norm, double* mag, uint32_t* status,
+                                       icrs_learned_stats* stats, void* workspace, size_t workspace_bytes) {
+  if (!h || !lc || !events_ok(h->cfg, n_events, params, epoch_offsets, n_epochs)) return ICRS_EINVAL;
+  if (h->cfg.n_lens != 2) return ICRS_EUNSUPPORTED;
+  if (lc->n_check < 8 || lc->n_check > 64 || lc->n_r < 4 || lc->n_r > 4096 || lc->n_theta < 64 ||
+      lc->n_theta > 1024 || !(lc->prune_ratio >= 0.0 && lc->prune_ratio < 0.1) || !(lc->vary_max > 0.0) ||
+      !(lc->gate_rel > 0.0) || !(fabs(lc->log_safety) < 10.0))
+    return ICRS_EINVAL;
+  if (n_epochs > 0 && (!t || !mag || !status || !packed || !mlp_params || !norm)) return ICRS_EINVAL;
+  if (packed && ((uintptr_t)packed & 15u)) return ICRS_EINVAL;
+  const LearnedLayout LL = learned_layout(h->cfg.n_lens, n_events, n_epochs);
+  if (workspace && workspace_bytes < LL.total) return ICRS_ENOMEM;
+  Views v;
+  const icrs_status ps = prepare(h, n_events, params, epoch_offsets, n_epochs, t, workspace, workspace_bytes, &v);
+  if (ps != ICRS_OK) return ps;
+  if (stats) memset(stats, 0, sizeof(*stats));
+  if (n_epochs == 0) return ICRS_OK;
+  char* base = (char*)workspace;
+  const icrs_config& c = h->cfg;
+  const int fp32_roots = c.root_precision == ICRS_FP32;
+  const int MI = c.n_lens * c.n_lens + 1;
+  double* cimg = (double*)(base + LL.cimg);
+  int32_t* cn = (int32_t*)(base + LL.cn);
+  double* a_c = (double*)(base + LL.a_c);
+  double* a_ring = (double*)(base + LL.a_ring);
+  double* add = (double*)(base + LL.add);
+  uint32_t* flags = (uint32_t*)(base + LL.flags);
+  double* ext = (double*)(base + LL.ext);
+  float* feat = (float*)(base + LL.feat);
+  float* y = (float*)(base + LL.y);
+  int32_t* lists = (int32_t*)(base + LL.lists);
+  int32_t* counts = (int32_t*)(base + LL.counts);
+  Timer tm(h);
+  ICRS_TRY(tm.begin());
+  ICRS_TRY(icrs::launch_centre_images(c.n_lens, fp32_roots, v.b, cimg, cn, a_c, status, h->stream));
+  ICRS_TRY(tm.end(&h->prof.ms_centre));
+  ICRS_TRY(tm.begin());
+  ICRS_TRY(icrs::launch_image_extents(c.n_lens, fp32_roots, lc->n_check, v.b, cimg, cn, ext, feat, nullptr, a_ring,
+                                      flags, h->stream));
+  ICRS_TRY(icrs::mlp::launch_forward(packed, mlp_params, norm, n_epochs * MI, feat, y, h->stream));
+  ICRS_TRY(icrs::launch_fill_i32(counts, 4, 0, h->stream));
+  ICRS_TRY(icrs::launch_learned_sectors(c.n_lens, v.b, cimg, cn, a_c, a_ring, ext, y, lc->log_safety,
+                                        lc->prune_ratio, lc->vary_max, flags, v.sec, add, lists, counts, counts + 2,
+                                        h->stream));
+  ICRS_TRY(tm.end(&h->prof.ms_limb_sectors));
+  ICRS_TRY(tm.flush());
+  int32_t cnt[4] = {0, 0, 0, 0};
+  ICRS_TRY(hipMemcpyAsync(cnt, counts, sizeof(cnt), hipMemcpyDeviceToHost, h->stream));
+  ICRS_TRY(hipStreamSynchronize(h->stream));
+  const int64_t n_learned = cnt[0];
+  RaySet rs;
+  rs.list = lists;
+  rs.n = n_learned;
+  rs.n_r = lc->n_r;
+  rs.n_theta = lc->n_theta;
+  rs.add_mag = add;
+  icrs_status st = run_rays(h, v, c.max_retries, mag, status, ICRS_ST_LEARNED, rs);
+  if (st != ICRS_OK) return st;
+  ICRS_TRY(icrs::launch_learned_gate(v.b, lists, counts, n_learned, a_c, a_ring, mag, status, lc->gate_rel, flags,
+                                     lists, counts, h->stream));
+  int32_t cnt2[4] = {0, 0, 0, 0};
+  ICRS_TRY(hipMemcpyAsync(cnt2, counts, sizeof(cnt2), hipMemcpyDeviceToHost, h->stream));
+  ICRS_TRY(hipStreamSynchronize(h->stream));
+  const int64_t n_fb = cnt2[1];
+  if (n_fb > 0) {
+    const int32_t* fb = lists + n_epochs;
+    ICRS_TRY(tm.begin());
+    ICRS_TRY(icrs::launch_limb_sectors(c.n_lens, fp32_roots, c.n_limb, v.b, v.sec, status, h->stream, fb, n_fb));
+    ICRS_TRY(tm.end(&h->prof.ms_limb_sectors));
+    ICRS_TRY(tm.flush());
+    RaySet fs;
+    fs.list = fb;
+    fs.n = n_fb;
+    st = run_rays(h, v, c.max_retries, mag, status, ICRS_ST_FALLBACK, fs);
+    if (st != ICRS_OK) return st;
+  }
+  if (stats) {
+    stats->n_epochs = n_epochs;
+    stats->n_fallback = n_fb;
+    stats->n_gate_rejected = n_fb - cnt[1];
+    stats->n_learned = n_learned - stats->n_gate_rejected;
+    stats->n_pruned_images = cnt[2];
+  }
+  return ICRS_OK;
 }
 
 const char* icrs_status_string(icrs_status s) {

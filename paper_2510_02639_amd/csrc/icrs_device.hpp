@@ -26,6 +26,8 @@ constexpr uint32_t kStCapOverflow = 4u;
 constexpr uint32_t kStClip = 8u;
 constexpr uint32_t kStNan = 16u;
 constexpr uint32_t kStGiven = 64u;
+constexpr uint32_t kStLearned = 128u;
+constexpr uint32_t kStFallback = 256u;
 
 // parameter vector layout: [s, q, u0, alpha, t0, tE, rho, u_ld, q3, r3, psi]
 constexpr int kParams = 11;

@@ -28,9 +28,10 @@ hipError_t launch_epoch_event(const Batch& b, int32_t* epoch_event, hipStream_t 
 hipError_t launch_centre_images(int n_lens, int root_fp32, const Batch& b, double* images, int32_t* n_images,
                                 double* a_ps, uint32_t* status, hipStream_t s);
 
-// limb images + sectors (one workgroup per epoch); ORs status bits
+// limb images + sectors (one workgroup per epoch); ORs status bits.  With list, only the
+// n_list epochs it names.
 hipError_t launch_limb_sectors(int n_lens, int root_fp32, int n_limb, const Batch& b, const SectorBuf& out,
-                               uint32_t* status, hipStream_t s);
+                               uint32_t* status, hipStream_t s, const int32_t* list = nullptr, int64_t n_list = 0);
 
 struct RayWork {
   const int32_t* list = nullptr;    // epochs to process (all their sectors), or nullptr = 0..n-1
@@ -52,11 +53,12 @@ hipError_t launch_rays(int n_lens, int ray_fp32, int stage, const Batch& b, cons
                        unsigned long long* queue, int32_t* fallback, int32_t* n_fallback, hipStream_t s);
 
 // sums sector fluxes into magnifications; epochs with edge touches and retries left get
-// widened sectors and are appended to next_list (count in *next_count)
+// widened sectors and are appended to next_list (count in *next_count).  add_mag (or null):
+// a per-epoch term added to the magnification (images given no grid).
 hipError_t launch_finalize(const Batch& b, const SectorBuf& sec, const RayWork& w, const double* partial,
                            const uint8_t* clip, int attempt, int max_retries, int32_t* next_list,
                            int32_t* next_count, double* mag, uint32_t* status, uint32_t extra_status,
-                           unsigned long long* passes, hipStream_t s);
+                           unsigned long long* passes, hipStream_t s, const double* add_mag = nullptr);
 
 // frozen-structure Jacobian jac[n_epochs][11] (and mag if non-null) on the given sectors;
 // with cot and grad non-null also grad[n_events][11] = sum_e cot[e] jac[e]
@@ -65,6 +67,19 @@ hipError_t launch_adjoint(int n_lens, const Batch& b, const SectorBuf& sec, int 
                           hipStream_t s);
 
 hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+
+// learned-bounds path (icrs_learned.hip)
+hipError_t launch_image_extents(int n_lens, int root_fp32, int n_pts, const Batch& b, const double* cimg,
+                                const int32_t* cn, double* ext, float* feat, float* tgt, double* a_ring,
+                                uint32_t* flags, hipStream_t s);
+hipError_t launch_learned_sectors(int n_lens, const Batch& b, const double* cimg, const int32_t* cn,
+                                  const double* a_c, const double* a_ring, const double* ext, const float* y,
+                                  double log_safety, double prune_ratio, double vary_max, uint32_t* flags,
+                                  const SectorBuf& sec, double* add_mag, int32_t* lists, int32_t* counts,
+                                  int32_t* n_pruned, hipStream_t s);
+hipError_t launch_learned_gate(const Batch& b, const int32_t* learned, const int32_t* n_learned, int64_t n_max,
+                               const double* a_c, const double* a_ring, const double* mag, uint32_t* status,
+                               double gate_rel, uint32_t* flags, int32_t* lists, int32_t* counts, hipStream_t s);
 
 namespace mlp {
 // learned-bounds network: FP32 master blob (param_floats()), packed bf16 weights

@@ -63,7 +63,8 @@ __global__ __launch_bounds__(256) void centre_images_kernel(Batch b, double* __r
 
 template <int N, typename T>
 __global__ __launch_bounds__(256) void limb_sectors_kernel(Batch b, int n_limb, SectorBuf out,
-                                                           uint32_t* __restrict__ status) {
+                                                           uint32_t* __restrict__ status,
+                                                           const int32_t* __restrict__ list) {
   constexpr int MI = N * N + 1;  // images per source point at most
   constexpr int cap = 5 * (N - 1);
   extern __shared__ double pts[];  // [blockDim.x * MI] r, then [blockDim.x * MI] theta
@@ -78,7 +79,7 @@ __global__ __launch_bounds__(256) void limb_sectors_kernel(Batch b, int n_limb, 
   __shared__ Sector S[kMaxCand];
   __shared__ uint32_t st_sh;
 
-  const int64_t e = blockIdx.x;
+  const int64_t e = list ? (int64_t)list[blockIdx.x] : (int64_t)blockIdx.x;
   const int tid = threadIdx.x;
   const double* p = b.params + (int64_t)b.epoch_event[e] * kParams;
   const double rho = p[6];
@@ -305,21 +306,22 @@ hipError_t launch_centre_images(int n_lens, int root_fp32, const Batch& b, doubl
 }
 
 hipError_t launch_limb_sectors(int n_lens, int root_fp32, int n_limb, const Batch& b, const SectorBuf& out,
-                               uint32_t* status, hipStream_t s) {
-  if (b.n_epochs == 0) return hipSuccess;
+                               uint32_t* status, hipStream_t s, const int32_t* list, int64_t n_list) {
+  const int64_t n = list ? n_list : b.n_epochs;
+  if (n <= 0) return hipSuccess;
   const int bs = ((n_limb + 63) / 64) * 64;
-  const dim3 g((unsigned)b.n_epochs), blk(bs);
+  const dim3 g((unsigned)n), blk(bs);
   const size_t lds = (size_t)bs * (n_lens * n_lens + 1) * 2 * sizeof(double);
   if (n_lens == 2) {
     if (root_fp32)
-      hipLaunchKernelGGL((limb_sectors_kernel<2, float>), g, blk, lds, s, b, n_limb, out, status);
+      hipLaunchKernelGGL((limb_sectors_kernel<2, float>), g, blk, lds, s, b, n_limb, out, status, list);
     else
-      hipLaunchKernelGGL((limb_sectors_kernel<2, double>), g, blk, lds, s, b, n_limb, out, status);
+      hipLaunchKernelGGL((limb_sectors_kernel<2, double>), g, blk, lds, s, b, n_limb, out, status, list);
   } else {
     if (root_fp32)
-      hipLaunchKernelGGL((limb_sectors_kernel<3, float>), g, blk, lds, s, b, n_limb, out, status);
+      hipLaunchKernelGGL((limb_sectors_kernel<3, float>), g, blk, lds, s, b, n_limb, out, status, list);
     else
-      hipLaunchKernelGGL((limb_sectors_kernel<3, double>), g, blk, lds, s, b, n_limb, out, status);
+      hipLaunchKernelGGL((limb_sectors_kernel<3, double>), g, blk, lds, s, b, n_limb, out, status, list);
   }
   return hipGetLastError();
 }

@@ -26,9 +26,10 @@ constexpr int kWaves = 4;
 // MapF32 works relative to the sector's FP64 anchor z_s = r_s e^{i theta_s} (box centre):
 // with dz = z - z_s = r e^{i theta_s}(e^{i dtheta} - 1) + (r - r_s) e^{i theta_s},
 // u_k = z - a_k and h_k = eps_k/(z_s - a_k),
-//   w - w_c = (w(z_s) - w_c) + dz + sum_k conj(dz h_k / u_k),
-// an identity with no cancellation, so FP32 rounding scales with |dz| (the sector's size)
-// instead of |z|.
+//   w - w_c = (w(z_s) - w_c) + dz + conj(dz sum_k h_k / u_k),
+// an identity with no cancellation (each lens term eps_k/conj(u_k) minus its anchor value
+// is -conj(dz h_k / u_k)), so FP32 rounding scales with |dz| (the sector's size) instead of
+// |z|.
 template <int N, int JMAX>
 struct MapF64 {
   using T = double;
@@ -117,20 +118,21 @@ struct MapF32 {
     ex = (float)dr_i * ux0;
     ey = (float)dr_i * uy0;
   }
+  // w - w_c = B + dz + conj(dz G), G = sum_k h_k / u_k (dz factored out of the lens sum)
   __device__ __forceinline__ float d2(int j) const {
     const float dzx = fmaf(r, gx[j], ex), dzy = fmaf(r, gy[j], ey);
-    float Dx = bx + dzx, Dy = by + dzy;
+    float Gx = 0.0f, Gy = 0.0f;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
       const float ux = ax[k] + dzx, uy = ay[k] + dzy;
       const float inv = __builtin_amdgcn_rcpf(fmaf(ux, ux, uy * uy));
-      const float px = fmaf(dzx, hx[k], -dzy * hy[k]);
-      const float py = fmaf(dzx, hy[k], dzy * hx[k]);
-      const float qx = fmaf(px, ux, py * uy);  // p conj(u)
-      const float qy = fmaf(py, ux, -px * uy);
-      Dx = fmaf(qx, inv, Dx);
-      Dy = fmaf(-qy, inv, Dy);
+      const float px = fmaf(hx[k], ux, hy[k] * uy);  // h conj(u)
+      const float py = fmaf(hy[k], ux, -hx[k] * uy);
+      Gx = fmaf(px, inv, Gx);
+      Gy = fmaf(py, inv, Gy);
     }
+    const float Dx = (bx + dzx) + fmaf(dzx, Gx, -dzy * Gy);
+    const float Dy = (by + dzy) - fmaf(dzx, Gy, dzy * Gx);
     return fmaf(Dx, Dx, Dy * Dy);
   }
 };
@@ -160,6 +162,44 @@ __device__ inline double fp32_error_bound(const Lens<N>& L, const double* sp, bo
   return 5.96e-8 * (1.0 + dz * amp / rho);
 }
 constexpr double kFp32Budget = 6e-5;  // per-node distance error (relative to rho) allowed in FP32
+
+// Lower bound of d = |w(z) - w_c| over the arc z = z0 e^{i phi}, |phi| <= Phi, z0 = r e^{i theta_c}.
+// w(z) = z + f(conj z) with f holomorphic, so for Delta = z - z0:
+//   w(z) = w0 + Delta + K conj(Delta) + R2,  K = f'(conj z0) = sum_k eps_k / conj(z0 - a_k)^2,
+//   |R2| <= sum_k eps_k / dmin_k^3 |Delta|^2   (dmin_k: lens k's distance to the arc's disc),
+// and Delta = i z0 phi + e with |e| <= r phi^2 / 2, |Delta| <= r Phi.  The linear part traces
+// the segment c + v phi (c = w0 - w_c, v = i z0 + K conj(i z0)); its distance to the origin
+// less the two remainder bounds is the bound.  Returns 0 when a lens is within r Phi of z0.
+template <int N>
+__device__ inline double arc_distance_lower_bound(const Lens<N>& L, c64 wc, double r, double cth, double sth,
+                                                  double Phi) {
+  const double zx = r * cth, zy = r * sth;
+  const double R = r * Phi;
+  double wx = zx, wy = zy, kx = 0.0, ky = 0.0, M = 0.0;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const double ux = zx - L.a[k].x, uy = zy - L.a[k].y;
+    const double u2 = fma(ux, ux, uy * uy);
+    const double dmin = sqrt(u2) - R;
+    if (!(dmin > 0.0)) return 0.0;
+    const double inv = 1.0 / u2;
+    const double gx = L.eps[k] * ux * inv, gy = L.eps[k] * uy * inv;  // eps / conj(u)
+    wx -= gx;
+    wy -= gy;
+    kx += (gx * ux - gy * uy) * inv;  // eps / conj(u)^2 = (eps / conj(u)) (u / |u|^2)
+    ky += (gx * uy + gy * ux) * inv;
+    M += L.eps[k] / (dmin * dmin * dmin);
+  }
+  const double tx = -zy, ty = zx;  // i z0
+  const double vx = tx + (kx * tx + ky * ty), vy = ty + (ky * tx - kx * ty);
+  const double cx = wx - wc.x, cy = wy - wc.y;
+  const double vv = fma(vx, vx, vy * vy);
+  double phi = vv > 0.0 ? -(cx * vx + cy * vy) / vv : 0.0;
+  phi = fmin(fmax(phi, -Phi), Phi);
+  const double ex = fma(vx, phi, cx), ey = fma(vy, phi, cy);
+  const double E = (1.0 + sqrt(fma(kx, kx, ky * ky))) * 0.5 * r * Phi * Phi + M * R * R;
+  return sqrt(fma(ex, ex, ey * ey)) - E;
+}
 
 // Wave-uniform boundary words of chunk j: inside nodes whose left (side 0) or right
 // (side 1) neighbour is outside or beyond a non-periodic edge.
@@ -203,7 +243,30 @@ __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L
   int clip = 0;
   T* buf = rowbuf_all + wave * (JMAX * 64);
 
-  for (int i = wave; i < n_r; i += kWaves) {
+  // Chunk culling: a 64-column chunk of a row is skipped when the arc through it, widened
+  // by two columns on each side, provably maps farther than rho (1 + 1e-3) from the source
+  // centre -- beyond the FP32 map's rounding budget, so every node there would be outside,
+  // and no crossing stencil (at most two columns from an inside node) reaches into it.
+  // One test pass per wave covers G = 64 / J of its rows: lane (st, jt) tests chunk jt of
+  // the st-th next row.  Skipping changes no result bit.
+  const int G = 64 / J;
+  const int jt = lane % J, st = lane / J;
+  double tcs, tsn;
+  sincos(sp[2] + (64.0 * jt + 32.0) * dth, &tsn, &tcs);
+  const double Phi = 34.0 * dth;
+  uint64_t skipmask = 0;
+  int it = 0;
+  for (int i = wave; i < n_r; i += kWaves, ++it) {
+    const int s = it % G;
+    if (s == 0) {
+      bool sk = false;
+      const int is = i + kWaves * st;
+      if (st < G && is < n_r)
+        sk = arc_distance_lower_bound<N>(L, wc, r_lo + (is + 0.5) * dr, tcs, tsn, Phi) > rho_d * 1.001;
+      skipmask = __ballot(sk);
+    }
+    const uint32_t rowskip = (uint32_t)(skipmask >> (s * J)) & ((1u << J) - 1u);
+    if (rowskip == (1u << J) - 1u) continue;  // the whole row misses the image
     const double r = r_lo + (i + 0.5) * dr;
     map.init_row(r, (i + 0.5 - 0.5 * n_r) * dr);
     uint64_t m[JMAX];
@@ -212,7 +275,7 @@ __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L
 #pragma unroll
     for (int j = 0; j < JMAX; ++j) {
       m[j] = 0;
-      if (EXACT || j < J) {
+      if ((EXACT || j < J) && !((rowskip >> j) & 1u)) {
         T d2 = map.d2(j);
         if (!EXACT) d2 = (lane + 64 * j < n_theta) ? d2 : T(__builtin_inf());
         const bool in = d2 < rho2;
@@ -385,7 +448,7 @@ __global__ void finalize_kernel(Batch b, SectorBuf sec, RayWork w, const double*
                                 const uint8_t* __restrict__ clip, int attempt, int max_retries,
                                 int32_t* __restrict__ next_list, int32_t* __restrict__ next_count,
                                 double* __restrict__ mag, uint32_t* __restrict__ status, uint32_t extra_status,
-                                unsigned long long* __restrict__ passes) {
+                                unsigned long long* __restrict__ passes, const double* __restrict__ add_mag) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (w.n_dev ? (int64_t)(*w.n_dev) : w.n)) return;
   const int64_t e = w.list ? (int64_t)w.list[idx] : idx;
@@ -426,7 +489,7 @@ __global__ void finalize_kernel(Batch b, SectorBuf sec, RayWork w, const double*
   const double rho = b.params[(int64_t)b.epoch_event[e] * kParams + 6];
   uint32_t st = status[e] | extra_status;
   if (any) st |= kStClip;
-  const double m = flux / (rho * rho);
+  const double m = flux / (rho * rho) + (add_mag ? add_mag[e] : 0.0);
   if (!isfinite(m)) st |= kStNan;
   mag[e] = m;
   status[e] = st;
@@ -508,10 +571,10 @@ hipError_t launch_rays(int n_lens, int ray_fp32, int stage, const Batch& b, cons
 hipError_t launch_finalize(const Batch& b, const SectorBuf& sec, const RayWork& w, const double* partial,
                            const uint8_t* clip, int attempt, int max_retries, int32_t* next_list,
                            int32_t* next_count, double* mag, uint32_t* status, uint32_t extra_status,
-                           unsigned long long* passes, hipStream_t s) {
+                           unsigned long long* passes, hipStream_t s, const double* add_mag) {
   if (w.n == 0) return hipSuccess;
   hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)((w.n + 255) / 256)), dim3(256), 0, s, b, sec, w, partial, clip,
-                     attempt, max_retries, next_list, next_count, mag, status, extra_status, passes);
+                     attempt, max_retries, next_list, next_count, mag, status, extra_status, passes, add_mag);
   return hipGetLastError();
 }
 

@@ -36,7 +36,22 @@ class icrs_profile(ctypes.Structure):
     _fields_ = [("ms_centre", ctypes.c_double), ("ms_limb_sectors", ctypes.c_double), ("ms_rays", ctypes.c_double),
                 ("ms_finalize", ctypes.c_double), ("n_calls", ctypes.c_int64), ("n_rays_launches", ctypes.c_int64),
                 ("n_sector_passes", ctypes.c_int64), ("n_epochs", ctypes.c_int64), ("ms_rays_main", ctypes.c_double),
-                ("n_main_launches", ctypes.c_int64), ("n_main_sectors", ctypes.c_int64)]
+                ("n_main_launches", ctypes.c_int64), ("n_main_sectors", ctypes.c_int64),
+                ("n_main_rays", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class icrs_learned_config(ctypes.Structure):
+    _fields_ = [("n_check", ctypes.c_int32), ("n_r", ctypes.c_int32), ("n_theta", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("log_safety", ctypes.c_double), ("prune_ratio", ctypes.c_double),
+                ("vary_max", ctypes.c_double), ("gate_rel", ctypes.c_double)]
+
+
+class icrs_learned_stats(ctypes.Structure):
+    _fields_ = [("n_epochs", ctypes.c_int64), ("n_learned", ctypes.c_int64), ("n_fallback", ctypes.c_int64),
+                ("n_gate_rejected", ctypes.c_int64), ("n_pruned_images", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -95,6 +110,14 @@ def lib():
     L.icrs_mlp_loss_grad.restype = ctypes.c_int
     L.icrs_mlp_adamw.argtypes = [vp, vp, vp, vp, vp, i64, f32, f32, f32, f32, f32, vp]
     L.icrs_mlp_adamw.restype = ctypes.c_int
+    L.icrs_image_bounds.argtypes = [vp, i64, vp, vp, i64, vp, vp, vp, vp, vp, vp, sz]
+    L.icrs_image_bounds.restype = ctypes.c_int
+    L.icrs_default_learned_config.argtypes = [ctypes.POINTER(icrs_learned_config)]
+    L.icrs_learned_workspace_bytes.argtypes = [vp, i64, i64]
+    L.icrs_learned_workspace_bytes.restype = sz
+    L.icrs_magnification_learned.argtypes = [vp, i64, vp, vp, i64, vp, ctypes.POINTER(icrs_learned_config), vp, vp,
+                                             vp, vp, vp, ctypes.POINTER(icrs_learned_stats), vp, sz]
+    L.icrs_magnification_learned.restype = ctypes.c_int
     L.icrs_status_string.argtypes = [ctypes.c_int]
     L.icrs_status_string.restype = ctypes.c_char_p
     _lib = L
@@ -105,7 +128,9 @@ EXPORTED = ["icrs_default_config", "icrs_create", "icrs_destroy", "icrs_workspac
             "icrs_magnification_given", "icrs_magnification_vjp", "icrs_get_sectors", "icrs_point_images",
             "icrs_prepare", "icrs_run", "icrs_set_profiling",
             "icrs_get_profile", "icrs_mlp_pack", "icrs_mlp_forward", "icrs_mlp_workspace_bytes",
-            "icrs_mlp_loss_grad", "icrs_mlp_adamw", "icrs_status_string"]
+            "icrs_mlp_loss_grad", "icrs_mlp_adamw", "icrs_image_bounds", "icrs_default_learned_config",
+            "icrs_learned_workspace_bytes", "icrs_magnification_learned", "icrs_status_string"]
+ST_LEARNED, ST_FALLBACK = 128, 256
 MLP_PARAM_FLOATS, MLP_PACKED_HALFS, MLP_NORM_FLOATS = 39312, 75776, 32
 
 
@@ -248,6 +273,50 @@ class Handle:
                                             _ptr(M), _ptr(ws), ws.numel())
         _check(code, "icrs_magnification_vjp")
         return grad, J, M
+
+    # ---- learned-bounds path ----------------------------------------------------------------
+    def learned_workspace(self, n_events, n_epochs):
+        n = lib().icrs_learned_workspace_bytes(self._h, n_events, n_epochs)
+        return torch.empty(max(n, 1), dtype=torch.uint8, device="cuda")
+
+    def image_bounds(self, params, offsets, t, workspace=None):
+        """Training data: (features [E, MI, 10] f32, targets [E, MI, 4] f32, n_images [E] i32,
+        flags [E] u32 as int32), all CUDA."""
+        p, o = _host_events(params, offsets)
+        t = _dev(t, torch.float64)
+        n = t.numel()
+        mi = self.cfg.n_lens ** 2 + 1
+        feat = torch.empty((n, mi, 10), dtype=torch.float32, device=t.device)
+        tgt = torch.empty((n, mi, 4), dtype=torch.float32, device=t.device)
+        nimg = torch.empty(n, dtype=torch.int32, device=t.device)
+        flags = torch.empty(n, dtype=torch.int32, device=t.device)
+        ws = workspace if workspace is not None else self.learned_workspace(p.shape[0], n)
+        _check(lib().icrs_image_bounds(self._h, p.shape[0], _ptr(p), _ptr(o), n, _ptr(t), _ptr(feat), _ptr(tgt),
+                                       _ptr(nimg), _ptr(flags), _ptr(ws), ws.numel()), "icrs_image_bounds")
+        return feat, tgt, nimg, flags
+
+    def magnification_learned(self, params, offsets, t, model, mag=None, status=None, workspace=None,
+                              n_check=16, n_r=None, n_theta=None, prune_ratio=1e-6, vary_max=0.1, gate_rel=1e-3):
+        """Learned-bounds path; model: a learned.BoundsModel.  Returns (mag, status, stats dict)."""
+        p, o = _host_events(params, offsets)
+        t = _dev(t, torch.float64)
+        n = t.numel()
+        lc = icrs_learned_config()
+        lib().icrs_default_learned_config(ctypes.byref(lc))
+        lc.n_check = n_check
+        lc.n_r = n_r if n_r is not None else self.cfg.n_r
+        lc.n_theta = n_theta if n_theta is not None else self.cfg.n_theta
+        lc.log_safety = model.log_safety
+        lc.prune_ratio, lc.vary_max, lc.gate_rel = prune_ratio, vary_max, gate_rel
+        mag = mag if mag is not None else torch.empty(n, dtype=torch.float64, device=t.device)
+        status = status if status is not None else torch.empty(n, dtype=torch.int32, device=t.device)
+        ws = workspace if workspace is not None else self.learned_workspace(p.shape[0], n)
+        st = icrs_learned_stats()
+        _check(lib().icrs_magnification_learned(self._h, p.shape[0], _ptr(p), _ptr(o), n, _ptr(t), ctypes.byref(lc),
+                                                _ptr(model.packed), _ptr(model.params), _ptr(model.norm),
+                                                _ptr(mag), _ptr(status), ctypes.byref(st), _ptr(ws), ws.numel()),
+               "icrs_magnification_learned")
+        return mag, status, st.as_dict()
 
     # ---- learned-bounds network (blob layouts in include/icrs.h) -------------------------
     def mlp_pack(self, params, packed):
