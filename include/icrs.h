@@ -253,7 +253,9 @@ icrs_status icrs_image_bounds(icrs_handle* h, int64_t n_events, const double* pa
  * scaled by exp(log_safety); images with mu < prune_ratio x A_ps get no grid and add mu;
  * epochs whose ring-average point-source magnification differs from the centre's by more
  * than vary_max (relative) go to the plain path before any ray; the drift gate sends back
- * results with |A - A_est| > gate_rel A_ps + |A_ring - A_ps|. */
+ * results with |A - A_est| > gate_rel A_ps + |A_ring - A_ps|; each box is widened by
+ * margin_frac of its extent plus the plain floors (rho/100 in r, rho/(100 r_mid) in theta).
+ * icrs_default_learned_config: 16, 128, 512, 0, 0.0, 1e-6, 0.1, 1e-3, 0.02. */
 typedef struct icrs_learned_config {
   int32_t n_check;
   int32_t n_r;
@@ -263,6 +265,7 @@ typedef struct icrs_learned_config {
   double prune_ratio;
   double vary_max;
   double gate_rel;
+  double margin_frac;
 } icrs_learned_config;
 
 typedef struct icrs_learned_stats {

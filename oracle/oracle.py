@@ -72,6 +72,7 @@ def lib():
                                               P(u32)]
         L.orc_jacobian_given.argtypes = [i, P(d), i64, P(d), i, i, d, i, P(d), P(u8), P(i32), P(d), P(d)]
         L.orc_magnification_frozen.argtypes = [i, P(d), P(d), i64, P(d), i, i, d, i, P(d), P(u8), P(i32), P(d)]
+        L.orc_disk_mag.argtypes = [i, P(d), i64, P(d), i, i, P(d), P(i32)]
         _lib = L
     return _lib
 
@@ -264,3 +265,17 @@ def magnification_frozen(n_lens, p_eval, p_ref, t, sectors, periodic, nsec, n_r=
     lib().orc_magnification_frozen(n_lens, _p(pe), _p(pr), n, _p(t), n_r, n_theta, delta_c, kmax, _p(sectors),
                                    _p(periodic, ctypes.c_uint8), _p(nsec, ctypes.c_int32), _p(mag))
     return mag
+
+
+def disk_mag(n_lens, p, t, n_x=32, n_phi=128):
+    """Brightness-weighted mean of eq. amp_point over the source disk (no image-plane grid;
+    valid where no caustic crosses the disk).  Returns (mag, count_changes) per epoch;
+    count_changes > 0 marks epochs where the reference does not apply."""
+    p = _dbl(p)
+    t = _dbl(np.atleast_1d(t))
+    n = t.size
+    mag = np.zeros(n)
+    ch = np.zeros(n, dtype=np.int32)
+    lib().orc_disk_mag(n_lens, _p(p), n, _p(t), n_x, n_phi, _p(mag), ch.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    return mag, ch
+

@@ -563,6 +563,7 @@ void icrs_default_learned_config(icrs_learned_config* lc) {
   lc->prune_ratio = 1e-6;
   lc->vary_max = 0.1;
   lc->gate_rel = 1e-3;
+  lc->margin_frac = 0.02;
 }
 
 icrs_status icrs_image_bounds(icrs_handle* h, int64_t n_events, const double* params, const int64_t* epoch_offsets,
@@ -595,7 +596,8 @@ icrs_status icrs_magnification_learned(icrs_handle* h, int64_t n_events, const d
   if (h->cfg.n_lens != 2) return ICRS_EUNSUPPORTED;
   if (lc->n_check < 8 || lc->n_check > 64 || lc->n_r < 4 || lc->n_r > 4096 || lc->n_theta < 64 ||
       lc->n_theta > 1024 || !(lc->prune_ratio >= 0.0 && lc->prune_ratio < 0.1) || !(lc->vary_max > 0.0) ||
-      !(lc->gate_rel > 0.0) || !(fabs(lc->log_safety) < 10.0))
+      !(lc->gate_rel > 0.0) || !(fabs(lc->log_safety) < 10.0) ||
+      !(lc->margin_frac >= 0.0 && lc->margin_frac <= 1.0))
     return ICRS_EINVAL;
   if (n_epochs > 0 && (!t || !mag || !status || !packed || !mlp_params || !norm)) return ICRS_EINVAL;
   if (packed && ((uintptr_t)packed & 15u)) return ICRS_EINVAL;
@@ -631,8 +633,8 @@ icrs_status icrs_magnification_learned(icrs_handle* h, int64_t n_events, const d
   ICRS_TRY(icrs::mlp::launch_forward(packed, mlp_params, norm, n_epochs * MI, feat, y, h->stream));
   ICRS_TRY(icrs::launch_fill_i32(counts, 4, 0, h->stream));
   ICRS_TRY(icrs::launch_learned_sectors(c.n_lens, v.b, cimg, cn, a_c, a_ring, ext, y, lc->log_safety,
-                                        lc->prune_ratio, lc->vary_max, flags, v.sec, add, lists, counts, counts + 2,
-                                        h->stream));
+                                        lc->margin_frac, lc->prune_ratio, lc->vary_max, flags, v.sec, add, lists,
+                                        counts, counts + 2, h->stream));
   ICRS_TRY(tm.end(&h->prof.ms_limb_sectors));
   ICRS_TRY(tm.flush());
   int32_t cnt[4] = {0, 0, 0, 0};

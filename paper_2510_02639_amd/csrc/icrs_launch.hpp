@@ -74,9 +74,9 @@ hipError_t launch_image_extents(int n_lens, int root_fp32, int n_pts, const Batc
                                 uint32_t* flags, hipStream_t s);
 hipError_t launch_learned_sectors(int n_lens, const Batch& b, const double* cimg, const int32_t* cn,
                                   const double* a_c, const double* a_ring, const double* ext, const float* y,
-                                  double log_safety, double prune_ratio, double vary_max, uint32_t* flags,
-                                  const SectorBuf& sec, double* add_mag, int32_t* lists, int32_t* counts,
-                                  int32_t* n_pruned, hipStream_t s);
+                                  double log_safety, double margin_frac, double prune_ratio, double vary_max,
+                                  uint32_t* flags, const SectorBuf& sec, double* add_mag, int32_t* lists,
+                                  int32_t* counts, int32_t* n_pruned, hipStream_t s);
 hipError_t launch_learned_gate(const Batch& b, const int32_t* learned, const int32_t* n_learned, int64_t n_max,
                                const double* a_c, const double* a_ring, const double* mag, uint32_t* status,
                                double gate_rel, uint32_t* flags, int32_t* lists, int32_t* counts, hipStream_t s);

@@ -7,8 +7,9 @@
 //      each image's extent,
 //   2. predicts each point-source image's box with the network (offsets in units of the
 //      image's linearised size sigma = rho / |1 - |kappa||),
-//   3. gives every image its own box: network box joined with the sampled extent, the
-//      plain safety margins, merged where boxes overlap; images whose point-source
+//   3. gives every image its own box: network box joined with the sampled extent, a
+//      safety margin (margin_frac of the extent plus the plain floors), merged where boxes
+//      overlap; images whose point-source
 //      magnification is below prune_ratio of the epoch's total get no grid and add their
 //      point-source magnification instead,
 // and the rays and clip retries run as in the plain path.  Epochs that fail a check fall
@@ -176,7 +177,8 @@ template <int N>
 __global__ void learned_sectors_kernel(Batch b, const double* __restrict__ cimg, const int32_t* __restrict__ cn,
                                        const double* __restrict__ a_c, const double* __restrict__ a_ring,
                                        const double* __restrict__ ext, const float* __restrict__ y, double log_safety,
-                                       double prune_ratio, double vary_max, uint32_t* __restrict__ flags,
+                                       double margin_frac, double prune_ratio, double vary_max,
+                                       uint32_t* __restrict__ flags,
                                        SectorBuf sec, double* __restrict__ add_mag, int32_t* __restrict__ lists,
                                        int32_t* __restrict__ counts, int32_t* __restrict__ n_pruned) {
   constexpr int MI = N * N + 1;
@@ -222,7 +224,12 @@ __global__ void learned_sectors_kernel(Batch b, const double* __restrict__ cimg,
       f |= kLfWide;
       break;
     }
-    S[ns++] = candidate_to_sector(r_lo, r_hi, thz + t_lo, thz + t_hi, 0, rho);
+    // safety margin margin_frac x extent plus the plain floors (rho/100 in r, rho/(100 r_mid) in theta)
+    const double mr = margin_frac * (r_hi - r_lo) + rho / 100.0;
+    const double mt = margin_frac * (t_hi - t_lo) + rho / (50.0 * (r_lo + r_hi));
+    Sector sc{fmax(r_lo - mr, 0.0), r_hi + mr, thz + t_lo - mt, thz + t_hi + mt, 0};
+    normalise_theta(sc);
+    S[ns++] = sc;
   }
   if (f) {
     flags[e] = f;
@@ -302,17 +309,17 @@ hipError_t launch_image_extents(int n_lens, int root_fp32, int n_pts, const Batc
 
 hipError_t launch_learned_sectors(int n_lens, const Batch& b, const double* cimg, const int32_t* cn,
                                   const double* a_c, const double* a_ring, const double* ext, const float* y,
-                                  double log_safety, double prune_ratio, double vary_max, uint32_t* flags,
-                                  const SectorBuf& sec, double* add_mag, int32_t* lists, int32_t* counts,
-                                  int32_t* n_pruned, hipStream_t s) {
+                                  double log_safety, double margin_frac, double prune_ratio, double vary_max,
+                                  uint32_t* flags, const SectorBuf& sec, double* add_mag, int32_t* lists,
+                                  int32_t* counts, int32_t* n_pruned, hipStream_t s) {
   if (b.n_epochs == 0) return hipSuccess;
   const dim3 g(blocks_for(b.n_epochs, 64)), blk(64);
   if (n_lens == 2)
     hipLaunchKernelGGL((learned_sectors_kernel<2>), g, blk, 0, s, b, cimg, cn, a_c, a_ring, ext, y, log_safety,
-                       prune_ratio, vary_max, flags, sec, add_mag, lists, counts, n_pruned);
+                       margin_frac, prune_ratio, vary_max, flags, sec, add_mag, lists, counts, n_pruned);
   else
     hipLaunchKernelGGL((learned_sectors_kernel<3>), g, blk, 0, s, b, cimg, cn, a_c, a_ring, ext, y, log_safety,
-                       prune_ratio, vary_max, flags, sec, add_mag, lists, counts, n_pruned);
+                       margin_frac, prune_ratio, vary_max, flags, sec, add_mag, lists, counts, n_pruned);
   return hipGetLastError();
 }
 

@@ -46,7 +46,7 @@ class icrs_profile(ctypes.Structure):
 class icrs_learned_config(ctypes.Structure):
     _fields_ = [("n_check", ctypes.c_int32), ("n_r", ctypes.c_int32), ("n_theta", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("log_safety", ctypes.c_double), ("prune_ratio", ctypes.c_double),
-                ("vary_max", ctypes.c_double), ("gate_rel", ctypes.c_double)]
+                ("vary_max", ctypes.c_double), ("gate_rel", ctypes.c_double), ("margin_frac", ctypes.c_double)]
 
 
 class icrs_learned_stats(ctypes.Structure):
@@ -296,7 +296,8 @@ class Handle:
         return feat, tgt, nimg, flags
 
     def magnification_learned(self, params, offsets, t, model, mag=None, status=None, workspace=None,
-                              n_check=16, n_r=None, n_theta=None, prune_ratio=1e-6, vary_max=0.1, gate_rel=1e-3):
+                              n_check=16, n_r=None, n_theta=None, prune_ratio=1e-6, vary_max=0.1, gate_rel=1e-3,
+                              margin_frac=0.02):
         """Learned-bounds path; model: a learned.BoundsModel.  Returns (mag, status, stats dict)."""
         p, o = _host_events(params, offsets)
         t = _dev(t, torch.float64)
@@ -308,6 +309,7 @@ class Handle:
         lc.n_theta = n_theta if n_theta is not None else self.cfg.n_theta
         lc.log_safety = model.log_safety
         lc.prune_ratio, lc.vary_max, lc.gate_rel = prune_ratio, vary_max, gate_rel
+        lc.margin_frac = margin_frac
         mag = mag if mag is not None else torch.empty(n, dtype=torch.float64, device=t.device)
         status = status if status is not None else torch.empty(n, dtype=torch.int32, device=t.device)
         ws = workspace if workspace is not None else self.learned_workspace(p.shape[0], n)
