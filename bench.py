@@ -5,12 +5,18 @@ Workload: 2048 binary planetary-regime events (log10 q in [-5,-2], s in [0.5,2],
 [0,0.3], linear limb darkening u in [0.3,0.7]) with rho = 1e-3 and 100..5000 epochs each,
 clustered within +-3 rho tE of caustic crossings (about 5.1 million epochs); 128 limb points,
 128 x 512 polar grids, FP32 ray loop, FP32 Ehrlich-Aberth with FP64 polish.  One step is one
-full pass of the path (source centres, limb images, sectors, rays, quadrature, clip retries)
-over the whole batch, inputs resident in HBM.
+full pass of the path over the whole batch with inputs resident in HBM.  Two paths are
+timed on the same batch:
+  * batched+learned (the headline `value`): centre images, 16 check points per epoch, the
+    bounds network on the matrix cores, per-image boxes, rays, drift gate, and the plain
+    path for every epoch the checks hand back -- all inside the step;
+  * plain: centre images, 128 limb points, sectors, rays, clip retries.
 
-Printed: one JSON line with the throughput, the ray kernel's roofline position (timed live
-with HIP events on the library's stream), the oracle's CPU throughput on a sample of the
-same epochs, and the sampled accuracy against it.
+Printed: one JSON line with both throughputs, the ray kernel's roofline position (its main
+pass timed live with HIP events on the library's stream, plain path: one launch per step),
+the oracle's CPU throughput on a sample of the same epochs, and, on that sample, each
+path's agreement with the oracle and its error against the oracle's grid-free source-disk
+quadrature (the exact finite-source magnification where no caustic crosses the disk).
 """
 from __future__ import annotations
 
@@ -31,13 +37,15 @@ PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}  # MI355X vector peaks
 KERNEL = {"fp32": "rays_kernel<2, 8, true, MapF32<2, 8>>", "fp64": "rays_kernel<2, 8, true, MapF64<2, 8>>"}
 # HBM bytes per launch of the main ray kernel from rocprofv3 FETCH_SIZE + WRITE_SIZE passes,
 # scaled by the same counters' reading on a plain copy kernel of known size; keyed by
-# (ray precision, events).  Filled in from measured counter runs; None when not measured
-# for the current kernel.
+# (ray precision, events).  Filled in from measured counter runs; absent (null) when not
+# measured for the current kernel.
 TRAFFIC = {}
 
 
-def cpu_baseline(w, gpu_mag, budget_s, seed=0):
-    """The FP64 oracle on a bounded sample of the same epochs (all host threads)."""
+def cpu_baseline(w, mags, budget_s, seed=0):
+    """The FP64 oracle on a bounded sample of the same epochs (all host threads); on the
+    same sample, each GPU path against the oracle and against the oracle's source-disk
+    quadrature (epochs where no caustic crosses the disk and two resolutions agree)."""
     from oracle import oracle as O
     rng = np.random.default_rng(seed)
     ev_of = np.repeat(np.arange(w.n_events), np.diff(w.offsets))
@@ -55,13 +63,44 @@ def cpu_baseline(w, gpu_mag, budget_s, seed=0):
     idx, mag, dt = run(rng.choice(w.n_epochs, size=64, replace=False))
     n = int(np.clip(budget_s / max(dt / 64, 1e-6), 64, 20000))
     idx, mag, dt = run(rng.choice(w.n_epochs, size=n, replace=False))
-    rel = np.abs(gpu_mag[idx] / mag - 1.0)
+    ref = np.full(idx.size, np.nan)
+    for i in np.unique(ev_of[idx]):
+        sel = np.nonzero(ev_of[idx] == i)[0]
+        m1, ch = O.disk_mag(w.n_lens, w.params[i], w.t[idx[sel]], n_x=16, n_phi=96)
+        m2, _ = O.disk_mag(w.n_lens, w.params[i], w.t[idx[sel]], n_x=24, n_phi=144)
+        ok = (ch == 0) & (np.abs(m1 / m2 - 1.0) < 1e-7)
+        ref[sel[ok]] = m2[ok]
+    good = np.isfinite(ref)
+    acc = {"n_sampled": int(idx.size), "n_disk_reference": int(good.sum())}
+    for name, g in mags.items():
+        rel = np.abs(g[idx] / mag - 1.0)
+        err = np.abs(g[idx][good] / ref[good] - 1.0)
+        acc[name] = {"vs_oracle_max": float(rel.max()), "vs_oracle_median": float(np.median(rel)),
+                     "vs_disk_median": float(np.median(err)), "vs_disk_p99": float(np.quantile(err, 0.99)),
+                     "vs_disk_frac_le_1e-4": float(np.mean(err <= 1e-4))}
     return {
         "value": idx.size / dt, "unit": "epochs/s", "cores": O.num_threads(), "kind": "oracle",
-        "sample": f"{idx.size} epochs drawn uniformly (seed {seed}) from the same workload, FP64 oracle, "
-                  f"{w.n_r}x{w.n_theta} grids, {dt:.1f} s",
-    }, {"n_sampled": int(idx.size), "max_rel_err": float(rel.max()), "median_rel_err": float(np.median(rel)),
-        "frac_le_1e-4": float(np.mean(rel <= 1e-4)), "frac_le_3e-5": float(np.mean(rel <= 3e-5))}
+        "sample": f"{idx.size} epochs drawn uniformly (seed {seed}) from the same workload, FP64 oracle "
+                  f"(plain path), {w.n_r}x{w.n_theta} grids, {dt:.1f} s",
+    }, acc
+
+
+def timed_steps(fn, steps, warmup, label, after_warmup=None):
+    import torch
+    for k in range(warmup):
+        fn()
+        torch.cuda.synchronize()
+        print(f"[bench] {label}: warmup step {k + 1}/{warmup} done", file=sys.stderr, flush=True)
+    if after_warmup:
+        after_warmup()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = None
+    for k in range(steps):
+        out = fn()
+        print(f"[bench] {label}: step {k + 1}/{steps} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t0
 
 
 def main():
@@ -74,6 +113,7 @@ def main():
     ap.add_argument("--roots", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--plain-only", action="store_true", help="time the plain path only (profiling runs)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -92,7 +132,7 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_each_way": src.numel() * 4, "launches": 3}), flush=True)
         return
-    from paper_2510_02639_amd import icrs, workloads
+    from paper_2510_02639_amd import icrs, learned, workloads
 
     t_gen = time.perf_counter()
     w = workloads.metric_workload(args.events)
@@ -103,57 +143,71 @@ def main():
     t = torch.tensor(w.t, device="cuda")
     mag = torch.empty(w.n_epochs, dtype=torch.float64, device="cuda")
     status = torch.empty(w.n_epochs, dtype=torch.int32, device="cuda")
-    ws = h.workspace(w.n_events, w.n_epochs)
-    for k in range(args.warmup):
-        h.magnification(w.params, w.offsets, t, mag, status, ws)
-        torch.cuda.synchronize()
-        print(f"[bench] warmup step {k + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    ws = h.learned_workspace(w.n_events, w.n_epochs)
 
-    h.set_profiling(True)
-    h.get_profile(reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        h.magnification(w.params, w.offsets, t, mag, status, ws)
-        print(f"[bench] step {k + 1}/{args.steps} enqueued", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    # plain path, profiled after the warm-up: the main ray pass is one launch per step
+    def start_profile():
+        h.set_profiling(True)
+        h.get_profile(reset=True)
+
+    _, dt_plain = timed_steps(lambda: h.magnification(w.params, w.offsets, t, mag, status, ws), args.steps,
+                              args.warmup, "plain", start_profile)
     prof = h.get_profile()
     h.set_profiling(False)
-
-    epochs = w.n_epochs * args.steps
-    rays = prof["n_sector_passes"] * w.n_r * w.n_theta
-    # dominant kernel: the main ray pass (one launch per step, timed alone with HIP events)
-    main_rays = prof["n_main_sectors"] * w.n_r * w.n_theta
-    achieved = main_rays * FLOPS_PER_RAY[2] / (prof["ms_rays_main"] * 1e-3) / 1e12
-    peak = PEAK_TFLOPS[args.rays]
-    n_main = max(prof["n_main_launches"], 1)
+    gm_plain = mag.cpu().numpy()
     st = status.cpu().numpy().astype(np.uint32)
-    gmag = mag.cpu().numpy()
+    plain_value = w.n_epochs * args.steps / dt_plain
 
-    line = {
-        "metric": METRIC, "value": epochs / dt, "unit": "epochs/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": dt * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
+    line = {"metric": METRIC}
+    if not args.plain_only:
+        model = learned.BoundsModel.load()
+        mag_l = torch.empty_like(mag)
+        status_l = torch.empty_like(status)
+        (_, _, lstats), dt_learned = timed_steps(
+            lambda: h.magnification_learned(w.params, w.offsets, t, model, mag_l, status_l, ws), args.steps,
+            args.warmup, "batched+learned")
+        gm_learned = mag_l.cpu().numpy()
+        value, dt_value = w.n_epochs * args.steps / dt_learned, dt_learned
+    else:
+        value, dt_value = plain_value, dt_plain
+
+    n_main = max(prof["n_main_launches"], 1)
+    achieved = prof["n_main_rays"] * FLOPS_PER_RAY[2] / (prof["ms_rays_main"] * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[args.rays]
+    line.update({
+        "value": value, "unit": "epochs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt_value * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32" if args.rays == "fp32" else "f64", "data": "synthetic",
         "config": {"workload": w.name, "n_events": w.n_events, "n_epochs": w.n_epochs, "n_limb": w.n_limb,
-                   "grid": [w.n_r, w.n_theta], "ray_precision": args.rays, "root_precision": "fp32+fp64-polish" if args.roots == "fp32" else "fp64",
-                   "path": "plain", "rho": 1e-3},
-        "rays_per_s": rays / dt,
+                   "grid": [w.n_r, w.n_theta], "ray_precision": args.rays,
+                   "root_precision": "fp32+fp64-polish" if args.roots == "fp32" else "fp64",
+                   "path": "plain" if args.plain_only else "batched+learned", "rho": 1e-3},
+        "plain": {"value": plain_value, "ms_per_step": dt_plain * 1e3 / args.steps,
+                  "rays_per_s": prof["n_sector_passes"] * w.n_r * w.n_theta / dt_plain,
+                  "breakdown_ms_per_step": {k: prof[k] / args.steps for k in
+                                            ("ms_centre", "ms_limb_sectors", "ms_rays", "ms_rays_main",
+                                             "ms_finalize")},
+                  "sectors_per_epoch": prof["n_sector_passes"] / max(prof["n_epochs"], 1),
+                  "status_counts": {name: int(np.sum((st & bit) != 0)) for name, bit in
+                                    [("root_nonconv", 1), ("img_count", 2), ("cap_overflow", 4), ("clip", 8),
+                                     ("nan", 16)]}},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": TRAFFIC.get((args.rays, w.n_events)), "kernel": KERNEL[args.rays],
-                     "flops_per_ray": FLOPS_PER_RAY[2], "rays_per_launch_avg": main_rays / n_main,
-                     "kernel_ms_per_launch_avg": prof["ms_rays_main"] / n_main},
-        "breakdown_ms_per_step": {k: prof[k] / args.steps for k in ("ms_centre", "ms_limb_sectors", "ms_rays",
-                                                                    "ms_rays_main", "ms_finalize")},
-        "sectors_per_epoch": prof["n_sector_passes"] / max(prof["n_epochs"], 1),
-        "status_counts": {name: int(np.sum((st & bit) != 0)) for name, bit in
-                          [("root_nonconv", 1), ("img_count", 2), ("cap_overflow", 4), ("clip", 8), ("nan", 16)]},
-    }
+                     "flops_per_ray": FLOPS_PER_RAY[2], "rays_per_launch_avg": prof["n_main_rays"] / n_main,
+                     "kernel_ms_per_launch_avg": prof["ms_rays_main"] / n_main,
+                     "path_timed": "plain (one main-pass launch per step)"},
+    })
+    if not args.plain_only:
+        line["learned"] = {"stats_per_step": lstats, "model": "paper_2510_02639_amd/data/bounds_mlp.npz",
+                           "log_safety": model.log_safety}
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
-        base, acc = cpu_baseline(w, gmag, args.cpu_seconds)
+        mags = {"plain": gm_plain}
+        if not args.plain_only:
+            mags["batched+learned"] = gm_learned
+        base, acc = cpu_baseline(w, mags, args.cpu_seconds)
         line["cpu_baseline"] = base
-        line["accuracy_vs_oracle"] = acc
+        line["accuracy"] = acc
     print(json.dumps(line), flush=True)
 
 
