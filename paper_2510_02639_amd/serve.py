@@ -31,6 +31,7 @@ class Request:
     arrival: float          # seconds from the start
     done: float = -1.0
     status_bits: int = 0
+    mag: np.ndarray = None  # filled when served
 
 
 def make_requests(seconds=60.0, rate=200.0, seed=51, max_events=None):
@@ -105,13 +106,15 @@ class Server:
             if not batch:       # a single request larger than the budget
                 raise RuntimeError("request exceeds the HBM budget")
             t0 = time.perf_counter()
-            _, status, off = self.run_batch(batch)
+            mag, status, off = self.run_batch(batch)
             t1 = time.perf_counter()
             busy += t1 - t0
             st = status.cpu().numpy()
+            mg = mag.cpu().numpy()
             for i, r in enumerate(batch):
                 r.done = t1 - start
                 r.status_bits = int(np.bitwise_or.reduce(st[off[i]:off[i + 1]].astype(np.uint32)))
+                r.mag = mg[off[i]:off[i + 1]]
             batch_sizes.append(len(batch))
             if verbose and len(batch_sizes) % 50 == 0:
                 print(f"[serve] t={t1 - start:.1f}s batches={len(batch_sizes)}", flush=True)

@@ -226,3 +226,24 @@ def test_fp32_rays_fall_back_to_fp64_next_to_a_planet():
     _report("fp32 near planet", rel)
     assert np.all(ns == ref["nsec"])
     assert np.all(rel <= FP32_TOL)
+
+
+def test_triple_fp32_rays_config3_grid():
+    """The triple-lens workload as configured: FP64 roots, FP32 rays, 128 limb points,
+    128 x 512 grids; given-grid parity with the oracle at the FP32 bar."""
+    big = W.config3(n_events=3, n_epochs=2000)
+    ts, off = [], [0]
+    for i in range(3):
+        seg = big.t[big.offsets[i]:big.offsets[i + 1]][985:1015:6]
+        ts.append(seg)
+        off.append(off[-1] + seg.size)
+    w = W.Workload("triple-fp32", 3, big.params, np.array(off, np.int64), np.concatenate(ts), 128, 128, 512,
+                   "fp32", "fp64")
+    ref = _oracle(w)
+    h = icrs.Handle(n_lens=3, n_limb=128, n_r=128, n_theta=512, ray_precision="fp32", root_precision="fp64")
+    t = torch.tensor(w.t, device="cuda")
+    args = [torch.tensor(ref[k], device="cuda") for k in ("sectors", "periodic", "nsec")]
+    mag, _ = h.magnification_given(w.params, w.offsets, t, *args)
+    rel = np.abs(mag.cpu().numpy() / ref["mag"] - 1)
+    _report("triple fp32 given grid", rel)
+    assert np.all(rel <= FP32_TOL)
