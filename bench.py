@@ -9,7 +9,9 @@ full pass of the path over the whole batch with inputs resident in HBM.  Two pat
 timed on the same batch:
   * batched+learned (the headline `value`): centre images, 16 check points per epoch, the
     bounds network on the matrix cores, per-image boxes, rays, drift gate, and the plain
-    path for every epoch the checks hand back -- all inside the step;
+    path for every epoch the checks hand back -- all inside the step.  Its grid is the
+    autotuner's choice (untimed, on a 1% calibration subset): the smallest grid whose
+    error is no worse than the plain path's at 128 x 512, in median and 99th percentile;
   * plain: centre images, 128 limb points, sectors, rays, clip retries.
 
 Printed: one JSON line with both throughputs, the ray kernel's roofline position (its main
@@ -160,12 +162,19 @@ def main():
 
     line = {"metric": METRIC}
     if not args.plain_only:
+        from paper_2510_02639_amd import autotune
         model = learned.BoundsModel.load()
+        # learned grid: the autotuner's choice on a 1% calibration subset (untimed)
+        t_tune = time.perf_counter()
+        tune = autotune.tune_learned(w, model, plain_grid=(w.n_r, w.n_theta), every=100)
+        t_tune = time.perf_counter() - t_tune
+        print(f"[bench] learned grid {tune.n_r} x {tune.n_theta} (tuned in {t_tune:.1f} s)", file=sys.stderr,
+              flush=True)
         mag_l = torch.empty_like(mag)
         status_l = torch.empty_like(status)
         (_, _, lstats), dt_learned = timed_steps(
-            lambda: h.magnification_learned(w.params, w.offsets, t, model, mag_l, status_l, ws), args.steps,
-            args.warmup, "batched+learned")
+            lambda: h.magnification_learned(w.params, w.offsets, t, model, mag_l, status_l, ws, n_r=tune.n_r,
+                                            n_theta=tune.n_theta), args.steps, args.warmup, "batched+learned")
         gm_learned = mag_l.cpu().numpy()
         value, dt_value = w.n_epochs * args.steps / dt_learned, dt_learned
     else:
@@ -181,7 +190,8 @@ def main():
         "config": {"workload": w.name, "n_events": w.n_events, "n_epochs": w.n_epochs, "n_limb": w.n_limb,
                    "grid": [w.n_r, w.n_theta], "ray_precision": args.rays,
                    "root_precision": "fp32+fp64-polish" if args.roots == "fp32" else "fp64",
-                   "path": "plain" if args.plain_only else "batched+learned", "rho": 1e-3},
+                   "path": "plain" if args.plain_only else "batched+learned", "rho": 1e-3,
+                   "learned_grid": None if args.plain_only else [tune.n_r, tune.n_theta]},
         "plain": {"value": plain_value, "ms_per_step": dt_plain * 1e3 / args.steps,
                   "rays_per_s": prof["n_sector_passes"] * w.n_r * w.n_theta / dt_plain,
                   "breakdown_ms_per_step": {k: prof[k] / args.steps for k in
@@ -199,7 +209,10 @@ def main():
     })
     if not args.plain_only:
         line["learned"] = {"stats_per_step": lstats, "model": "paper_2510_02639_amd/data/bounds_mlp.npz",
-                           "log_safety": model.log_safety}
+                           "log_safety": model.log_safety, "grid": [tune.n_r, tune.n_theta],
+                           "autotune": {"plain_error_median_p99": tune.plain_error, "tried": tune.errors,
+                                        "calibration_epochs": tune.n_calibration, "rates": tune.rates,
+                                        "seconds": t_tune}}
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         mags = {"plain": gm_plain}

@@ -84,3 +84,73 @@ def tune(w: Workload, tol=3e-5, every=100, n_r_ref=512, n_theta_ref=1024, candid
     timings = {p: _rate(cal, chosen[0], chosen[1], p, roots) for p in ("fp32", "fp64")}
     rays = max(timings, key=timings.get)
     return TuneResult(chosen[0], chosen[1], rays, tol, int(cal.n_epochs), int(trusted.sum()), errors, timings)
+
+
+LEARNED_CANDIDATES = [(32, 128), (32, 192), (48, 192), (32, 256), (48, 256), (64, 192), (64, 256), (64, 320),
+                      (80, 320), (64, 384), (96, 320), (96, 384), (112, 448), (128, 384), (96, 512), (128, 448),
+                      (128, 512)]
+
+
+@dataclasses.dataclass
+class LearnedTuneResult:
+    n_r: int
+    n_theta: int
+    plain_grid: tuple
+    plain_error: tuple        # (median, 99th percentile) of the plain path at plain_grid
+    errors: list              # (n_r, n_theta, median, p99) per candidate tried
+    n_calibration: int
+    rates: dict               # epochs/s on the calibration subset of the grids that qualified
+
+
+def tune_learned(w: Workload, model, plain_grid=(128, 512), every=100, n_r_ref=512, n_theta_ref=1024,
+                 candidates=LEARNED_CANDIDATES, verbose=False) -> LearnedTuneResult:
+    """Fastest learned-path grid whose error on the calibration subset is no worse than the
+    plain path's at plain_grid, in median and in the 99th percentile.  Both are measured
+    against the learned path itself in FP64 on the fine grid (per-image boxes, so small
+    images are resolved; the reference converges with the grid, not with the boxes).
+    Candidates are tried cheapest first; the first three that qualify are timed (a coarse
+    grid can lose to a finer one when more epochs fail the drift gate and fall back)."""
+    cal = w.sample_epochs(every)
+    t = torch.tensor(cal.t, device="cuda")
+    href = icrs.Handle(n_lens=cal.n_lens, n_limb=cal.n_limb, n_r=n_r_ref, n_theta=n_theta_ref, ray_precision="fp64",
+                       root_precision="fp64")
+    ref, _, _ = href.magnification_learned(cal.params, cal.offsets, t, model, n_r=n_r_ref, n_theta=n_theta_ref)
+    ref = ref.cpu().numpy()
+
+    def err(m):
+        e = np.abs(m / ref - 1.0)
+        return float(np.median(e)), float(np.quantile(e, 0.99))
+
+    hp = icrs.Handle(n_lens=cal.n_lens, n_limb=cal.n_limb, n_r=plain_grid[0], n_theta=plain_grid[1],
+                     ray_precision="fp32", root_precision="fp32")
+    mp, _ = hp.magnification(cal.params, cal.offsets, t)
+    ep = err(mp.cpu().numpy())
+    if verbose:
+        print(f"[autotune] plain {plain_grid}: median {ep[0]:.2e} p99 {ep[1]:.2e}", flush=True)
+    h = icrs.Handle(n_lens=cal.n_lens, n_limb=cal.n_limb, n_r=plain_grid[0], n_theta=plain_grid[1],
+                    ray_precision="fp32", root_precision="fp32")
+    errors, ok = [], []
+    for n_r, n_theta in sorted(candidates, key=lambda g: (g[0] * g[1], g[1])):
+        m, _, _ = h.magnification_learned(cal.params, cal.offsets, t, model, n_r=n_r, n_theta=n_theta)
+        el = err(m.cpu().numpy())
+        errors.append((n_r, n_theta) + el)
+        if verbose:
+            print(f"[autotune] learned {n_r} x {n_theta}: median {el[0]:.2e} p99 {el[1]:.2e}", flush=True)
+        if el[0] <= ep[0] and el[1] <= ep[1]:
+            ok.append((n_r, n_theta))
+            if len(ok) == 3:
+                break
+    rates = {}
+    ws = h.learned_workspace(cal.n_events, cal.n_epochs)
+    for g in ok:
+        run = lambda: h.magnification_learned(cal.params, cal.offsets, t, model, workspace=ws, n_r=g[0], n_theta=g[1])
+        run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            run()
+        torch.cuda.synchronize()
+        rates[g] = cal.n_epochs * 3 / (time.perf_counter() - t0)
+    chosen = max(rates, key=rates.get) if rates else tuple(plain_grid)
+    return LearnedTuneResult(chosen[0], chosen[1], tuple(plain_grid), ep, errors, int(cal.n_epochs),
+                             {f"{k[0]}x{k[1]}": v for k, v in rates.items()})

@@ -65,42 +65,47 @@ __device__ inline void image_features(const double* p, const Lens<N>& L, c64 wc,
   f[9] = (float)(-log10(g));
 }
 
-// One workgroup per epoch (blockDim a multiple of 64 >= n_pts): images of n_pts limb points
-// assigned to the nearest centre image; per centre image the min/max of r and of theta
-// relative to the image (ext [E][MI][4]); features [E][MI][10]; with tgt, the training
-// targets ln(offset / sigma) of the four extents (offsets floored at 1e-3 sigma);
+// Groups of P lanes (P a power of two >= max(n_pts, 16); G = blockDim / P groups per
+// workgroup, one epoch per group): images of n_pts limb points assigned to the nearest
+// centre image; per centre image the min/max of r and of theta relative to the image
+// (ext [E][MI][4]); features [E][MI][10]; with tgt, the training targets
+// ln(offset / sigma) of the four extents (offsets floored at 1e-3 sigma);
 // a_ring[e] = mean point-source magnification over the limb points; flags[e].
+constexpr int kMaxGroups = 4;
+
 template <int N, typename T>
-__global__ __launch_bounds__(256) void image_extents_kernel(Batch b, int n_pts, const double* __restrict__ cimg,
+__global__ __launch_bounds__(256) void image_extents_kernel(Batch b, int n_pts, int P, const double* __restrict__ cimg,
                                                             const int32_t* __restrict__ cn, double* __restrict__ ext,
                                                             float* __restrict__ feat, float* __restrict__ tgt,
                                                             double* __restrict__ a_ring, uint32_t* __restrict__ flags) {
   constexpr int MI = N * N + 1;
-  __shared__ c64 cz[MI];
-  __shared__ unsigned long long key[MI][4];
-  __shared__ int cnt[MI];
-  __shared__ uint32_t flag_sh;
-  __shared__ double asum;
-  const int64_t e = blockIdx.x;
-  const int tid = threadIdx.x;
-  const int nc = cn[e];
-  const double* p = b.params + (int64_t)b.epoch_event[e] * kParams;
+  __shared__ c64 cz[kMaxGroups][MI];
+  __shared__ unsigned long long key[kMaxGroups][MI][4];
+  __shared__ int cnt[kMaxGroups][MI];
+  __shared__ uint32_t flag_sh[kMaxGroups];
+  __shared__ double asum[kMaxGroups];
+  const int G = blockDim.x / P;
+  const int g = threadIdx.x / P, k = threadIdx.x % P;
+  const int64_t e = (int64_t)blockIdx.x * G + g;
+  const bool valid = e < b.n_epochs;
+  const int nc = valid ? cn[e] : 0;
+  const double* p = b.params + (valid ? (int64_t)b.epoch_event[e] * kParams : 0);
   const Lens<N> L = make_lens<N>(p);
-  const c64 wc = source_center(p, b.t[e]);
-  if (tid < MI) {
-    cz[tid] = mk(cimg[(e * kMaxSectors + tid) * 2], cimg[(e * kMaxSectors + tid) * 2 + 1]);
-    key[tid][0] = key[tid][2] = ~0ull;
-    key[tid][1] = key[tid][3] = 0ull;
-    cnt[tid] = 0;
+  const c64 wc = valid ? source_center(p, b.t[e]) : mk(0.0, 0.0);
+  if (valid && k < MI) {
+    cz[g][k] = mk(cimg[(e * kMaxSectors + k) * 2], cimg[(e * kMaxSectors + k) * 2 + 1]);
+    key[g][k][0] = key[g][k][2] = ~0ull;
+    key[g][k][1] = key[g][k][3] = 0ull;
+    cnt[g][k] = 0;
   }
-  if (tid == 0) {
-    flag_sh = (nc < 1) ? kLfEmpty : 0u;
-    asum = 0.0;
+  if (valid && k == 0) {
+    flag_sh[g] = (nc < 1) ? kLfEmpty : 0u;
+    asum[g] = 0.0;
   }
   __syncthreads();
-  if (tid < n_pts && nc >= 1) {
+  if (valid && k < n_pts && nc >= 1) {
     double sp, cp;
-    sincospi(2.0 * tid / n_pts, &sp, &cp);
+    sincospi(2.0 * k / n_pts, &sp, &cp);
     const double rho = p[6];
     const c64 w = mk(wc.x + rho * cp, wc.y + rho * sp);
     c64 img[MI];
@@ -114,59 +119,59 @@ __global__ __launch_bounds__(256) void image_extents_kernel(Batch b, int n_pts, 
       int best = 0;
       double bd = 1e300;
       for (int i = 0; i < nc; ++i) {
-        const double d = norm2(img[j] - cz[i]);
+        const double d = norm2(img[j] - cz[g][i]);
         if (d < bd) {
           bd = d;
           best = i;
         }
       }
       const double r = sqrt(norm2(img[j]));
-      const double dth = wrap_pi(atan2(img[j].y, img[j].x) - atan2(cz[best].y, cz[best].x));
-      atomicMin(&key[best][0], dkey(r));
-      atomicMax(&key[best][1], dkey(r));
-      atomicMin(&key[best][2], dkey(dth));
-      atomicMax(&key[best][3], dkey(dth));
-      atomicAdd(&cnt[best], 1);
+      const double dth = wrap_pi(atan2(img[j].y, img[j].x) - atan2(cz[g][best].y, cz[g][best].x));
+      atomicMin(&key[g][best][0], dkey(r));
+      atomicMax(&key[g][best][1], dkey(r));
+      atomicMin(&key[g][best][2], dkey(dth));
+      atomicMax(&key[g][best][3], dkey(dth));
+      atomicAdd(&cnt[g][best], 1);
     }
-    if (f) atomicOr(&flag_sh, f);
-    atomicAdd(&asum, A);
+    if (f) atomicOr(&flag_sh[g], f);
+    atomicAdd(&asum[g], A);
   }
   __syncthreads();
-  if (tid < MI) {
-    const int j = tid;
+  if (valid && k < MI) {
+    const int j = k;
     float fv[10];
     double o[4] = {0.0, 0.0, 0.0, 0.0};
     uint32_t f = 0u;
     if (j < nc) {
       double sigma, mu;
-      image_features<N>(p, L, wc, cz[j], fv, &sigma, &mu);
-      if (cnt[j] == 0) {
+      image_features<N>(p, L, wc, cz[g][j], fv, &sigma, &mu);
+      if (cnt[g][j] == 0) {
         f |= kLfEmpty;
       } else {
-        o[0] = dkey_inv(key[j][0]);
-        o[1] = dkey_inv(key[j][1]);
-        o[2] = dkey_inv(key[j][2]);
-        o[3] = dkey_inv(key[j][3]);
+        o[0] = dkey_inv(key[g][j][0]);
+        o[1] = dkey_inv(key[g][j][1]);
+        o[2] = dkey_inv(key[g][j][2]);
+        o[3] = dkey_inv(key[g][j][3]);
         if (o[3] - o[2] >= kPi) f |= kLfWide;
       }
       if (tgt) {
-        const double rz = sqrt(norm2(cz[j]));
+        const double rz = sqrt(norm2(cz[g][j]));
         const double off[4] = {rz - o[0], o[1] - rz, -rz * o[2], rz * o[3]};
-        for (int k = 0; k < 4; ++k) tgt[(e * MI + j) * 4 + k] = (float)log(fmax(off[k], 1e-3 * sigma) / sigma);
+        for (int q = 0; q < 4; ++q) tgt[(e * MI + j) * 4 + q] = (float)log(fmax(off[q], 1e-3 * sigma) / sigma);
       }
     } else {
-      for (int k = 0; k < 10; ++k) fv[k] = 0.0f;
+      for (int q = 0; q < 10; ++q) fv[q] = 0.0f;
       if (tgt)
-        for (int k = 0; k < 4; ++k) tgt[(e * MI + j) * 4 + k] = 0.0f;
+        for (int q = 0; q < 4; ++q) tgt[(e * MI + j) * 4 + q] = 0.0f;
     }
-    for (int k = 0; k < 10; ++k) feat[(e * MI + j) * 10 + k] = fv[k];
-    for (int k = 0; k < 4; ++k) ext[(e * MI + j) * 4 + k] = o[k];
-    if (f) atomicOr(&flag_sh, f);
+    for (int q = 0; q < 10; ++q) feat[(e * MI + j) * 10 + q] = fv[q];
+    for (int q = 0; q < 4; ++q) ext[(e * MI + j) * 4 + q] = o[q];
+    if (f) atomicOr(&flag_sh[g], f);
   }
   __syncthreads();
-  if (tid == 0) {
-    flags[e] = flag_sh;
-    if (a_ring) a_ring[e] = asum / n_pts;
+  if (valid && k == 0) {
+    flags[e] = flag_sh[g];
+    if (a_ring) a_ring[e] = asum[g] / n_pts;
   }
 }
 
@@ -287,22 +292,28 @@ hipError_t launch_image_extents(int n_lens, int root_fp32, int n_pts, const Batc
                                 const int32_t* cn, double* ext, float* feat, float* tgt, double* a_ring,
                                 uint32_t* flags, hipStream_t s) {
   if (b.n_epochs == 0) return hipSuccess;
-  const int bs = ((n_pts + 63) / 64) * 64;
-  const dim3 g((unsigned)b.n_epochs), blk(bs);
+  // group width: a power of two covering the points and the images (>= 16); small point
+  // counts share a wave between several epochs
+  int P = 16;
+  while (P < n_pts) P <<= 1;
+  const int bs = P >= 64 ? P : 64;
+  const int G = bs / P;
+  if (G > kMaxGroups || P > 256) return hipErrorInvalidValue;
+  const dim3 g((unsigned)((b.n_epochs + G - 1) / G)), blk(bs);
   if (n_lens == 2) {
     if (root_fp32)
-      hipLaunchKernelGGL((image_extents_kernel<2, float>), g, blk, 0, s, b, n_pts, cimg, cn, ext, feat, tgt, a_ring,
-                         flags);
+      hipLaunchKernelGGL((image_extents_kernel<2, float>), g, blk, 0, s, b, n_pts, P, cimg, cn, ext, feat, tgt,
+                         a_ring, flags);
     else
-      hipLaunchKernelGGL((image_extents_kernel<2, double>), g, blk, 0, s, b, n_pts, cimg, cn, ext, feat, tgt, a_ring,
-                         flags);
+      hipLaunchKernelGGL((image_extents_kernel<2, double>), g, blk, 0, s, b, n_pts, P, cimg, cn, ext, feat, tgt,
+                         a_ring, flags);
   } else {
     if (root_fp32)
-      hipLaunchKernelGGL((image_extents_kernel<3, float>), g, blk, 0, s, b, n_pts, cimg, cn, ext, feat, tgt, a_ring,
-                         flags);
+      hipLaunchKernelGGL((image_extents_kernel<3, float>), g, blk, 0, s, b, n_pts, P, cimg, cn, ext, feat, tgt,
+                         a_ring, flags);
     else
-      hipLaunchKernelGGL((image_extents_kernel<3, double>), g, blk, 0, s, b, n_pts, cimg, cn, ext, feat, tgt, a_ring,
-                         flags);
+      hipLaunchKernelGGL((image_extents_kernel<3, double>), g, blk, 0, s, b, n_pts, P, cimg, cn, ext, feat, tgt,
+                         a_ring, flags);
   }
   return hipGetLastError();
 }
