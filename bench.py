@@ -11,7 +11,8 @@ timed on the same batch:
     bounds network on the matrix cores, per-image boxes, rays, drift gate, and the plain
     path for every epoch the checks hand back -- all inside the step.  Its grid is the
     autotuner's choice (untimed, on a 1% calibration subset): the smallest grid whose
-    error is no worse than the plain path's at 128 x 512, in median and 99th percentile;
+    error is no worse than the plain path's at 128 x 512, in median and 99th percentile
+    (grid and drift-gate tolerance tuned together);
   * plain: centre images, 128 limb points, sectors, rays, clip retries.
 
 Printed: one JSON line with both throughputs, the ray kernel's roofline position (its main
@@ -168,13 +169,14 @@ def main():
         t_tune = time.perf_counter()
         tune = autotune.tune_learned(w, model, plain_grid=(w.n_r, w.n_theta), every=100)
         t_tune = time.perf_counter() - t_tune
-        print(f"[bench] learned grid {tune.n_r} x {tune.n_theta} (tuned in {t_tune:.1f} s)", file=sys.stderr,
-              flush=True)
+        print(f"[bench] learned grid {tune.n_r} x {tune.n_theta}, gate {tune.gate_rel:g} (tuned in {t_tune:.1f} s)",
+              file=sys.stderr, flush=True)
         mag_l = torch.empty_like(mag)
         status_l = torch.empty_like(status)
         (_, _, lstats), dt_learned = timed_steps(
             lambda: h.magnification_learned(w.params, w.offsets, t, model, mag_l, status_l, ws, n_r=tune.n_r,
-                                            n_theta=tune.n_theta), args.steps, args.warmup, "batched+learned")
+                                            n_theta=tune.n_theta, gate_rel=tune.gate_rel), args.steps, args.warmup,
+            "batched+learned")
         gm_learned = mag_l.cpu().numpy()
         value, dt_value = w.n_epochs * args.steps / dt_learned, dt_learned
     else:
@@ -210,6 +212,7 @@ def main():
     if not args.plain_only:
         line["learned"] = {"stats_per_step": lstats, "model": "paper_2510_02639_amd/data/bounds_mlp.npz",
                            "log_safety": model.log_safety, "grid": [tune.n_r, tune.n_theta],
+                           "gate_rel": tune.gate_rel,
                            "autotune": {"plain_error_median_p99": tune.plain_error, "tried": tune.errors,
                                         "calibration_epochs": tune.n_calibration, "rates": tune.rates,
                                         "seconds": t_tune}}

@@ -95,6 +95,7 @@ LEARNED_CANDIDATES = [(32, 128), (32, 192), (48, 192), (32, 256), (48, 256), (64
 class LearnedTuneResult:
     n_r: int
     n_theta: int
+    gate_rel: float
     plain_grid: tuple
     plain_error: tuple        # (median, 99th percentile) of the plain path at plain_grid
     errors: list              # (n_r, n_theta, median, p99) per candidate tried
@@ -103,13 +104,14 @@ class LearnedTuneResult:
 
 
 def tune_learned(w: Workload, model, plain_grid=(128, 512), every=100, n_r_ref=512, n_theta_ref=1024,
-                 candidates=LEARNED_CANDIDATES, verbose=False) -> LearnedTuneResult:
+                 candidates=LEARNED_CANDIDATES, gates=(1e-3, 3e-3), verbose=False) -> LearnedTuneResult:
     """Fastest learned-path grid whose error on the calibration subset is no worse than the
     plain path's at plain_grid, in median and in the 99th percentile.  Both are measured
     against the learned path itself in FP64 on the fine grid (per-image boxes, so small
     images are resolved; the reference converges with the grid, not with the boxes).
-    Candidates are tried cheapest first; the first three that qualify are timed (a coarse
-    grid can lose to a finer one when more epochs fail the drift gate and fall back)."""
+    Candidates (grid, drift-gate tolerance) are tried cheapest grid first; the first three
+    that qualify are timed (a coarse grid can lose to a finer one when more epochs fail the
+    drift gate and fall back to the plain path)."""
     cal = w.sample_epochs(every)
     t = torch.tensor(cal.t, device="cuda")
     href = icrs.Handle(n_lens=cal.n_lens, n_limb=cal.n_limb, n_r=n_r_ref, n_theta=n_theta_ref, ray_precision="fp64",
@@ -131,19 +133,23 @@ def tune_learned(w: Workload, model, plain_grid=(128, 512), every=100, n_r_ref=5
                     ray_precision="fp32", root_precision="fp32")
     errors, ok = [], []
     for n_r, n_theta in sorted(candidates, key=lambda g: (g[0] * g[1], g[1])):
-        m, _, _ = h.magnification_learned(cal.params, cal.offsets, t, model, n_r=n_r, n_theta=n_theta)
-        el = err(m.cpu().numpy())
-        errors.append((n_r, n_theta) + el)
-        if verbose:
-            print(f"[autotune] learned {n_r} x {n_theta}: median {el[0]:.2e} p99 {el[1]:.2e}", flush=True)
-        if el[0] <= ep[0] and el[1] <= ep[1]:
-            ok.append((n_r, n_theta))
-            if len(ok) == 3:
-                break
+        for gate in gates:
+            m, _, _ = h.magnification_learned(cal.params, cal.offsets, t, model, n_r=n_r, n_theta=n_theta,
+                                              gate_rel=gate)
+            el = err(m.cpu().numpy())
+            errors.append((n_r, n_theta, gate) + el)
+            if verbose:
+                print(f"[autotune] learned {n_r} x {n_theta} gate {gate:g}: median {el[0]:.2e} p99 {el[1]:.2e}",
+                      flush=True)
+            if el[0] <= ep[0] and el[1] <= ep[1]:
+                ok.append((n_r, n_theta, gate))
+        if len(ok) >= 3:
+            break
     rates = {}
     ws = h.learned_workspace(cal.n_events, cal.n_epochs)
     for g in ok:
-        run = lambda: h.magnification_learned(cal.params, cal.offsets, t, model, workspace=ws, n_r=g[0], n_theta=g[1])
+        run = lambda: h.magnification_learned(cal.params, cal.offsets, t, model, workspace=ws, n_r=g[0],
+                                              n_theta=g[1], gate_rel=g[2])
         run()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -151,6 +157,6 @@ def tune_learned(w: Workload, model, plain_grid=(128, 512), every=100, n_r_ref=5
             run()
         torch.cuda.synchronize()
         rates[g] = cal.n_epochs * 3 / (time.perf_counter() - t0)
-    chosen = max(rates, key=rates.get) if rates else tuple(plain_grid)
-    return LearnedTuneResult(chosen[0], chosen[1], tuple(plain_grid), ep, errors, int(cal.n_epochs),
-                             {f"{k[0]}x{k[1]}": v for k, v in rates.items()})
+    chosen = max(rates, key=rates.get) if rates else (plain_grid[0], plain_grid[1], gates[0])
+    return LearnedTuneResult(chosen[0], chosen[1], chosen[2], tuple(plain_grid), ep, errors, int(cal.n_epochs),
+                             {f"{k[0]}x{k[1]}/gate{k[2]:g}": v for k, v in rates.items()})
