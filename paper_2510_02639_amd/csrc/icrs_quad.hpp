@@ -13,35 +13,51 @@ template <>
 struct Num<double> {
   static constexpr double newton_tol = 1e-12;
   static constexpr int newton_iter = 16;
+  static constexpr int fast_steps = 4;
 };
 template <>
 struct Num<float> {
   static constexpr float newton_tol = 1e-6f;
   static constexpr int newton_iter = 12;
+  static constexpr int fast_steps = 3;
 };
 
 // f(delta) of App. A.2 (u1 > 0) or delta + 1/2 (uniform source, App. A.1)
 template <typename T>
 __device__ __forceinline__ T edge_factor(T delta, T u1, T delta_c) {
   if (u1 == T(0)) return delta + T(0.5);
-  if (delta >= delta_c && delta > T(0)) return (T(0.5) + delta) * T(2.0 / 3.0) * sqrt(T(1) + T(1) / (T(2) * delta));
+  if (delta >= delta_c && delta > T(0))
+    return (T(0.5) + delta) * T(2.0 / 3.0) * sqrt(T(1) + T(0.5) * rcp_fast(delta));
   return T(2.0 / 3.0) * delta + T(0.5);
 }
 
 // Crossing of the cubic Lagrange interpolant through (t, d) = (-1,d0), (0,d1), (1,d2),
 // (2,d3) with rho on the bracket [0,1] (d1, d2 on opposite sides of rho); linear between
 // d1 and d2 when cubic is false.  Safeguarded Newton from the linear estimate: the bracket
-// shrinks on every step and a step leaving it is replaced by bisection.
+// shrinks on every step and a step leaving it is replaced by bisection.  Quotients use the
+// hardware reciprocal (refined once in FP64): they only steer the iteration.
 template <typename T>
 __device__ inline T crossing_t(T d0, T d1, T d2, T d3, bool cubic, T rho) {
   const T den = d2 - d1;
-  T t = (den == T(0)) ? T(0.5) : (rho - d1) / den;
+  T t = (den == T(0)) ? T(0.5) : (rho - d1) * rcp_fast(den);
   t = fmin(fmax(t, T(0)), T(1));
   if (!cubic) return t;
   const T c0 = d1 - rho;
   const T c1 = -d0 * T(1.0 / 3.0) - T(0.5) * d1 + d2 - d3 * T(1.0 / 6.0);
   const T c2 = T(0.5) * d0 - d1 + T(0.5) * d2;
   const T c3 = (d3 - d0) * T(1.0 / 6.0) + T(0.5) * (d1 - d2);
+  // a few plain Newton steps from the linear estimate settle almost every crossing; a lane
+  // whose iterate leaves the bracket or is still moving takes the safeguarded loop
+  T tq = t;
+  T last_step = T(0);
+#pragma unroll
+  for (int it = 0; it < Num<T>::fast_steps; ++it) {
+    const T g = ((c3 * tq + c2) * tq + c1) * tq + c0;
+    const T dg = (T(3) * c3 * tq + T(2) * c2) * tq + c1;
+    last_step = g * rcp_fast(dg);
+    tq -= last_step;
+  }
+  if (tq >= T(0) && tq <= T(1) && fabs(last_step) <= Num<T>::newton_tol) return tq;
   const bool in0 = c0 < T(0);
   T a = T(0), b = T(1);
   for (int it = 0; it < Num<T>::newton_iter; ++it) {
@@ -52,7 +68,7 @@ __device__ inline T crossing_t(T d0, T d1, T d2, T d3, bool cubic, T rho) {
     else
       b = t;
     const T dg = (T(3) * c3 * t + T(2) * c2) * t + c1;
-    const T step = g / dg;
+    const T step = g * rcp_fast(dg);  // Newton step; its rounding does not move the root
     T tn = t - step;
     // converged: accept before the safeguard (t sits on a bracket end by now, and a
     // roundoff-sized step may land just outside it)

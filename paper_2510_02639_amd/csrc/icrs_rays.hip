@@ -342,9 +342,10 @@ __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L
           // side 1: crossing in (theta_l, theta_{l+1}), bracket p = l,   delta = t
           const int pp = side ? l : (l == 0 ? last : l - 1);
           const bool cubic = per || (pp - 1 >= 0 && pp + 2 <= last);
-          const int im1 = per ? (pp - 1 + n_theta) % n_theta : max(pp - 1, 0);
-          const int ip2 = per ? (pp + 2) % n_theta : min(pp + 2, last);
-          const int ip1 = (pp + 1) % n_theta;
+          // neighbours of pp in [0, n_theta): wrap by one subtraction (periodic) or clamp
+          const int im1 = per ? (pp == 0 ? last : pp - 1) : max(pp - 1, 0);
+          const int ip1 = pp == last ? 0 : pp + 1;
+          const int ip2 = per ? (pp + 2 > last ? pp + 2 - n_theta : pp + 2) : min(pp + 2, last);
           const T t = crossing_t<T>(sqrt(buf[im1]), sqrt(buf[pp]), sqrt(buf[ip1]), sqrt(buf[ip2]), cubic, rho);
           corr = edge_factor<T>(side ? t : T(1) - t, u1, delta_c) - T(1);
         }
