@@ -220,7 +220,8 @@ __device__ __forceinline__ uint64_t boundary_word(const uint64_t (&m)[JMAX], int
 template <int N, int JMAX, bool EXACT, typename MAP>
 __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L, c64 wc, double rho_d, double u1_d,
                                     double delta_c_d, int n_r, int n_theta, typename MAP::T* rowbuf_all,
-                                    double* wsum, int* wclip, double* flux_out, int* clip_out_bits) {
+                                    uint64_t* bwords, double* wsum, int* wclip, double* flux_out,
+                                    int* clip_out_bits) {
   using T = typename MAP::T;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -242,6 +243,7 @@ __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L
   double acc = 0.0;
   int clip = 0;
   T* buf = rowbuf_all + wave * (JMAX * 64);
+  uint64_t* bwl = bwords + wave * (2 * JMAX);
 
   // Chunk culling: a 64-column chunk of a row is skipped when the arc through it, widened
   // by two columns on each side, provably maps farther than rho (1 + 1e-3) from the source
@@ -297,12 +299,25 @@ __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L
       if (m[0] & 1ull) clip |= 4;
       if (in_last) clip |= 8;
     }
+    // boundary words (wave-uniform): inside nodes whose left (side 0) or right (side 1)
+    // neighbour is outside or beyond a non-periodic edge; their popcounts stay scalar and
+    // the words go to LDS, so a lane's rank search compares counts only and reads one word
     int n_left = 0, n_all = 0;
+    int pc0[JMAX], pc1[JMAX];
 #pragma unroll
     for (int j = 0; j < JMAX; ++j) {
+      pc0[j] = pc1[j] = 0;
       if (EXACT || j < J) {
-        n_left += __popcll(boundary_word<JMAX>(m, j, J, 0, per, in_last, jl, bl));
-        n_all += __popcll(boundary_word<JMAX>(m, j, J, 1, per, in_last, jl, bl));
+        const uint64_t w0 = boundary_word<JMAX>(m, j, J, 0, per, in_last, jl, bl);
+        const uint64_t w1 = boundary_word<JMAX>(m, j, J, 1, per, in_last, jl, bl);
+        pc0[j] = __popcll(w0);
+        pc1[j] = __popcll(w1);
+        n_left += pc0[j];
+        n_all += pc1[j];
+        if (lane == 0) {
+          bwl[j] = w0;
+          bwl[JMAX + j] = w1;
+        }
       }
     }
     n_all += n_left;
@@ -315,22 +330,16 @@ __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L
       if (k < n_all) {
         const int side = k >= n_left ? 1 : 0;
         int rem = side ? k - n_left : k;
-        uint64_t word = 0;
         int jw = 0;
 #pragma unroll
         for (int j = 0; j < JMAX; ++j) {
           if (EXACT || j < J) {
-            const uint64_t w0 = boundary_word<JMAX>(m, j, J, 0, per, in_last, jl, bl);
-            const uint64_t w1 = boundary_word<JMAX>(m, j, J, 1, per, in_last, jl, bl);
-            const uint64_t wd = side ? w1 : w0;
-            const int pc = __popcll(wd);
-            if (rem >= 0 && rem < pc) {
-              word = wd;
-              jw = j;
-            }
+            const int pc = side ? pc1[j] : pc0[j];
+            if (rem >= 0 && rem < pc) jw = j;
             if (rem >= 0) rem -= (rem < pc) ? (1 << 30) : pc;
           }
         }
+        uint64_t word = bwl[side * JMAX + jw];
         rem += 1 << 30;  // rank of the node inside its word (< 64 whenever k < n_all)
         for (int q = 0; q < rem && q < 64; ++q) word &= word - 1ull;
         const int l = 64 * jw + __ffsll((unsigned long long)word) - 1;
@@ -389,6 +398,7 @@ __global__ __launch_bounds__(256) void rays_kernel(Batch b, SectorBuf sec, RayWo
                                                    unsigned long long* __restrict__ queue) {
   using T = typename MAP::T;
   __shared__ T rowbuf[kWaves * JMAX * 64];
+  __shared__ uint64_t bwords[kWaves * 2 * JMAX];
   __shared__ double wsum[kWaves];
   __shared__ int wclip[kWaves];
   __shared__ unsigned long long next_sh;
@@ -435,7 +445,7 @@ __global__ __launch_bounds__(256) void rays_kernel(Batch b, SectorBuf sec, RayWo
       }
       double flux = 0.0;
       int c = 0;
-      shoot_sector<N, JMAX, EXACT, MAP>(sp, per, L, wc, p[6], p[7], delta_c, n_r, n_theta, rowbuf, wsum, wclip, &flux,
+      shoot_sector<N, JMAX, EXACT, MAP>(sp, per, L, wc, p[6], p[7], delta_c, n_r, n_theta, rowbuf, bwords, wsum, wclip, &flux,
                                         &c);
       if (threadIdx.x == 0) {
         partial[e * kMaxSectors + slot] = flux;
