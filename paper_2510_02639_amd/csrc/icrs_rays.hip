@@ -284,7 +284,12 @@ __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L
         m[j] = __ballot(in);
         any |= m[j];
         if (EXACT || lane + 64 * j < n_theta) buf[lane + 64 * j] = d2;
-        if (m[j]) row += in ? brightness<T>(d2, inv_rho2, i_lin, i_sqrt) : T(0);
+        if (m[j]) {
+          // an empty inline asm keeps this wave-uniform branch a branch: without it the
+          // compiler computes the brightness for every chunk and selects
+          __asm__ volatile("");
+          row += in ? brightness<T>(d2, inv_rho2, i_lin, i_sqrt) : T(0);
+        }
       }
     }
     if (any == 0) continue;  // wave-uniform: the row misses the image
