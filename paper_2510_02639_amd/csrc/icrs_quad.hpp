@@ -22,12 +22,20 @@ struct Num<float> {
   static constexpr int fast_steps = 3;
 };
 
+// sqrt(c) for c >= 0 from the hardware reciprocal square root (one Newton step in FP64)
+__device__ __forceinline__ double sqrt_fast(double c) {
+  double y = __builtin_amdgcn_rsq(c);
+  y = y * fma(-0.5 * c * y, y, 1.5);
+  return c > 0.0 ? c * y : 0.0;
+}
+__device__ __forceinline__ float sqrt_fast(float c) { return __builtin_amdgcn_sqrtf(c); }
+
 // f(delta) of App. A.2 (u1 > 0) or delta + 1/2 (uniform source, App. A.1)
 template <typename T>
 __device__ __forceinline__ T edge_factor(T delta, T u1, T delta_c) {
   if (u1 == T(0)) return delta + T(0.5);
   if (delta >= delta_c && delta > T(0))
-    return (T(0.5) + delta) * T(2.0 / 3.0) * sqrt(T(1) + T(0.5) * rcp_fast(delta));
+    return (T(0.5) + delta) * T(2.0 / 3.0) * sqrt_fast(T(1) + T(0.5) * rcp_fast(delta));
   return T(2.0 / 3.0) * delta + T(0.5);
 }
 
@@ -82,13 +90,6 @@ __device__ inline T crossing_t(T d0, T d1, T d2, T d3, bool cubic, T rho) {
   return t;
 }
 
-// sqrt(c) for c >= 0 from the hardware reciprocal square root (one Newton step in FP64)
-__device__ __forceinline__ double sqrt_fast(double c) {
-  double y = __builtin_amdgcn_rsq(c);
-  y = y * fma(-0.5 * c * y, y, 1.5);
-  return c > 0.0 ? c * y : 0.0;
-}
-__device__ __forceinline__ float sqrt_fast(float c) { return __builtin_amdgcn_sqrtf(c); }
 
 // e^{i x} - 1 without cancellation: (-2 sin^2(x/2), sin x)
 __device__ __forceinline__ c64 expm1_i(double x) {

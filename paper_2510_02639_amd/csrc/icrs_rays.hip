@@ -360,7 +360,8 @@ __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L
           const int im1 = per ? (pp == 0 ? last : pp - 1) : max(pp - 1, 0);
           const int ip1 = pp == last ? 0 : pp + 1;
           const int ip2 = per ? (pp + 2 > last ? pp + 2 - n_theta : pp + 2) : min(pp + 2, last);
-          const T t = crossing_t<T>(sqrt(buf[im1]), sqrt(buf[pp]), sqrt(buf[ip1]), sqrt(buf[ip2]), cubic, rho);
+          const T t = crossing_t<T>(sqrt_fast(buf[im1]), sqrt_fast(buf[pp]), sqrt_fast(buf[ip1]),
+                                      sqrt_fast(buf[ip2]), cubic, rho);
           corr = edge_factor<T>(side ? t : T(1) - t, u1, delta_c) - T(1);
         }
         row += brightness<T>(buf[l], inv_rho2, i_lin, i_sqrt) * corr;
