@@ -215,13 +215,57 @@ __device__ __forceinline__ uint64_t boundary_word(const uint64_t (&m)[JMAX], int
   return m[j] & ~right;
 }
 
+// Per-wave queue of boundary nodes waiting for their crossing correction.  Rows append
+// their (node, side) items with the stencil already read from the row buffer; one pass of
+// 64 lanes then solves 64 crossings at once instead of a handful per row.
+constexpr int kQueue = 128;
+
+template <typename T>
+struct CrossQueue {
+  T d[4][kQueue];    // stencil distances d_{p-1}, d_p, d_{p+1}, d_{p+2}
+  T b[kQueue];       // brightness of the boundary node
+  double r[kQueue];  // its row radius
+  int f[kQueue];     // bit 0: side (1 = right), bit 1: cubic stencil, bit 2: neighbour beyond an edge
+};
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// sum over the n queued items of r_i I (f(delta) - 1), lane k taking items k, k + 64, ...;
+// one out-of-line copy serves every call site
+template <typename T>
+__device__ __attribute__((noinline)) double flush_crossings(const CrossQueue<T>* q, int n, T rho, T u1, T delta_c,
+                                                            T f_edge) {
+  const int lane = threadIdx.x & 63;
+  double s = 0.0;
+  for (int base = 0; base < n; base += 64) {
+    const int k = base + lane;
+    if (k < n) {
+      const int f = q->f[k];
+      T corr;
+      if (f & 4) {
+        corr = f_edge;
+      } else {
+        // side 0: crossing in (theta_{l-1}, theta_l), delta = 1 - t; side 1: in (theta_l, theta_{l+1}), delta = t
+        const T t = crossing_t<T>(q->d[0][k], q->d[1][k], q->d[2][k], q->d[3][k], (f & 2) != 0, rho);
+        corr = edge_factor<T>((f & 1) ? t : T(1) - t, u1, delta_c) - T(1);
+      }
+      s += q->r[k] * (double)(q->b[k] * corr);
+    }
+  }
+  return s;
+}
+
 // One (epoch, sector) grid shot by the whole workgroup; the flux and clip bits end up in
 // thread 0.  EXACT: n_theta == 64 * JMAX (no partial column chunk).
 template <int N, int JMAX, bool EXACT, typename MAP>
 __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L, c64 wc, double rho_d, double u1_d,
                                     double delta_c_d, int n_r, int n_theta, typename MAP::T* rowbuf_all,
-                                    uint64_t* bwords, double* wsum, int* wclip, double* flux_out,
-                                    int* clip_out_bits) {
+                                    uint64_t* bwords, CrossQueue<typename MAP::T>* queues, double* wsum,
+                                    int* wclip, double* flux_out, int* clip_out_bits) {
   using T = typename MAP::T;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -244,6 +288,8 @@ __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L
   int clip = 0;
   T* buf = rowbuf_all + wave * (JMAX * 64);
   uint64_t* bwl = bwords + wave * (2 * JMAX);
+  CrossQueue<T>* cq = queues + wave;
+  int qn = 0;
 
   // Chunk culling: a 64-column chunk of a row is skipped when the arc through it, widened
   // by two columns on each side, provably maps farther than rho (1 + 1e-3) from the source
@@ -329,8 +375,14 @@ __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // one crossing (node, side) per lane
+    // queue the row's crossings, 64 per step, flushing when the queue would overflow
     for (int base = 0; base < n_all; base += 64) {
+      if (qn + 64 > kQueue) {
+        wave_lds_sync();
+        acc += flush_crossings<T>(cq, qn, rho, u1, delta_c, f_edge);
+        wave_lds_sync();
+        qn = 0;
+      }
       const int k = base + lane;
       if (k < n_all) {
         const int side = k >= n_left ? 1 : 0;
@@ -348,29 +400,38 @@ __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L
         rem += 1 << 30;  // rank of the node inside its word (< 64 whenever k < n_all)
         for (int q = 0; q < rem && q < 64; ++q) word &= word - 1ull;
         const int l = 64 * jw + __ffsll((unsigned long long)word) - 1;
-        T corr;
+        const int slot = qn + lane;
+        int fl = side;
         if ((side == 0 && l == 0 && !per) || (side == 1 && l == last && !per)) {
-          corr = f_edge;
+          fl |= 4;
         } else {
-          // side 0: crossing in (theta_{l-1}, theta_l), bracket p = l-1, delta = 1 - t
-          // side 1: crossing in (theta_l, theta_{l+1}), bracket p = l,   delta = t
+          // side 0: crossing in (theta_{l-1}, theta_l), bracket p = l-1; side 1: in (theta_l, theta_{l+1}), p = l
           const int pp = side ? l : (l == 0 ? last : l - 1);
           const bool cubic = per || (pp - 1 >= 0 && pp + 2 <= last);
           // neighbours of pp in [0, n_theta): wrap by one subtraction (periodic) or clamp
           const int im1 = per ? (pp == 0 ? last : pp - 1) : max(pp - 1, 0);
           const int ip1 = pp == last ? 0 : pp + 1;
           const int ip2 = per ? (pp + 2 > last ? pp + 2 - n_theta : pp + 2) : min(pp + 2, last);
-          const T t = crossing_t<T>(sqrt_fast(buf[im1]), sqrt_fast(buf[pp]), sqrt_fast(buf[ip1]),
-                                      sqrt_fast(buf[ip2]), cubic, rho);
-          corr = edge_factor<T>(side ? t : T(1) - t, u1, delta_c) - T(1);
+          cq->d[0][slot] = sqrt_fast(buf[im1]);
+          cq->d[1][slot] = sqrt_fast(buf[pp]);
+          cq->d[2][slot] = sqrt_fast(buf[ip1]);
+          cq->d[3][slot] = sqrt_fast(buf[ip2]);
+          if (cubic) fl |= 2;
         }
-        row += brightness<T>(buf[l], inv_rho2, i_lin, i_sqrt) * corr;
+        cq->b[slot] = brightness<T>(buf[l], inv_rho2, i_lin, i_sqrt);
+        cq->r[slot] = r;
+        cq->f[slot] = fl;
       }
+      qn += min(64, n_all - base);
     }
     acc += r * (double)row;
     __builtin_amdgcn_wave_barrier();
   }
 
+  if (qn > 0) {
+    wave_lds_sync();
+    acc += flush_crossings<T>(cq, qn, rho, u1, delta_c, f_edge);
+  }
   // deterministic reductions: butterfly inside the wave, then waves in order
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
@@ -405,6 +466,7 @@ __global__ __launch_bounds__(256) void rays_kernel(Batch b, SectorBuf sec, RayWo
   using T = typename MAP::T;
   __shared__ T rowbuf[kWaves * JMAX * 64];
   __shared__ uint64_t bwords[kWaves * 2 * JMAX];
+  __shared__ CrossQueue<T> queues[kWaves];
   __shared__ double wsum[kWaves];
   __shared__ int wclip[kWaves];
   __shared__ unsigned long long next_sh;
@@ -451,7 +513,7 @@ __global__ __launch_bounds__(256) void rays_kernel(Batch b, SectorBuf sec, RayWo
       }
       double flux = 0.0;
       int c = 0;
-      shoot_sector<N, JMAX, EXACT, MAP>(sp, per, L, wc, p[6], p[7], delta_c, n_r, n_theta, rowbuf, bwords, wsum, wclip, &flux,
+      shoot_sector<N, JMAX, EXACT, MAP>(sp, per, L, wc, p[6], p[7], delta_c, n_r, n_theta, rowbuf, bwords, queues, wsum, wclip, &flux,
                                         &c);
       if (threadIdx.x == 0) {
         partial[e * kMaxSectors + slot] = flux;
