@@ -161,7 +161,7 @@ __device__ inline double fp32_error_bound(const Lens<N>& L, const double* sp, bo
   }
   return 5.96e-8 * (1.0 + dz * amp / rho);
 }
-constexpr double kFp32Budget = 6e-5;  // per-node distance error (relative to rho) allowed in FP32
+constexpr double kFp32Budget = 3e-5;  // per-node distance error (relative to rho) allowed in FP32
 
 // Lower bound of d = |w(z) - w_c| over the arc z = z0 e^{i phi}, |phi| <= Phi, z0 = r e^{i theta_c}.
 // w(z) = z + f(conj z) with f holomorphic, so for Delta = z - z0:
