@@ -33,6 +33,8 @@ constexpr int kWaves = 4;
 template <int N, int JMAX>
 struct MapF64 {
   using T = double;
+  static constexpr bool kRefine = false;
+  static constexpr int kMinWaves = 1;  // no occupancy floor
   double cs[JMAX], sn[JMAX];
   Lens<N> L;
   c64 wc;
@@ -74,6 +76,9 @@ struct MapF64 {
 template <int N, int JMAX>
 struct MapF32 {
   using T = float;
+  static constexpr bool kRefine = true;  // chi of nodes near the edge decided in FP64
+  // binary lens, up to 512 columns: held to 168 VGPRs (three waves per SIMD) without spills
+  static constexpr int kMinWaves = (N == 2 && JMAX <= 8) ? 3 : 1;
   float gx[JMAX], gy[JMAX];  // e^{i theta_s} (e^{i dtheta_l} - 1) per owned column
   float ux0, uy0;            // e^{i theta_s}
   float bx, by;              // w(z_s) - w_c
@@ -140,6 +145,9 @@ struct MapF32 {
 // Rounding bound of the FP32 map on one sector, relative to rho: |dz| is at most the chord
 // of the half angular width plus half the radial extent, and each lens term is at most
 // eps_k |dz| / dist_k^2 with dist_k a lower bound of the lens' distance to the sector box.
+// The map rounds quantities of that size a handful of times; four units in the last place
+// (2^-22) per unit of |dz| amp / rho keep the figure above the error of an FP32 emulation of
+// the map on sampled workload sectors, which reaches 2.3 units.
 template <int N>
 __device__ inline double fp32_error_bound(const Lens<N>& L, const double* sp, bool per, double rho) {
   const double r_lo = sp[0], r_hi = sp[1], th_lo = sp[2], th_hi = sp[3];
@@ -159,9 +167,32 @@ __device__ inline double fp32_error_bound(const Lens<N>& L, const double* sp, bo
     const double dist = fmax(dr, rk * (dth >= 0.5 * kPi ? 1.0 : sin(dth)));
     amp += (dist > 0.0) ? L.eps[k] / (dist * dist) : 1e300;
   }
-  return 5.96e-8 * (1.0 + dz * amp / rho);
+  return 0x1p-22 * (1.0 + dz * amp / rho);
 }
 constexpr double kFp32Budget = 3e-5;  // per-node distance error (relative to rho) allowed in FP32
+
+// Nodes whose FP32 squared distance lies within 2 e_s + 2^-21 (relative to rho^2) of rho^2,
+// e_s the sector's rounding bound, have chi decided by the FP64 map: under the limb-darkened
+// edge rule a flipped node moves the sector's flux by a sizeable part of a node's weight, which
+// in a poorly resolved image exceeds the FP32 tolerance.  The FP64 evaluation stays out of
+// line: inlined into the row loop it costs the hot path registers.
+//
+// |w(z) - w_c|^2 at z = r e^{i theta} in FP64 (eq. lens_eq).
+template <int N>
+__device__ __attribute__((noinline)) double node_d2_f64(const Lens<N> L, c64 wc, double r, double theta) {
+  double s, c;
+  sincos(theta, &s, &c);
+  const double x = r * c, y = r * s;
+  double wx = x - wc.x, wy = y - wc.y;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const double dx = x - L.a[k].x, dy = y - L.a[k].y;
+    const double inv = L.eps[k] / fma(dx, dx, dy * dy);
+    wx = fma(-inv, dx, wx);
+    wy = fma(-inv, dy, wy);
+  }
+  return fma(wx, wx, wy * wy);
+}
 
 // Lower bound of d = |w(z) - w_c| over the arc z = z0 e^{i phi}, |phi| <= Phi, z0 = r e^{i theta_c}.
 // w(z) = z + f(conj z) with f holomorphic, so for Delta = z - z0:
@@ -265,13 +296,14 @@ template <int N, int JMAX, bool EXACT, typename MAP>
 __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L, c64 wc, double rho_d, double u1_d,
                                     double delta_c_d, int n_r, int n_theta, typename MAP::T* rowbuf_all,
                                     uint64_t* bwords, CrossQueue<typename MAP::T>* queues, double* wsum,
-                                    int* wclip, double* flux_out, int* clip_out_bits) {
+                                    int* wclip, double ebound, double* flux_out, int* clip_out_bits) {
   using T = typename MAP::T;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const double r_lo = sp[0], r_hi = sp[1];
   const T rho = (T)rho_d, u1 = (T)u1_d, delta_c = (T)delta_c_d;
   const T rho2 = (T)(rho_d * rho_d), inv_rho2 = (T)(1.0 / (rho_d * rho_d));
+  const T chi_band = (T)((2.0 * ebound + 0x1p-21) * rho_d * rho_d);
   const double I0d = 3.0 / (kPi * (3.0 - u1_d));
   const T i_lin = (T)(I0d * (1.0 - u1_d)), i_sqrt = (T)(I0d * u1_d);
   const int J = EXACT ? JMAX : (n_theta + 63) >> 6;
@@ -320,12 +352,14 @@ __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L
     uint64_t m[JMAX];
     uint64_t any = 0;
     T row = T(0);
+    T mind = T(__builtin_inf());  // closest |d^2 - rho^2| among the lane's nodes of the row
 #pragma unroll
     for (int j = 0; j < JMAX; ++j) {
       m[j] = 0;
       if ((EXACT || j < J) && !((rowskip >> j) & 1u)) {
         T d2 = map.d2(j);
         if (!EXACT) d2 = (lane + 64 * j < n_theta) ? d2 : T(__builtin_inf());
+        if constexpr (MAP::kRefine) mind = fmin(mind, fabs(d2 - rho2));
         const bool in = d2 < rho2;
         m[j] = __ballot(in);
         any |= m[j];
@@ -335,6 +369,36 @@ __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L
           // compiler computes the brightness for every chunk and selects
           __asm__ volatile("");
           row += in ? brightness<T>(d2, inv_rho2, i_lin, i_sqrt) : T(0);
+        }
+      }
+    }
+    if constexpr (MAP::kRefine) {
+      if (__ballot(mind <= chi_band)) {
+        // chi of the nodes in the band decided in FP64; the stored FP32 value keeps the
+        // decision (d2 < rho2 iff inside) and the row sum swaps the node's brightness
+        uint32_t mine = 0;
+#pragma unroll
+        for (int j = 0; j < JMAX; ++j)
+          if ((EXACT || j < J) && !((rowskip >> j) & 1u) && (EXACT || lane + 64 * j < n_theta))
+            mine |= (fabs(buf[lane + 64 * j] - rho2) <= chi_band ? 1u : 0u) << j;
+        while (mine) {
+          const int j = __ffs(mine) - 1;
+          mine &= mine - 1u;
+          const int l = lane + 64 * j;
+          const T old = buf[l];
+          const double e = node_d2_f64<N>(L, wc, r, sp[2] + (l + 0.5) * dth);
+          const bool in = e < rho_d * rho_d;
+          const T d2 = in ? fmin((T)e, nextafterf(rho2, T(0))) : fmax((T)e, rho2);
+          buf[l] = d2;
+          row += (in ? brightness<T>(d2, inv_rho2, i_lin, i_sqrt) : T(0)) -
+                 (old < rho2 ? brightness<T>(old, inv_rho2, i_lin, i_sqrt) : T(0));
+        }
+        any = 0;
+#pragma unroll
+        for (int j = 0; j < JMAX; ++j) {
+          if ((EXACT || j < J) && !((rowskip >> j) & 1u))
+            m[j] = __ballot((EXACT || lane + 64 * j < n_theta) && buf[lane + 64 * j] < rho2);
+          any |= m[j];
         }
       }
     }
@@ -459,7 +523,7 @@ __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L
 // budget to w.fallback for the FP64 pass.  Every workgroup leaves once the counter has
 // passed the end.
 template <int N, int JMAX, bool EXACT, typename MAP>
-__global__ __launch_bounds__(256) void rays_kernel(Batch b, SectorBuf sec, RayWork w, int n_r, int n_theta,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MAP::kMinWaves))) void rays_kernel(Batch b, SectorBuf sec, RayWork w, int n_r, int n_theta,
                                                    double delta_c, double* __restrict__ partial,
                                                    uint8_t* __restrict__ clip_out,
                                                    unsigned long long* __restrict__ queue) {
@@ -471,6 +535,7 @@ __global__ __launch_bounds__(256) void rays_kernel(Batch b, SectorBuf sec, RayWo
   __shared__ int wclip[kWaves];
   __shared__ unsigned long long next_sh;
   __shared__ int skip_sh;
+  __shared__ double ebound_sh;
 
   const unsigned long long total = w.items   ? (unsigned long long)(*w.n_items)
                                    : w.n_dev ? (unsigned long long)(*w.n_dev)
@@ -499,22 +564,23 @@ __global__ __launch_bounds__(256) void rays_kernel(Batch b, SectorBuf sec, RayWo
     for (int slot = s0; slot < s1; ++slot) {
       const double* sp = sec.sectors + (e * kMaxSectors + slot) * 4;
       const bool per = sec.periodic[e * kMaxSectors + slot] != 0;
+      double ebound = 0.0;
       if constexpr (sizeof(T) == 4) {
-        if (w.fallback) {
-          if (threadIdx.x == 0) {
-            skip_sh = fp32_error_bound<N>(L, sp, per, p[6]) > kFp32Budget;
-            if (skip_sh) w.fallback[atomicAdd(w.n_fallback, 1)] = (int32_t)(e * 16 + slot);
-          }
-          __syncthreads();
-          const int skip = skip_sh;
-          __syncthreads();
-          if (skip) continue;
+        if (threadIdx.x == 0) {
+          ebound_sh = fp32_error_bound<N>(L, sp, per, p[6]);
+          skip_sh = w.fallback && ebound_sh > kFp32Budget;
+          if (skip_sh) w.fallback[atomicAdd(w.n_fallback, 1)] = (int32_t)(e * 16 + slot);
         }
+        __syncthreads();
+        const int skip = skip_sh;
+        ebound = ebound_sh;
+        __syncthreads();
+        if (skip) continue;
       }
       double flux = 0.0;
       int c = 0;
-      shoot_sector<N, JMAX, EXACT, MAP>(sp, per, L, wc, p[6], p[7], delta_c, n_r, n_theta, rowbuf, bwords, queues, wsum, wclip, &flux,
-                                        &c);
+      shoot_sector<N, JMAX, EXACT, MAP>(sp, per, L, wc, p[6], p[7], delta_c, n_r, n_theta, rowbuf, bwords, queues, wsum,
+                                        wclip, ebound, &flux, &c);
       if (threadIdx.x == 0) {
         partial[e * kMaxSectors + slot] = flux;
         clip_out[e * kMaxSectors + slot] = (uint8_t)c;
