@@ -247,3 +247,25 @@ def test_triple_fp32_rays_config3_grid():
     rel = np.abs(mag.cpu().numpy() / ref["mag"] - 1)
     _report("triple fp32 given grid", rel)
     assert np.all(rel <= FP32_TOL)
+
+
+def test_fp32_rays_on_poorly_resolved_near_caustic_images():
+    """Epochs of the 2048-event benchmark workload where an image covers only a few hundred
+    to a few thousand nodes of its 128 x 512 box, next to a caustic (magnification 10-30).
+    There a node whose FP32 distance falls on the other side of rho than its FP64 distance
+    moves the magnification by up to 4e-4 under the limb-darkened edge rule; the FP32 loop
+    decides such nodes in FP64 and must stay within the FP32 bar on the oracle's sectors."""
+    big = W.metric_workload(2048)
+    epochs = [902185, 2408231, 4723974, 365802, 2649306, 4664374, 367163, 2857995]
+    ev = np.searchsorted(big.offsets, epochs, side="right") - 1
+    t = big.t[epochs]
+    w = W.Workload("near-caustic-fp32", 2, big.params[ev], np.arange(len(epochs) + 1, dtype=np.int64), t, 128, 128,
+                   512, "fp32", "fp32")
+    ref = _oracle(w)
+    h = icrs.Handle(n_lens=2, n_limb=128, n_r=128, n_theta=512, ray_precision="fp32", root_precision="fp32")
+    args = [torch.tensor(ref[k], device="cuda") for k in ("sectors", "periodic", "nsec")]
+    mag, _ = h.magnification_given(w.params, w.offsets, torch.tensor(t, device="cuda"), *args)
+    rel = np.abs(mag.cpu().numpy() / ref["mag"] - 1)
+    _report("fp32 near-caustic images", rel)
+    assert np.all(ref["mag"] > 10)
+    assert np.all(rel <= FP32_TOL)
