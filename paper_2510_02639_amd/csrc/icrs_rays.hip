@@ -201,6 +201,8 @@ __device__ __attribute__((noinline)) double node_d2_f64(const Lens<N> L, c64 wc,
 // and Delta = i z0 phi + e with |e| <= r phi^2 / 2, |Delta| <= r Phi.  The linear part traces
 // the segment c + v phi (c = w0 - w_c, v = i z0 + K conj(i z0)); its distance to the origin
 // less the two remainder bounds is the bound.  Returns 0 when a lens is within r Phi of z0.
+// Quotients and roots use the refined hardware reciprocal and square root: their relative
+// error (~1e-15) is far inside the 1e-3 margin the caller asks for.
 template <int N>
 __device__ inline double arc_distance_lower_bound(const Lens<N>& L, c64 wc, double r, double cth, double sth,
                                                   double Phi) {
@@ -211,25 +213,25 @@ __device__ inline double arc_distance_lower_bound(const Lens<N>& L, c64 wc, doub
   for (int k = 0; k < N; ++k) {
     const double ux = zx - L.a[k].x, uy = zy - L.a[k].y;
     const double u2 = fma(ux, ux, uy * uy);
-    const double dmin = sqrt(u2) - R;
+    const double dmin = sqrt_fast(u2) - R;
     if (!(dmin > 0.0)) return 0.0;
-    const double inv = 1.0 / u2;
+    const double inv = rcp_fast(u2);
     const double gx = L.eps[k] * ux * inv, gy = L.eps[k] * uy * inv;  // eps / conj(u)
     wx -= gx;
     wy -= gy;
     kx += (gx * ux - gy * uy) * inv;  // eps / conj(u)^2 = (eps / conj(u)) (u / |u|^2)
     ky += (gx * uy + gy * ux) * inv;
-    M += L.eps[k] / (dmin * dmin * dmin);
+    M += L.eps[k] * rcp_fast(dmin * dmin * dmin);
   }
   const double tx = -zy, ty = zx;  // i z0
   const double vx = tx + (kx * tx + ky * ty), vy = ty + (ky * tx - kx * ty);
   const double cx = wx - wc.x, cy = wy - wc.y;
   const double vv = fma(vx, vx, vy * vy);
-  double phi = vv > 0.0 ? -(cx * vx + cy * vy) / vv : 0.0;
+  double phi = vv > 0.0 ? -(cx * vx + cy * vy) * rcp_fast(vv) : 0.0;
   phi = fmin(fmax(phi, -Phi), Phi);
   const double ex = fma(vx, phi, cx), ey = fma(vy, phi, cy);
-  const double E = (1.0 + sqrt(fma(kx, kx, ky * ky))) * 0.5 * r * Phi * Phi + M * R * R;
-  return sqrt(fma(ex, ex, ey * ey)) - E;
+  const double E = (1.0 + sqrt_fast(fma(kx, kx, ky * ky))) * 0.5 * r * Phi * Phi + M * R * R;
+  return sqrt_fast(fma(ex, ex, ey * ey)) - E;
 }
 
 // Wave-uniform boundary words of chunk j: inside nodes whose left (side 0) or right
@@ -422,7 +424,7 @@ __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L
 #pragma unroll
     for (int j = 0; j < JMAX; ++j) {
       pc0[j] = pc1[j] = 0;
-      if (EXACT || j < J) {
+      if ((EXACT || j < J) && m[j]) {  // an empty chunk has no boundary nodes
         const uint64_t w0 = boundary_word<JMAX>(m, j, J, 0, per, in_last, jl, bl);
         const uint64_t w1 = boundary_word<JMAX>(m, j, J, 1, per, in_last, jl, bl);
         pc0[j] = __popcll(w0);
