@@ -28,8 +28,8 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
-  size_t params, offsets, epoch_event, sectors, periodic, nsec, partial, clip, list_a, list_b, fallback, jac, counters,
-      total;
+  size_t params, offsets, epoch_event, sectors, periodic, nsec, partial, clip, list_a, list_b, fallback, jac, roots,
+      counters, total;
 };
 
 Layout layout_for(int64_t n_events, int64_t n_epochs) {
@@ -52,6 +52,7 @@ Layout layout_for(int64_t n_events, int64_t n_epochs) {
   L.list_b = take(E * sizeof(int32_t));
   L.fallback = take(E * ICRS_MAX_SECTORS * sizeof(int32_t));
   L.jac = take(E * ICRS_N_PARAMS * sizeof(double));
+  L.roots = take(E * 10 * 2 * sizeof(double));  // the source centre's polynomial roots
   L.counters = take(64);
   L.params = take(V * ICRS_N_PARAMS * sizeof(double));
   L.offsets = take((V + 1) * sizeof(int64_t));
@@ -177,6 +178,7 @@ struct Views {
   int32_t* list_b;
   int32_t* fallback;
   double* jac;
+  double* roots;       // [n_epochs][10] complex: roots of the centre's lens polynomial
   int32_t* counters;   // [0] retry count, [4] FP64 fallback count, [8..9] int64 sector passes,
                        // [12..13] int64 work queue
 };
@@ -202,6 +204,7 @@ icrs_status prepare(icrs_handle* h, int64_t n_events, const double* params, cons
   v->list_b = (int32_t*)(base + L.list_b);
   v->fallback = (int32_t*)(base + L.fallback);
   v->jac = (double*)(base + L.jac);
+  v->roots = (double*)(base + L.roots);
   v->counters = (int32_t*)(base + L.counters);
   if (n_events == 0) return ICRS_OK;
   ICRS_TRY(hipMemcpyAsync(base + L.params, params, (size_t)n_events * ICRS_N_PARAMS * sizeof(double),
@@ -295,8 +298,10 @@ icrs_status run_rays(icrs_handle* h, const Views& v, int max_retries, double* ma
 icrs_status run_plain_device(icrs_handle* h, const Views& v, double* mag, uint32_t* status) {
   const icrs_config& c = h->cfg;
   const int fp32_roots = c.root_precision == ICRS_FP32;
-  ICRS_TRY(icrs::launch_centre_images(c.n_lens, fp32_roots, v.b, nullptr, nullptr, nullptr, status, h->stream));
-  ICRS_TRY(icrs::launch_limb_sectors(c.n_lens, fp32_roots, c.n_limb, v.b, v.sec, status, h->stream));
+  ICRS_TRY(icrs::launch_centre_images(c.n_lens, fp32_roots, v.b, nullptr, nullptr, nullptr, status, h->stream,
+                                      v.roots));
+  ICRS_TRY(icrs::launch_limb_sectors(c.n_lens, fp32_roots, c.n_limb, v.b, v.sec, status, h->stream, nullptr, 0,
+                                     v.roots));
   RayWork w;
   w.n = v.b.n_epochs;
   int32_t* lists[2] = {v.list_a, v.list_b};
@@ -392,10 +397,12 @@ icrs_status icrs_magnification(icrs_handle* h, int64_t n_events, const double* p
   const int fp32_roots = c.root_precision == ICRS_FP32;
   Timer tm(h);
   ICRS_TRY(tm.begin());
-  ICRS_TRY(icrs::launch_centre_images(c.n_lens, fp32_roots, v.b, nullptr, nullptr, nullptr, status, h->stream));
+  ICRS_TRY(icrs::launch_centre_images(c.n_lens, fp32_roots, v.b, nullptr, nullptr, nullptr, status, h->stream,
+                                      v.roots));
   ICRS_TRY(tm.end(&h->prof.ms_centre));
   ICRS_TRY(tm.begin());
-  ICRS_TRY(icrs::launch_limb_sectors(c.n_lens, fp32_roots, c.n_limb, v.b, v.sec, status, h->stream));
+  ICRS_TRY(icrs::launch_limb_sectors(c.n_lens, fp32_roots, c.n_limb, v.b, v.sec, status, h->stream, nullptr, 0,
+                                     v.roots));
   ICRS_TRY(tm.end(&h->prof.ms_limb_sectors));
   ICRS_TRY(tm.flush());
   return run_rays(h, v, c.max_retries, mag, status, 0u);
@@ -437,6 +444,7 @@ icrs_status icrs_run(icrs_handle* h, const double* t, double* mag, uint32_t* sta
   v.list_b = (int32_t*)(base + L.list_b);
   v.fallback = (int32_t*)(base + L.fallback);
   v.jac = (double*)(base + L.jac);
+  v.roots = (double*)(base + L.roots);
   v.counters = (int32_t*)(base + L.counters);
   return run_plain_device(h, v, mag, status);
 }
@@ -581,10 +589,10 @@ icrs_status icrs_image_bounds(icrs_handle* h, int64_t n_events, const double* pa
   const int fp32_roots = c.root_precision == ICRS_FP32;
   double* cimg = (double*)(base + LL.cimg);
   ICRS_TRY(icrs::launch_centre_images(c.n_lens, fp32_roots, v.b, cimg, n_images, (double*)(base + LL.a_c), nullptr,
-                                      h->stream));
+                                      h->stream, v.roots));
   return hip_status(icrs::launch_image_extents(c.n_lens, fp32_roots, c.n_limb, v.b, cimg, n_images,
                                                (double*)(base + LL.ext), features, targets,
-                                               (double*)(base + LL.a_ring), flags, h->stream));
+                                               (double*)(base + LL.a_ring), flags, h->stream, v.roots));
 }
 
 icrs_status icrs_magnification_learned(icrs_handle* h, int64_t n_events, const double* params,
@@ -625,11 +633,11 @@ icrs_status icrs_magnification_learned(icrs_handle* h, int64_t n_events, const d
   int32_t* counts = (int32_t*)(base + LL.counts);
   Timer tm(h);
   ICRS_TRY(tm.begin());
-  ICRS_TRY(icrs::launch_centre_images(c.n_lens, fp32_roots, v.b, cimg, cn, a_c, status, h->stream));
+  ICRS_TRY(icrs::launch_centre_images(c.n_lens, fp32_roots, v.b, cimg, cn, a_c, status, h->stream, v.roots));
   ICRS_TRY(tm.end(&h->prof.ms_centre));
   ICRS_TRY(tm.begin());
   ICRS_TRY(icrs::launch_image_extents(c.n_lens, fp32_roots, lc->n_check, v.b, cimg, cn, ext, feat, nullptr, a_ring,
-                                      flags, h->stream));
+                                      flags, h->stream, v.roots));
   ICRS_TRY(icrs::mlp::launch_forward(packed, mlp_params, norm, n_epochs * MI, feat, y, h->stream));
   ICRS_TRY(icrs::launch_fill_i32(counts, 4, 0, h->stream));
   ICRS_TRY(icrs::launch_learned_sectors(c.n_lens, v.b, cimg, cn, a_c, a_ring, ext, y, lc->log_safety,
@@ -658,7 +666,8 @@ icrs_status icrs_magnification_learned(icrs_handle* h, int64_t n_events, const d
   if (n_fb > 0) {
     const int32_t* fb = lists + n_epochs;
     ICRS_TRY(tm.begin());
-    ICRS_TRY(icrs::launch_limb_sectors(c.n_lens, fp32_roots, c.n_limb, v.b, v.sec, status, h->stream, fb, n_fb));
+    ICRS_TRY(icrs::launch_limb_sectors(c.n_lens, fp32_roots, c.n_limb, v.b, v.sec, status, h->stream, fb, n_fb,
+                                       v.roots));
     ICRS_TRY(tm.end(&h->prof.ms_limb_sectors));
     ICRS_TRY(tm.flush());
     RaySet fs;

@@ -13,6 +13,7 @@ namespace icrs {
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kMaxSectors = 10;  // per-epoch sector slots (cap 5(N-1) <= 10)
+constexpr int kMaxRoots = 10;    // lens-polynomial roots per point, N^2 + 1 <= 10
 constexpr int kBinsTheta = 64;
 constexpr int kBinsR = 32;
 constexpr int kMaxRunsR = 11;      // 32 bins, runs split by >= 2 empty bins
@@ -382,29 +383,55 @@ __device__ inline void accept_image(const Lens<N>& L, c64 w, c64 z0, c64 (&img)[
   if (n < M) img[n++] = z;
 }
 
-// All validated images of the point source at w.  EA in precision T (FP32 roots are
-// polished in FP64 on the lens equation).  Returns status bits.
+// All validated images of the point source at w.  Cold start: EA in precision T (FP32 roots
+// are then refined by FP64 EA).  With warm (the D roots of a nearby point's polynomial, e.g.
+// the source centre's for a limb point) FP64 EA starts there and needs a few iterations; a
+// warm start that does not converge falls back to the cold path.  roots_out, if given,
+// receives the D polynomial roots.  Returns status bits.
+constexpr int kEAWarmIter = 50;
+
 template <int N, typename T>
-__device__ inline uint32_t find_images(const Lens<N>& L, c64 w, c64 (&img)[N * N + 1], int& n_img, int max_iter) {
+__device__ inline uint32_t find_images(const Lens<N>& L, c64 w, c64 (&img)[N * N + 1], int& n_img, int max_iter,
+                                       const c64* warm = nullptr, c64* roots_out = nullptr) {
   constexpr int D = N * N + 1;
   uint32_t st = 0;
   c64 P[D + 1];
   lens_polynomial<N>(L, w, P);
-  cx<T> b[D + 1];
-#pragma unroll
-  for (int j = 0; j <= D; ++j) b[j] = mk(T(P[j].x), T(P[j].y));
-  cx<T> z[D];
-  bool conv = true;
-  ehrlich_aberth<T, D>(b, z, max_iter, &conv);
   c64 zr[D];
+  bool conv = false;
+  if (warm) {
 #pragma unroll
-  for (int k = 0; k < D; ++k) zr[k] = mk(double(z[k].x), double(z[k].y));
-  if constexpr (sizeof(T) == 4) {
-    // FP64 Ehrlich-Aberth from the FP32 roots: the repulsion keeps clustered roots next to
-    // a low-mass lens apart while they converge (FP32 alone cannot resolve them)
-    bool conv64 = true;
-    ehrlich_aberth<double, D>(P, zr, 50, &conv64, true);
-    conv = conv64;
+    for (int k = 0; k < D; ++k) zr[k] = warm[k];
+    conv = true;
+    ehrlich_aberth<double, D>(P, zr, kEAWarmIter, &conv, true);
+    // two starts that settled on one root (the repulsion normally prevents it) leave a root
+    // unfound: take the cold path then
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+      for (int j = i + 1; j < D; ++j)
+        if (norm2(zr[i] - zr[j]) <= 1e-24 * fmax(1.0, norm2(zr[i]))) conv = false;
+  }
+  if (!conv) {
+    cx<T> b[D + 1];
+#pragma unroll
+    for (int j = 0; j <= D; ++j) b[j] = mk(T(P[j].x), T(P[j].y));
+    cx<T> z[D];
+    conv = true;
+    ehrlich_aberth<T, D>(b, z, max_iter, &conv);
+#pragma unroll
+    for (int k = 0; k < D; ++k) zr[k] = mk(double(z[k].x), double(z[k].y));
+    if constexpr (sizeof(T) == 4) {
+      // FP64 Ehrlich-Aberth from the FP32 roots: the repulsion keeps clustered roots next to
+      // a low-mass lens apart while they converge (FP32 alone cannot resolve them)
+      bool conv64 = true;
+      ehrlich_aberth<double, D>(P, zr, 50, &conv64, true);
+      conv = conv64;
+    }
+  }
+  if (roots_out) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) roots_out[k] = zr[k];
   }
   if (!conv) st |= kStRootNonconv;
   n_img = 0;

@@ -24,14 +24,17 @@ struct SectorBuf {
 
 hipError_t launch_epoch_event(const Batch& b, int32_t* epoch_event, hipStream_t s);
 
-// point images of every epoch's source centre; writes status[e] (assigns)
+// point images of every epoch's source centre; writes status[e] (assigns).  roots, if given,
+// receives the polynomial's roots ([n_epochs][kMaxRoots] complex).
 hipError_t launch_centre_images(int n_lens, int root_fp32, const Batch& b, double* images, int32_t* n_images,
-                                double* a_ps, uint32_t* status, hipStream_t s);
+                                double* a_ps, uint32_t* status, hipStream_t s, double* roots = nullptr);
 
 // limb images + sectors (one workgroup per epoch); ORs status bits.  With list, only the
-// n_list epochs it names.
+// n_list epochs it names.  With roots (the centre polynomial's, from launch_centre_images), the
+// limb points' root solves start there.
 hipError_t launch_limb_sectors(int n_lens, int root_fp32, int n_limb, const Batch& b, const SectorBuf& out,
-                               uint32_t* status, hipStream_t s, const int32_t* list = nullptr, int64_t n_list = 0);
+                               uint32_t* status, hipStream_t s, const int32_t* list = nullptr, int64_t n_list = 0,
+                               const double* roots = nullptr);
 
 struct RayWork {
   const int32_t* list = nullptr;    // epochs to process (all their sectors), or nullptr = 0..n-1
@@ -71,7 +74,7 @@ hipError_t launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 // learned-bounds path (icrs_learned.hip)
 hipError_t launch_image_extents(int n_lens, int root_fp32, int n_pts, const Batch& b, const double* cimg,
                                 const int32_t* cn, double* ext, float* feat, float* tgt, double* a_ring,
-                                uint32_t* flags, hipStream_t s);
+                                uint32_t* flags, hipStream_t s, const double* roots = nullptr);
 hipError_t launch_learned_sectors(int n_lens, const Batch& b, const double* cimg, const int32_t* cn,
                                   const double* a_c, const double* a_ring, const double* ext, const float* y,
                                   double log_safety, double margin_frac, double prune_ratio, double vary_max,

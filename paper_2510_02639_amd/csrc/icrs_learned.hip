@@ -77,7 +77,8 @@ template <int N, typename T>
 __global__ __launch_bounds__(256) void image_extents_kernel(Batch b, int n_pts, int P, const double* __restrict__ cimg,
                                                             const int32_t* __restrict__ cn, double* __restrict__ ext,
                                                             float* __restrict__ feat, float* __restrict__ tgt,
-                                                            double* __restrict__ a_ring, uint32_t* __restrict__ flags) {
+                                                            double* __restrict__ a_ring, uint32_t* __restrict__ flags,
+                                                            const double* __restrict__ roots) {
   constexpr int MI = N * N + 1;
   __shared__ c64 cz[kMaxGroups][MI];
   __shared__ unsigned long long key[kMaxGroups][MI][4];
@@ -108,9 +109,12 @@ __global__ __launch_bounds__(256) void image_extents_kernel(Batch b, int n_pts, 
     sincospi(2.0 * k / n_pts, &sp, &cp);
     const double rho = p[6];
     const c64 w = mk(wc.x + rho * cp, wc.y + rho * sp);
-    c64 img[MI];
+    c64 img[MI], warm[MI];
+    if (roots)
+      for (int j = 0; j < MI; ++j) warm[j] = mk(roots[(e * kMaxRoots + j) * 2], roots[(e * kMaxRoots + j) * 2 + 1]);
     int n = 0;
-    const uint32_t st = find_images<N, T>(L, w, img, n, sizeof(T) == 8 ? kEAMaxIterFP64 : kEAMaxIterFP32);
+    const uint32_t st = find_images<N, T>(L, w, img, n, sizeof(T) == 8 ? kEAMaxIterFP64 : kEAMaxIterFP32,
+                                          roots ? warm : nullptr);
     uint32_t f = st ? kLfRoots : 0u;
     if (n != nc) f |= kLfCount;
     double A = 0.0;
@@ -290,7 +294,7 @@ inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) /
 
 hipError_t launch_image_extents(int n_lens, int root_fp32, int n_pts, const Batch& b, const double* cimg,
                                 const int32_t* cn, double* ext, float* feat, float* tgt, double* a_ring,
-                                uint32_t* flags, hipStream_t s) {
+                                uint32_t* flags, hipStream_t s, const double* roots) {
   if (b.n_epochs == 0) return hipSuccess;
   // group width: a power of two covering the points and the images (>= 16); small point
   // counts share a wave between several epochs
@@ -303,17 +307,17 @@ hipError_t launch_image_extents(int n_lens, int root_fp32, int n_pts, const Batc
   if (n_lens == 2) {
     if (root_fp32)
       hipLaunchKernelGGL((image_extents_kernel<2, float>), g, blk, 0, s, b, n_pts, P, cimg, cn, ext, feat, tgt,
-                         a_ring, flags);
+                         a_ring, flags, roots);
     else
       hipLaunchKernelGGL((image_extents_kernel<2, double>), g, blk, 0, s, b, n_pts, P, cimg, cn, ext, feat, tgt,
-                         a_ring, flags);
+                         a_ring, flags, roots);
   } else {
     if (root_fp32)
       hipLaunchKernelGGL((image_extents_kernel<3, float>), g, blk, 0, s, b, n_pts, P, cimg, cn, ext, feat, tgt,
-                         a_ring, flags);
+                         a_ring, flags, roots);
     else
       hipLaunchKernelGGL((image_extents_kernel<3, double>), g, blk, 0, s, b, n_pts, P, cimg, cn, ext, feat, tgt,
-                         a_ring, flags);
+                         a_ring, flags, roots);
   }
   return hipGetLastError();
 }

@@ -38,17 +38,22 @@ __global__ void epoch_event_kernel(const int64_t* __restrict__ off, int64_t n_ev
 template <int N, typename T>
 __global__ __launch_bounds__(256) void centre_images_kernel(Batch b, double* __restrict__ images,
                                                             int32_t* __restrict__ n_images, double* __restrict__ a_ps,
-                                                            uint32_t* __restrict__ status) {
+                                                            uint32_t* __restrict__ status, double* __restrict__ roots) {
   constexpr int MI = N * N + 1;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= b.n_epochs) return;
   const double* p = b.params + (int64_t)b.epoch_event[e] * kParams;
   const Lens<N> L = make_lens<N>(p);
   const c64 wc = source_center(p, b.t[e]);
-  c64 img[MI];
+  c64 img[MI], zr[MI];
   int n = 0;
   const uint32_t st =
-      find_images<N, T>(L, wc, img, n, sizeof(T) == 8 ? kEAMaxIterFP64 : kEAMaxIterFP32);
+      find_images<N, T>(L, wc, img, n, sizeof(T) == 8 ? kEAMaxIterFP64 : kEAMaxIterFP32, nullptr, zr);
+  if (roots)
+    for (int j = 0; j < MI; ++j) {
+      roots[(e * kMaxRoots + j) * 2 + 0] = zr[j].x;
+      roots[(e * kMaxRoots + j) * 2 + 1] = zr[j].y;
+    }
   double A = 0.0;
   for (int j = 0; j < n; ++j) A += 1.0 / fabs(1.0 - norm2(lens_kappa(L, img[j])));
   if (a_ps) a_ps[e] = A;
@@ -64,7 +69,8 @@ __global__ __launch_bounds__(256) void centre_images_kernel(Batch b, double* __r
 template <int N, typename T>
 __global__ __launch_bounds__(256) void limb_sectors_kernel(Batch b, int n_limb, SectorBuf out,
                                                            uint32_t* __restrict__ status,
-                                                           const int32_t* __restrict__ list) {
+                                                           const int32_t* __restrict__ list,
+                                                           const double* __restrict__ roots) {
   constexpr int MI = N * N + 1;  // images per source point at most
   constexpr int cap = 5 * (N - 1);
   extern __shared__ double pts[];  // [blockDim.x * MI] r, then [blockDim.x * MI] theta
@@ -100,8 +106,11 @@ __global__ __launch_bounds__(256) void limb_sectors_kernel(Batch b, int n_limb, 
     double sp, cp;
     sincospi(2.0 * tid / n_limb, &sp, &cp);
     const c64 w = mk(wc.x + rho * cp, wc.y + rho * sp);
-    c64 img[MI];
-    const uint32_t st = find_images<N, T>(L, w, img, n, sizeof(T) == 8 ? kEAMaxIterFP64 : kEAMaxIterFP32);
+    c64 img[MI], warm[MI];
+    if (roots)
+      for (int j = 0; j < MI; ++j) warm[j] = mk(roots[(e * kMaxRoots + j) * 2], roots[(e * kMaxRoots + j) * 2 + 1]);
+    const uint32_t st = find_images<N, T>(L, w, img, n, sizeof(T) == 8 ? kEAMaxIterFP64 : kEAMaxIterFP32,
+                                          roots ? warm : nullptr);
     if (st) atomicOr(&st_sh, st);
     for (int j = 0; j < n; ++j) {
       const double r = hypot(img[j].x, img[j].y);
@@ -288,25 +297,26 @@ hipError_t launch_epoch_event(const Batch& b, int32_t* epoch_event, hipStream_t 
 }
 
 hipError_t launch_centre_images(int n_lens, int root_fp32, const Batch& b, double* images, int32_t* n_images,
-                                double* a_ps, uint32_t* status, hipStream_t s) {
+                                double* a_ps, uint32_t* status, hipStream_t s, double* roots) {
   if (b.n_epochs == 0) return hipSuccess;
   const dim3 g(blocks_for(b.n_epochs, 64)), blk(64);
   if (n_lens == 2) {
     if (root_fp32)
-      hipLaunchKernelGGL((centre_images_kernel<2, float>), g, blk, 0, s, b, images, n_images, a_ps, status);
+      hipLaunchKernelGGL((centre_images_kernel<2, float>), g, blk, 0, s, b, images, n_images, a_ps, status, roots);
     else
-      hipLaunchKernelGGL((centre_images_kernel<2, double>), g, blk, 0, s, b, images, n_images, a_ps, status);
+      hipLaunchKernelGGL((centre_images_kernel<2, double>), g, blk, 0, s, b, images, n_images, a_ps, status, roots);
   } else {
     if (root_fp32)
-      hipLaunchKernelGGL((centre_images_kernel<3, float>), g, blk, 0, s, b, images, n_images, a_ps, status);
+      hipLaunchKernelGGL((centre_images_kernel<3, float>), g, blk, 0, s, b, images, n_images, a_ps, status, roots);
     else
-      hipLaunchKernelGGL((centre_images_kernel<3, double>), g, blk, 0, s, b, images, n_images, a_ps, status);
+      hipLaunchKernelGGL((centre_images_kernel<3, double>), g, blk, 0, s, b, images, n_images, a_ps, status, roots);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_limb_sectors(int n_lens, int root_fp32, int n_limb, const Batch& b, const SectorBuf& out,
-                               uint32_t* status, hipStream_t s, const int32_t* list, int64_t n_list) {
+                               uint32_t* status, hipStream_t s, const int32_t* list, int64_t n_list,
+                               const double* roots) {
   const int64_t n = list ? n_list : b.n_epochs;
   if (n <= 0) return hipSuccess;
   const int bs = ((n_limb + 63) / 64) * 64;
@@ -314,14 +324,14 @@ hipError_t launch_limb_sectors(int n_lens, int root_fp32, int n_limb, const Batc
   const size_t lds = (size_t)bs * (n_lens * n_lens + 1) * 2 * sizeof(double);
   if (n_lens == 2) {
     if (root_fp32)
-      hipLaunchKernelGGL((limb_sectors_kernel<2, float>), g, blk, lds, s, b, n_limb, out, status, list);
+      hipLaunchKernelGGL((limb_sectors_kernel<2, float>), g, blk, lds, s, b, n_limb, out, status, list, roots);
     else
-      hipLaunchKernelGGL((limb_sectors_kernel<2, double>), g, blk, lds, s, b, n_limb, out, status, list);
+      hipLaunchKernelGGL((limb_sectors_kernel<2, double>), g, blk, lds, s, b, n_limb, out, status, list, roots);
   } else {
     if (root_fp32)
-      hipLaunchKernelGGL((limb_sectors_kernel<3, float>), g, blk, lds, s, b, n_limb, out, status, list);
+      hipLaunchKernelGGL((limb_sectors_kernel<3, float>), g, blk, lds, s, b, n_limb, out, status, list, roots);
     else
-      hipLaunchKernelGGL((limb_sectors_kernel<3, double>), g, blk, lds, s, b, n_limb, out, status, list);
+      hipLaunchKernelGGL((limb_sectors_kernel<3, double>), g, blk, lds, s, b, n_limb, out, status, list, roots);
   }
   return hipGetLastError();
 }
