@@ -536,18 +536,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MAP::kMinWa
   __shared__ double wsum[kWaves];
   __shared__ int wclip[kWaves];
   __shared__ unsigned long long next_sh;
-  __shared__ int skip_sh;
-  __shared__ double ebound_sh;
+  __shared__ double ebound_sh[kMaxSectors];
 
   const unsigned long long total = w.items   ? (unsigned long long)(*w.n_items)
                                    : w.n_dev ? (unsigned long long)(*w.n_dev)
                                              : (unsigned long long)w.n;
-  for (;;) {
-    if (threadIdx.x == 0) next_sh = atomicAdd(queue, 1ull);
-    __syncthreads();
-    const unsigned long long idx = next_sh;
-    __syncthreads();
-    if (idx >= total) break;
+  // thread 0 takes the next task's ticket when it starts a task, so the atomic's round trip
+  // overlaps the task's work
+  if (threadIdx.x == 0) next_sh = atomicAdd(queue, 1ull);
+  __syncthreads();
+  unsigned long long idx = next_sh;
+  __syncthreads();
+  while (idx < total) {
+    unsigned long long ticket = 0;
+    if (threadIdx.x == 0) ticket = atomicAdd(queue, 1ull);
     int64_t e;
     int s0, s1;
     if (w.items) {
@@ -563,21 +565,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MAP::kMinWa
     const double* p = b.params + (int64_t)b.epoch_event[e] * kParams;
     const Lens<N> L = make_lens<N>(p);
     const c64 wc = source_center(p, b.t[e]);
+    if constexpr (sizeof(T) == 4) {
+      // the task's sectors get their rounding bounds in parallel, one lane each; sectors
+      // over the budget are listed for the FP64 pass
+      const int slot = s0 + (int)threadIdx.x;
+      if (slot < s1) {
+        const double* sp = sec.sectors + (e * kMaxSectors + slot) * 4;
+        const double eb = fp32_error_bound<N>(L, sp, sec.periodic[e * kMaxSectors + slot] != 0, p[6]);
+        ebound_sh[threadIdx.x] = eb;
+        if (w.fallback && eb > kFp32Budget) w.fallback[atomicAdd(w.n_fallback, 1)] = (int32_t)(e * 16 + slot);
+      }
+      __syncthreads();
+    }
     for (int slot = s0; slot < s1; ++slot) {
       const double* sp = sec.sectors + (e * kMaxSectors + slot) * 4;
       const bool per = sec.periodic[e * kMaxSectors + slot] != 0;
       double ebound = 0.0;
       if constexpr (sizeof(T) == 4) {
-        if (threadIdx.x == 0) {
-          ebound_sh = fp32_error_bound<N>(L, sp, per, p[6]);
-          skip_sh = w.fallback && ebound_sh > kFp32Budget;
-          if (skip_sh) w.fallback[atomicAdd(w.n_fallback, 1)] = (int32_t)(e * 16 + slot);
-        }
-        __syncthreads();
-        const int skip = skip_sh;
-        ebound = ebound_sh;
-        __syncthreads();
-        if (skip) continue;
+        ebound = ebound_sh[slot - s0];
+        if (w.fallback && ebound > kFp32Budget) continue;  // uniform: one LDS value for the workgroup
       }
       double flux = 0.0;
       int c = 0;
@@ -588,6 +594,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MAP::kMinWa
         clip_out[e * kMaxSectors + slot] = (uint8_t)c;
       }
     }
+    if (threadIdx.x == 0) next_sh = ticket;
+    __syncthreads();
+    idx = next_sh;
+    __syncthreads();
   }
 }
 
