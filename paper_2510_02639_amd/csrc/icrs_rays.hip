@@ -255,8 +255,7 @@ constexpr int kQueue = 128;
 
 template <typename T>
 struct CrossQueue {
-  T d[4][kQueue];    // stencil distances d_{p-1}, d_p, d_{p+1}, d_{p+2}
-  T b[kQueue];       // brightness of the boundary node
+  T d[4][kQueue];    // squared stencil distances d_{p-1}^2 .. d_{p+2}^2 (an edge item keeps its node's in d[1])
   double r[kQueue];  // its row radius
   int f[kQueue];     // bit 0: side (1 = right), bit 1: cubic stencil, bit 2: neighbour beyond an edge
 };
@@ -268,25 +267,29 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 // sum over the n queued items of r_i I (f(delta) - 1), lane k taking items k, k + 64, ...;
-// one out-of-line copy serves every call site
+// square roots and brightness are taken here, where every lane has an item.  One out-of-line
+// copy serves every call site.
 template <typename T>
 __device__ __attribute__((noinline)) double flush_crossings(const CrossQueue<T>* q, int n, T rho, T u1, T delta_c,
-                                                            T f_edge) {
+                                                            T f_edge, T inv_rho2, T i_lin, T i_sqrt) {
   const int lane = threadIdx.x & 63;
   double s = 0.0;
   for (int base = 0; base < n; base += 64) {
     const int k = base + lane;
     if (k < n) {
       const int f = q->f[k];
+      // the boundary node is p (right side, or an edge item) or p + 1 (left side)
+      const T b = brightness<T>((f & 5) ? q->d[1][k] : q->d[2][k], inv_rho2, i_lin, i_sqrt);
       T corr;
       if (f & 4) {
         corr = f_edge;
       } else {
         // side 0: crossing in (theta_{l-1}, theta_l), delta = 1 - t; side 1: in (theta_l, theta_{l+1}), delta = t
-        const T t = crossing_t<T>(q->d[0][k], q->d[1][k], q->d[2][k], q->d[3][k], (f & 2) != 0, rho);
+        const T t = crossing_t<T>(sqrt_fast(q->d[0][k]), sqrt_fast(q->d[1][k]), sqrt_fast(q->d[2][k]),
+                                  sqrt_fast(q->d[3][k]), (f & 2) != 0, rho);
         corr = edge_factor<T>((f & 1) ? t : T(1) - t, u1, delta_c) - T(1);
       }
-      s += q->r[k] * (double)(q->b[k] * corr);
+      s += q->r[k] * (double)(b * corr);
     }
   }
   return s;
@@ -445,7 +448,7 @@ __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L
     for (int base = 0; base < n_all; base += 64) {
       if (qn + 64 > kQueue) {
         wave_lds_sync();
-        acc += flush_crossings<T>(cq, qn, rho, u1, delta_c, f_edge);
+        acc += flush_crossings<T>(cq, qn, rho, u1, delta_c, f_edge, inv_rho2, i_lin, i_sqrt);
         wave_lds_sync();
         qn = 0;
       }
@@ -470,6 +473,7 @@ __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L
         int fl = side;
         if ((side == 0 && l == 0 && !per) || (side == 1 && l == last && !per)) {
           fl |= 4;
+          cq->d[1][slot] = buf[l];
         } else {
           // side 0: crossing in (theta_{l-1}, theta_l), bracket p = l-1; side 1: in (theta_l, theta_{l+1}), p = l
           const int pp = side ? l : (l == 0 ? last : l - 1);
@@ -478,13 +482,12 @@ __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L
           const int im1 = per ? (pp == 0 ? last : pp - 1) : max(pp - 1, 0);
           const int ip1 = pp == last ? 0 : pp + 1;
           const int ip2 = per ? (pp + 2 > last ? pp + 2 - n_theta : pp + 2) : min(pp + 2, last);
-          cq->d[0][slot] = sqrt_fast(buf[im1]);
-          cq->d[1][slot] = sqrt_fast(buf[pp]);
-          cq->d[2][slot] = sqrt_fast(buf[ip1]);
-          cq->d[3][slot] = sqrt_fast(buf[ip2]);
+          cq->d[0][slot] = buf[im1];
+          cq->d[1][slot] = buf[pp];
+          cq->d[2][slot] = buf[ip1];
+          cq->d[3][slot] = buf[ip2];
           if (cubic) fl |= 2;
         }
-        cq->b[slot] = brightness<T>(buf[l], inv_rho2, i_lin, i_sqrt);
         cq->r[slot] = r;
         cq->f[slot] = fl;
       }
@@ -496,7 +499,7 @@ __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L
 
   if (qn > 0) {
     wave_lds_sync();
-    acc += flush_crossings<T>(cq, qn, rho, u1, delta_c, f_edge);
+    acc += flush_crossings<T>(cq, qn, rho, u1, delta_c, f_edge, inv_rho2, i_lin, i_sqrt);
   }
   // deterministic reductions: butterfly inside the wave, then waves in order
 #pragma unroll
