@@ -178,11 +178,14 @@ def _planetary_subset(n_events=6, per_event=6, rho=None, seed=2):
                       128, 128, 512, "fp32", "fp32")
 
 
-def test_fp32_rays_given_grid_planetary():
-    """FP32 ray loop (anchor-relative) on the oracle's own sectors: 3e-5 of the FP64 oracle."""
+@pytest.mark.parametrize("n_r,n_theta", [(128, 512), (64, 256), (48, 320), (32, 1024)])
+def test_fp32_rays_given_grid_planetary(n_r, n_theta):
+    """FP32 ray loop (anchor-relative) on the oracle's own sectors: 3e-5 of the FP64 oracle.
+    The grids cover every kernel shape: 4, 8 (with a partial chunk at 320) and 16 column
+    chunks per lane."""
     w = _planetary_subset(rho=1e-3)
     ref = _oracle(w)
-    h = icrs.Handle(n_lens=2, n_limb=128, n_r=128, n_theta=512, ray_precision="fp32", root_precision="fp32")
+    h = icrs.Handle(n_lens=2, n_limb=128, n_r=n_r, n_theta=n_theta, ray_precision="fp32", root_precision="fp32")
     t = torch.tensor(w.t, device="cuda")
     mag, st = h.magnification_given(w.params, w.offsets, t, torch.tensor(ref["sectors"], device="cuda"),
                                     torch.tensor(ref["periodic"], device="cuda"),
@@ -192,10 +195,10 @@ def test_fp32_rays_given_grid_planetary():
     for i in range(w.n_events):
         sl = slice(w.offsets[i], w.offsets[i + 1])
         om.append(O.magnification_given(2, w.params[i], w.t[sl], ref["sectors"][sl], ref["periodic"][sl],
-                                        ref["nsec"][sl], 128, 512)[0])
+                                        ref["nsec"][sl], n_r, n_theta)[0])
     om = np.concatenate(om)
     rel = np.abs(mag.cpu().numpy() / om - 1)
-    _report("given fp32 planetary", rel)
+    _report(f"given fp32 planetary {n_r}x{n_theta}", rel)
     assert np.all(rel <= FP32_TOL)
 
 
