@@ -85,7 +85,69 @@ def cpu_baseline(w, mags, budget_s, seed=0):
         "value": idx.size / dt, "unit": "epochs/s", "cores": O.num_threads(), "kind": "oracle",
         "sample": f"{idx.size} epochs drawn uniformly (seed {seed}) from the same workload, FP64 oracle "
                   f"(plain path), {w.n_r}x{w.n_theta} grids, {dt:.1f} s",
-    }, acc
+    }, acc, (idx[good], ref[good])
+
+
+PLAIN_LADDER = [(128, 512), (256, 512), (256, 1024), (512, 1024)]
+LEARNED_LADDER = [(64, 256), (128, 512), (256, 512), (256, 1024)]
+
+
+def accuracy_sweep(w, model, gate_rel, idx, ref, every=10):
+    """Throughput against true accuracy: each path on a ladder of grids, its error against the
+    grid-free disk quadrature on the sampled epochs, and its rate on every `every`-th epoch of
+    the workload (inputs resident, one warm-up call, then one timed call).  The learned rungs
+    hand their fallback epochs to the plain grid of the same rung.  Picks, per path, the
+    fastest grid whose median error is at most 1e-4."""
+    import torch
+    from paper_2510_02639_amd import icrs, workloads
+    ev_of = np.repeat(np.arange(w.n_events), np.diff(w.offsets))
+    one = workloads.Workload("sampled", 2, w.params[ev_of[idx]], np.arange(idx.size + 1, dtype=np.int64), w.t[idx],
+                             w.n_limb, w.n_r, w.n_theta, "fp32", "fp32")
+    sub = w.sample_epochs(every)
+    t_one = torch.tensor(one.t, device="cuda")
+    t_sub = torch.tensor(sub.t, device="cuda")
+    out = {"reference": f"grid-free source-disk quadrature of the oracle on {idx.size} sampled epochs",
+           "rate_subset_epochs": int(sub.n_epochs)}
+
+    def stats(m):
+        e = np.abs(m / ref - 1.0)
+        return {"median": float(np.median(e)), "p90": float(np.quantile(e, 0.9)),
+                "p99": float(np.quantile(e, 0.99)), "frac_le_1e-4": float(np.mean(e <= 1e-4))}
+
+    def rate(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return sub.n_epochs / (time.perf_counter() - t0)
+
+    for name, ladder in (("plain", PLAIN_LADDER), ("batched+learned", LEARNED_LADDER)):
+        rows = []
+        for rung, (n_r, n_theta) in enumerate(ladder):
+            pg = PLAIN_LADDER[rung]
+            hg = icrs.Handle(n_lens=2, n_limb=w.n_limb, n_r=pg[0], n_theta=pg[1], ray_precision="fp32",
+                             root_precision="fp32")
+            if name == "plain":
+                m = hg.magnification(one.params, one.offsets, t_one)[0].cpu().numpy()
+                ws = hg.workspace(sub.n_events, sub.n_epochs)
+                r = rate(lambda: hg.magnification(sub.params, sub.offsets, t_sub, workspace=ws))
+            else:
+                m = hg.magnification_learned(one.params, one.offsets, t_one, model, n_r=n_r, n_theta=n_theta,
+                                             gate_rel=gate_rel)[0].cpu().numpy()
+                ws = hg.learned_workspace(sub.n_events, sub.n_epochs)
+                r = rate(lambda: hg.magnification_learned(sub.params, sub.offsets, t_sub, model, workspace=ws,
+                                                          n_r=n_r, n_theta=n_theta, gate_rel=gate_rel))
+            rows.append({"grid": [n_r, n_theta], "epochs_per_s": r, **stats(m)})
+            print(f"[bench] sweep {name} {n_r}x{n_theta}: {r:.3g} epochs/s, median err {rows[-1]['median']:.2e}",
+                  file=sys.stderr, flush=True)
+        out[name] = rows
+    pick = {}
+    for name in ("plain", "batched+learned"):
+        ok = [r for r in out[name] if r["median"] <= 1e-4]
+        pick[name] = max(ok, key=lambda r: r["epochs_per_s"]) if ok else None
+    out["median_le_1e-4"] = pick
+    return out
 
 
 def timed_steps(fn, steps, warmup, label, after_warmup=None):
@@ -116,6 +178,7 @@ def main():
     ap.add_argument("--roots", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the accuracy/throughput sweep over grids")
     ap.add_argument("--plain-only", action="store_true", help="time the plain path only (profiling runs)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration) and exit")
@@ -221,9 +284,11 @@ def main():
         mags = {"plain": gm_plain}
         if not args.plain_only:
             mags["batched+learned"] = gm_learned
-        base, acc = cpu_baseline(w, mags, args.cpu_seconds)
+        base, acc, (s_idx, s_ref) = cpu_baseline(w, mags, args.cpu_seconds)
         line["cpu_baseline"] = base
         line["accuracy"] = acc
+        if not args.plain_only and not args.no_sweep:
+            line["accuracy_sweep"] = accuracy_sweep(w, model, tune.gate_rel, s_idx, s_ref)
     print(json.dumps(line), flush=True)
 
 
