@@ -132,78 +132,37 @@ __global__ __launch_bounds__(256) void limb_sectors_kernel(Batch b, int n_limb, 
   }
   __syncthreads();
 
-  // 3. runs of occupied bins joined across single empty bins (theta circular)
-  if (tid == 0) {
-    for (int i = 0; i < kBinsTheta; ++i) trun_of[i] = -1;
-    for (int i = 0; i < kBinsR; ++i) rrun_of[i] = -1;
-    int nt = 0, full = 0;
-    int start = -1;
-    for (int bb = 0; bb < kBinsTheta; ++bb)
-      if (occ_t[bb] && !occ_t[(bb + kBinsTheta - 1) % kBinsTheta] && !occ_t[(bb + kBinsTheta - 2) % kBinsTheta]) {
-        start = bb;
-        break;
-      }
-    bool any_t = false;
-    for (int bb = 0; bb < kBinsTheta; ++bb) any_t = any_t || occ_t[bb];
-    if (any_t && start < 0) {  // no gap of two empty bins: a full ring
-      full = 1;
-      nt = 1;
-      trun_first[0] = 0;
-      for (int i = 0; i < kBinsTheta; ++i) trun_of[i] = 0;
-    } else if (any_t) {
-      int bb = start, visited = 0;
-      while (visited < kBinsTheta) {
-        if (!occ_t[bb]) {
-          bb = (bb + 1) % kBinsTheta;
-          ++visited;
-          continue;
-        }
-        const int s0 = bb;
-        int last = bb;
-        bb = (bb + 1) % kBinsTheta;
-        ++visited;
-        while (visited < kBinsTheta) {
-          if (occ_t[bb])
-            last = bb;
-          else if (!occ_t[(bb + 1) % kBinsTheta])
-            break;
-          bb = (bb + 1) % kBinsTheta;
-          ++visited;
-        }
-        const int len = (last - s0 + kBinsTheta) % kBinsTheta + 1;
-        if (nt < kMaxRunsTheta) {
-          trun_first[nt] = s0;
-          for (int q = 0; q < len; ++q) trun_of[(s0 + q) % kBinsTheta] = nt;
-          ++nt;
-        }
-      }
+  // 3. runs of occupied bins joined across single empty bins (theta circular), by bit
+  //    operations on the occupancy masks in the first wave (one lane per bin).  A bin joins a
+  //    run when it is occupied or both its neighbours are (G); runs are the maximal stretches
+  //    of G, numbered from the lowest-index start upwards; a stretch that wraps past bin 63
+  //    is the last run.  G covering the whole circle is one full-ring run.
+  if (tid < 64) {
+    const uint64_t M = __ballot(occ_t[tid] != 0);
+    const uint64_t G = M | (((M << 1) | (M >> 63)) & ((M >> 1) | (M << 63)));
+    const int full = (M != 0ull && G == ~0ull) ? 1 : 0;
+    const uint64_t S = full ? 1ull : G & ~((G << 1) | (G >> 63));  // run starts
+    const int nt = __popcll(S);
+    const uint64_t upto = (tid == 63) ? ~0ull : ((2ull << tid) - 1ull);  // bins 0..tid
+    int tr = -1;
+    if ((G >> tid) & 1ull) {
+      const int c = __popcll(S & upto);
+      tr = c > 0 ? c - 1 : nt - 1;
     }
-    int nr = 0;
-    int bb = 0;
-    while (bb < kBinsR) {
-      if (!occ_r[bb]) {
-        ++bb;
-        continue;
-      }
-      const int s0 = bb;
-      int last = bb;
-      ++bb;
-      while (bb < kBinsR) {
-        if (occ_r[bb])
-          last = bb;
-        else if (bb + 1 >= kBinsR || !occ_r[bb + 1])
-          break;
-        ++bb;
-      }
-      if (nr < kMaxRunsR) {
-        for (int q = s0; q <= last; ++q) rrun_of[q] = nr;
-        ++nr;
-      }
-      bb = last + 1;
+    trun_of[tid] = tr;
+    if ((S >> tid) & 1ull) trun_first[__popcll(S & (upto >> 1))] = tid;
+    const uint32_t Mr = (uint32_t)__ballot(tid < kBinsR && occ_r[tid] != 0);
+    const uint32_t Gr = Mr | ((Mr << 1) & (Mr >> 1));
+    const uint32_t Sr = Gr & ~(Gr << 1);
+    if (tid < kBinsR) {
+      const uint32_t upr = (tid == 31) ? ~0u : ((2u << tid) - 1u);
+      rrun_of[tid] = ((Gr >> tid) & 1u) ? __popc(Sr & upr) - 1 : -1;
     }
-    n_tr = nt;
-    n_rr = nr;
-    full_ring = full;
+    if (tid == 0) {
+      n_tr = nt;
+      n_rr = __popc(Sr);
+      full_ring = full;
+    }
   }
   __syncthreads();
   const int nc = n_tr * n_rr;
