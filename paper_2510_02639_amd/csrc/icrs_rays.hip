@@ -6,8 +6,9 @@
 // columns l, l+64, l+128, ...  For one row a lane maps its nodes through the lens equation,
 // adds the brightness of its inside nodes, and the wave takes ballots of chi = [d < rho].
 // Inside nodes with an outside (or missing) neighbour are found with bit operations on the
-// ballot masks, handed out one per lane, and get their crossing and edge weight in a single
-// pass, reading neighbour distances back from a per-wave LDS row buffer.
+// ballot masks and handed out one per lane; each queues its stencil (squared neighbour
+// distances read back from a per-wave LDS row buffer) in a per-wave LDS queue, and one
+// out-of-line pass solves 64 queued crossings at a time, rows mixed.
 #include "icrs_device.hpp"
 #include "icrs_launch.hpp"
 #include "icrs_quad.hpp"
@@ -250,7 +251,8 @@ __device__ __forceinline__ uint64_t boundary_word(const uint64_t (&m)[JMAX], int
 
 // Per-wave queue of boundary nodes waiting for their crossing correction.  Rows append
 // their (node, side) items with the stencil already read from the row buffer; one pass of
-// 64 lanes then solves 64 crossings at once instead of a handful per row.
+// 64 lanes then solves 64 crossings at once instead of a handful per row.  An item's row
+// radius is its weight r_i.
 constexpr int kQueue = 128;
 
 template <typename T>
@@ -528,10 +530,9 @@ __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L
 // budget to w.fallback for the FP64 pass.  Every workgroup leaves once the counter has
 // passed the end.
 template <int N, int JMAX, bool EXACT, typename MAP>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MAP::kMinWaves))) void rays_kernel(Batch b, SectorBuf sec, RayWork w, int n_r, int n_theta,
-                                                   double delta_c, double* __restrict__ partial,
-                                                   uint8_t* __restrict__ clip_out,
-                                                   unsigned long long* __restrict__ queue) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MAP::kMinWaves))) void rays_kernel(
+    Batch b, SectorBuf sec, RayWork w, int n_r, int n_theta, double delta_c, double* __restrict__ partial,
+    uint8_t* __restrict__ clip_out, unsigned long long* __restrict__ queue) {
   using T = typename MAP::T;
   __shared__ T rowbuf[kWaves * JMAX * 64];
   __shared__ uint64_t bwords[kWaves * 2 * JMAX];
