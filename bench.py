@@ -42,7 +42,7 @@ KERNEL = {"fp32": "rays_kernel<2, 8, true, MapF32<2, 8>>", "fp64": "rays_kernel<
 # scaled by the same counters' reading on a plain copy kernel of known size; keyed by
 # (ray precision, events).  Filled in from measured counter runs; absent (null) when not
 # measured for the current kernel.
-TRAFFIC = {("fp32", 2048): 2.409e9}   # FETCH 861878 KiB x 2.0 + WRITE 629173 KiB x 1.0
+TRAFFIC = {("fp32", 2048): 2.422e9}   # FETCH 867433 KiB x 2.0 + WRITE 630768 KiB x 1.0
 
 
 def cpu_baseline(w, mags, budget_s, seed=0):
