@@ -37,12 +37,18 @@ sys.path.insert(0, ROOT)
 METRIC = "magnified epochs/sec at rho=1e-3 LD (rel err<=1e-4), plain vs batched+learned"
 FLOPS_PER_RAY = {2: 35.0, 3: 48.0}          # algorithmic flop-equivalents per ray
 PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}  # MI355X vector peaks
-KERNEL = {"fp32": "rays_kernel<2, 8, true, MapF32<2, 8>>", "fp64": "rays_kernel<2, 8, true, MapF64<2, 8>>"}
+def kernel_name(rays, n_theta):
+    """The ray kernel instantiation a grid of n_theta columns runs on (4, 8 or 16 columns per lane)."""
+    j = (n_theta + 63) // 64
+    jmax = 4 if j <= 4 else 8 if j <= 8 else 16
+    exact = n_theta % 64 == 0 and j == jmax
+    m = "MapF32" if rays == "fp32" else "MapF64"
+    return f"rays_kernel<2, {jmax}, {'true' if exact else 'false'}, {m}<2, {jmax}>>"
 # HBM bytes per launch of the main ray kernel from rocprofv3 FETCH_SIZE + WRITE_SIZE passes,
 # scaled by the same counters' reading on a plain copy kernel of known size; keyed by
-# (ray precision, events).  Filled in from measured counter runs; absent (null) when not
-# measured for the current kernel.
-TRAFFIC = {("fp32", 2048): 2.422e9}   # FETCH 867433 KiB x 2.0 + WRITE 630768 KiB x 1.0
+# (ray precision, events, path).  Filled in from measured counter runs; absent (null) when
+# not measured for the current kernel.
+TRAFFIC = {("fp32", 2048, "plain"): 2.422e9}   # FETCH 867433 KiB x 2.0 + WRITE 630768 KiB x 1.0
 
 
 def cpu_baseline(w, mags, budget_s, seed=0):
@@ -242,12 +248,28 @@ def main():
             "batched+learned")
         gm_learned = mag_l.cpu().numpy()
         value, dt_value = w.n_epochs * args.steps / dt_learned, dt_learned
+        # one more (untimed) learned step, profiled: the learned boxes' main ray pass
+        h.set_profiling(True)
+        h.get_profile(reset=True)
+        h.magnification_learned(w.params, w.offsets, t, model, mag_l, status_l, ws, n_r=tune.n_r,
+                                n_theta=tune.n_theta, gate_rel=tune.gate_rel)
+        torch.cuda.synchronize()
+        lprof = h.get_profile()
+        h.set_profiling(False)
     else:
         value, dt_value = plain_value, dt_plain
 
-    n_main = max(prof["n_main_launches"], 1)
-    achieved = prof["n_main_rays"] * FLOPS_PER_RAY[2] / (prof["ms_rays_main"] * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.rays]
+
+    def roofline(n_rays, ms, n_launch, n_theta, path, timed):
+        achieved = n_rays * FLOPS_PER_RAY[2] / (ms * 1e-3) / 1e12
+        return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": TRAFFIC.get((args.rays, w.n_events, path)), "kernel": kernel_name(args.rays, n_theta),
+                "flops_per_ray": FLOPS_PER_RAY[2], "rays_per_launch_avg": n_rays / max(n_launch, 1),
+                "kernel_ms_per_launch_avg": ms / max(n_launch, 1), "path_timed": timed}
+
+    roof_plain = roofline(prof["n_main_rays"], prof["ms_rays_main"], prof["n_main_launches"], w.n_theta, "plain",
+                          "plain (one main-pass launch per step)")
     line.update({
         "value": value, "unit": "epochs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": dt_value * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
@@ -265,13 +287,14 @@ def main():
                   "sectors_per_epoch": prof["n_sector_passes"] / max(prof["n_epochs"], 1),
                   "status_counts": {name: int(np.sum((st & bit) != 0)) for name, bit in
                                     [("root_nonconv", 1), ("img_count", 2), ("cap_overflow", 4), ("clip", 8),
-                                     ("nan", 16)]}},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": TRAFFIC.get((args.rays, w.n_events)), "kernel": KERNEL[args.rays],
-                     "flops_per_ray": FLOPS_PER_RAY[2], "rays_per_launch_avg": prof["n_main_rays"] / n_main,
-                     "kernel_ms_per_launch_avg": prof["ms_rays_main"] / n_main,
-                     "path_timed": "plain (one main-pass launch per step)"},
+                                     ("nan", 16)]},
+                  "roofline": roof_plain},
     })
+    # the dominant kernel of the timed step: the learned boxes' main ray pass (the plain
+    # path's main pass when only that path runs)
+    line["roofline"] = roof_plain if args.plain_only else roofline(
+        lprof["n_learned_rays"], lprof["ms_rays_learned"], lprof["n_learned_launches"], tune.n_theta, "learned",
+        "batched+learned (the learned boxes' main ray pass, one launch per step; profiled on one extra step)")
     if not args.plain_only:
         line["learned"] = {"stats_per_step": lstats, "model": "paper_2510_02639_amd/data/bounds_mlp.npz",
                            "log_safety": model.log_safety, "grid": [tune.n_r, tune.n_theta],

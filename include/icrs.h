@@ -184,10 +184,14 @@ typedef struct icrs_profile {
   int64_t n_rays_launches;
   int64_t n_sector_passes;
   int64_t n_epochs;
-  double ms_rays_main;     /* main ray pass of the first attempt            */
-  int64_t n_main_launches;
-  int64_t n_main_sectors;
+  double ms_rays_main;     /* main ray pass of the first attempt over plain  */
+  int64_t n_main_launches; /* sectors (the plain path, the learned path's     */
+  int64_t n_main_sectors;  /* fallback epochs, caller-given sectors)          */
   int64_t n_main_rays;     /* n_main_sectors x that call's n_r x n_theta     */
+  double ms_rays_learned;  /* the same for the learned path's own boxes      */
+  int64_t n_learned_launches;
+  int64_t n_learned_sectors;
+  int64_t n_learned_rays;  /* n_learned_sectors x the learned n_r x n_theta  */
 } icrs_profile;
 
 icrs_status icrs_set_profiling(icrs_handle* h, int on);

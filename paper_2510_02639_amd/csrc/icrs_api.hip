@@ -245,7 +245,9 @@ icrs_status run_rays(icrs_handle* h, const Views& v, int max_retries, double* ma
     ICRS_TRY(icrs::launch_rays(c.n_lens, c.ray_precision, 0, v.b, v.sec, w, c.n_r, c.n_theta, c.delta_c, v.partial,
                                v.clip, (unsigned long long*)(v.counters + 12), v.fallback, v.counters + 4,
                                h->stream));
-    ICRS_TRY(tm.end(&h->prof.ms_rays, attempt == 0 ? &h->prof.ms_rays_main : nullptr));
+    const bool learned = (extra_status & ICRS_ST_LEARNED) != 0;
+    ICRS_TRY(tm.end(&h->prof.ms_rays,
+                    attempt == 0 ? (learned ? &h->prof.ms_rays_learned : &h->prof.ms_rays_main) : nullptr));
     ICRS_TRY(tm.begin());
     ICRS_TRY(icrs::launch_rays(c.n_lens, c.ray_precision, 1, v.b, v.sec, w, c.n_r, c.n_theta, c.delta_c, v.partial,
                                v.clip, (unsigned long long*)(v.counters + 12), v.fallback, v.counters + 4,
@@ -266,9 +268,15 @@ icrs_status run_rays(icrs_handle* h, const Views& v, int max_retries, double* ma
       ICRS_TRY(hipMemcpyAsync(&nfb, v.counters + 4, sizeof(nfb), hipMemcpyDeviceToHost, h->stream));
       ICRS_TRY(hipStreamSynchronize(h->stream));
       const int64_t main = (int64_t)np - (c.ray_precision == ICRS_FP32 ? (int64_t)nfb : 0);
-      h->prof.n_main_launches += 1;
-      h->prof.n_main_sectors += main;
-      h->prof.n_main_rays += main * (int64_t)c.n_r * c.n_theta;
+      if (learned) {
+        h->prof.n_learned_launches += 1;
+        h->prof.n_learned_sectors += main;
+        h->prof.n_learned_rays += main * (int64_t)c.n_r * c.n_theta;
+      } else {
+        h->prof.n_main_launches += 1;
+        h->prof.n_main_sectors += main;
+        h->prof.n_main_rays += main * (int64_t)c.n_r * c.n_theta;
+      }
     }
     if (attempt >= max_retries) break;
     int32_t count = 0;

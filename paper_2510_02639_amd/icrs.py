@@ -37,7 +37,9 @@ class icrs_profile(ctypes.Structure):
                 ("ms_finalize", ctypes.c_double), ("n_calls", ctypes.c_int64), ("n_rays_launches", ctypes.c_int64),
                 ("n_sector_passes", ctypes.c_int64), ("n_epochs", ctypes.c_int64), ("ms_rays_main", ctypes.c_double),
                 ("n_main_launches", ctypes.c_int64), ("n_main_sectors", ctypes.c_int64),
-                ("n_main_rays", ctypes.c_int64)]
+                ("n_main_rays", ctypes.c_int64), ("ms_rays_learned", ctypes.c_double),
+                ("n_learned_launches", ctypes.c_int64), ("n_learned_sectors", ctypes.c_int64),
+                ("n_learned_rays", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -53,3 +53,29 @@ def test_host_only_entry_points():
     bad.n_lens = 4
     h = ctypes.c_void_p()
     assert L.icrs_create(ctypes.byref(bad), None, ctypes.byref(h)) == -1
+
+
+def _struct_fields(name):
+    """(type, field) pairs of `typedef struct name { ... } name;` in the header."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct %s \{(.*?)\} %s;" % (name, name), text, flags=re.S).group(1)
+    out = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        typ, fields = decl.split(None, 1)
+        out += [(typ, f.strip()) for f in fields.split(",")]
+    return out
+
+
+@pytest.mark.parametrize("name", ["icrs_config", "icrs_profile", "icrs_learned_config", "icrs_learned_stats"])
+def test_binding_structs_match_header(name):
+    """The ctypes mirrors of the ABI structs list the header's fields in order, with the same
+    widths, so the library and the binding agree on every offset."""
+    from paper_2510_02639_amd import icrs
+    widths = {"double": 8, "int64_t": 8, "uint64_t": 8, "int32_t": 4, "uint32_t": 4, "int": 4, "float": 4}
+    fields = _struct_fields(name)
+    mirror = getattr(icrs, name)._fields_
+    assert [f for _, f in fields] == [f for f, _ in mirror]
+    assert [widths[t] for t, _ in fields] == [ctypes.sizeof(c) for _, c in mirror]
