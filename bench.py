@@ -48,7 +48,8 @@ def kernel_name(rays, n_theta):
 # scaled by the same counters' reading on a plain copy kernel of known size; keyed by
 # (ray precision, events, path).  Filled in from measured counter runs; absent (null) when
 # not measured for the current kernel.
-TRAFFIC = {("fp32", 2048, "plain"): 2.422e9}   # FETCH 867433 KiB x 2.0 + WRITE 630768 KiB x 1.0
+TRAFFIC = {("fp32", 2048, "plain"): 2.424e9,    # FETCH 868384 KiB x 2.0 + WRITE 630297 KiB x 1.0
+           ("fp32", 2048, "learned"): 2.252e9}  # FETCH 865604 KiB x 2.0 + WRITE 467630 KiB x 1.0
 
 
 def cpu_baseline(w, mags, budget_s, seed=0):
