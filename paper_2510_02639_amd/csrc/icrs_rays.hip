@@ -35,7 +35,8 @@ template <int N, int JMAX>
 struct MapF64 {
   using T = double;
   static constexpr bool kRefine = false;
-  static constexpr int kMinWaves = 1;  // no occupancy floor
+  // binary lens, up to 512 columns: three waves per SIMD (168 VGPRs, a few spills) beat two
+  static constexpr int kMinWaves = (N == 2 && JMAX <= 8) ? 3 : 1;
   double cs[JMAX], sn[JMAX];
   Lens<N> L;
   c64 wc;
