@@ -79,9 +79,9 @@ template <int N, int JMAX>
 struct MapF32 {
   using T = float;
   static constexpr bool kRefine = true;  // chi of nodes near the edge decided in FP64
-  // up to 512 columns: held to 168 VGPRs, three waves per SIMD (the triple lens spills a
-  // few hundred bytes per lane and still runs 22% faster than with two waves)
-  static constexpr int kMinWaves = JMAX <= 8 ? 3 : 1;
+  // held to 168 VGPRs, three waves per SIMD: the triple lens and the 1024-column grids spill
+  // a few hundred bytes per lane and still run ~22% faster than with two waves
+  static constexpr int kMinWaves = 3;
   float gx[JMAX], gy[JMAX];  // e^{i theta_s} (e^{i dtheta_l} - 1) per owned column
   float ux0, uy0;            // e^{i theta_s}
   float bx, by;              // w(z_s) - w_c
