@@ -35,7 +35,7 @@ template <int N, int JMAX>
 struct MapF64 {
   using T = double;
   static constexpr bool kRefine = false;
-  // up to 512 columns: three waves per SIMD (168 VGPRs, a few spills) beat two
+  // up to 512 columns: three waves per SIMD (168 VGPRs, a few spills) beat two and four
   static constexpr int kMinWaves = JMAX <= 8 ? 3 : 1;
   double cs[JMAX], sn[JMAX];
   Lens<N> L;
@@ -79,9 +79,10 @@ template <int N, int JMAX>
 struct MapF32 {
   using T = float;
   static constexpr bool kRefine = true;  // chi of nodes near the edge decided in FP64
-  // held to 168 VGPRs, three waves per SIMD: the triple lens and the 1024-column grids spill
-  // a few hundred bytes per lane and still run ~22% faster than with two waves
-  static constexpr int kMinWaves = 3;
+  // an occupancy floor: the binary lens at four waves per SIMD (128 VGPRs, 160-270 B of
+  // spills per lane) runs ~10% faster than at three and ~40% faster than at two; five or six
+  // waves spill more than they gain; the triple lens is best at three
+  static constexpr int kMinWaves = N == 2 ? 4 : 3;
   float gx[JMAX], gy[JMAX];  // e^{i theta_s} (e^{i dtheta_l} - 1) per owned column
   float ux0, uy0;            // e^{i theta_s}
   float bx, by;              // w(z_s) - w_c
