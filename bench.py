@@ -44,12 +44,14 @@ def kernel_name(rays, n_theta):
     exact = n_theta % 64 == 0 and j == jmax
     m = "MapF32" if rays == "fp32" else "MapF64"
     return f"rays_kernel<2, {jmax}, {'true' if exact else 'false'}, {m}<2, {jmax}>>"
+
+
 # HBM bytes per launch of the main ray kernel from rocprofv3 FETCH_SIZE + WRITE_SIZE passes,
 # scaled by the same counters' reading on a plain copy kernel of known size; keyed by
 # (ray precision, events, path).  Filled in from measured counter runs; absent (null) when
 # not measured for the current kernel.
-TRAFFIC = {("fp32", 2048, "plain"): 2.424e9,    # FETCH 868384 KiB x 2.0 + WRITE 630297 KiB x 1.0
-           ("fp32", 2048, "learned"): 2.252e9}  # FETCH 865604 KiB x 2.0 + WRITE 467630 KiB x 1.0
+TRAFFIC = {("fp32", 2048, "plain"): 2.666e11,   # FETCH 70680782 KiB x 2.0 + WRITE 118964285 KiB x 1.0
+           ("fp32", 2048, "learned"): 6.885e10}  # FETCH 22674013 KiB x 2.0 + WRITE 21886529 KiB x 1.0
 
 
 def cpu_baseline(w, mags, budget_s, seed=0):
