@@ -70,16 +70,16 @@ __device__ inline Bright bright_grad(double d2, double rho, double u1) {
   return b;
 }
 
-// Three waves per SIMD (the LDS allows three workgroups per CU): the compiler's own choice,
-// 256 VGPRs and one or two waves, runs the VJP 1.56x slower despite the spills this costs.
+// Three waves per SIMD: the compiler's own choice, 256 VGPRs and one or two waves, runs the
+// VJP 1.6x slower despite the spills this costs; four waves spill too much.
 template <int N, int JMAX>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void adjoint_kernel(
     Batch b, SectorBuf sec, int n_r, int n_theta, double delta_c, double* __restrict__ jac, double* __restrict__ mag_out,
     unsigned long long* __restrict__ queue) {
   constexpr int NG = 3 * N + 2;
   constexpr int NA = NG + 3;  // g partials, flux, rho, u1
-  __shared__ double colc[kAdjMaxTheta], cols[kAdjMaxTheta];
-  __shared__ double rowbuf[kAW][kAdjMaxTheta];
+  __shared__ double colc[JMAX * 64], cols[JMAX * 64];  // the launch picks JMAX with n_theta <= 64 JMAX
+  __shared__ double rowbuf[kAW][JMAX * 64];
   __shared__ double red[kAW][NA];
   __shared__ unsigned long long next_sh;
 
