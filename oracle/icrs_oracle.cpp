@@ -243,13 +243,18 @@ bool ea_roots(const Poly& P, std::vector<cplx>& z, int* iters_out) {
 // equation itself (with F = lens_map(z) - w and kappa as above, the step solving
 // dz + kappa conj(dz) = -F is dz = (kappa conj(F) - F) / (1 - |kappa|^2)), kept when
 // |F| <= 1e-10 afterwards, and dropped as a duplicate within 1e-9 max(1,|z|) of a kept one.
+// A root still within the residual bound after 8 steps whose steps have not converged (last
+// step above 1e-14 max(1,|z|)) takes up to 8 more while it stays within the bound: a
+// spurious root of the polynomial can wander into an image's basin and stop within the
+// residual bound yet outside the duplicate radius, which would count that image twice.
 // An image count outside {N+1, N+3, ..., 5(N-1)} triggers one extra pass seeded next to
 // each lens (z = a_k - eps_k / conj(w' - a_k), w' = w shifted by the other lenses'
 // deflection at a_k -- the leading-order image near a lens); a count still outside the
 // set raises ST_IMG_COUNT.
 cplx polish(const Lens& L, cplx w, cplx z) {
-  for (int s = 0; s < 8; ++s) {
+  for (int s = 0; s < 16; ++s) {
     const cplx F = lens_map(L, z) - w;
+    if (s >= 8 && !(std::abs(F) <= 1e-10)) break;
     const cplx k = kappa_of(L, z);
     const double den = 1.0 - std::norm(k);
     if (den == 0.0 || !std::isfinite(den)) break;

@@ -349,11 +349,16 @@ __device__ inline int ehrlich_aberth(const cx<T> (&b)[D + 1], cx<T> (&z)[D], int
 // Validation (Sec. 2.1: roots are checked by substitution into eq. lens_eq).  Each candidate
 // gets at most 8 Newton steps on the lens equation itself -- the step solving
 // dz + kappa conj(dz) = -F is (kappa conj(F) - F)/(1 - |kappa|^2) -- and is kept when
-// |F| <= 1e-10, unless it lies within 1e-9 max(1,|z|) of an image already kept.
+// |F| <= 1e-10, unless it lies within 1e-9 max(1,|z|) of an image already kept.  A candidate
+// still within the residual bound after 8 steps that has not converged gets up to 8 more, for
+// as long as it stays within the bound: a spurious root of the polynomial can drift into an
+// image's basin and stop inside the residual bound but outside the duplicate radius, where it
+// would count as a second copy of that image.
 template <int N>
 __device__ inline c64 polish(const Lens<N>& L, c64 w, c64 z) {
-  for (int s = 0; s < 8; ++s) {
+  for (int s = 0; s < 16; ++s) {
     const c64 F = lens_map(L, z) - w;
+    if (s >= 8 && !(norm2(F) <= 1e-20)) break;
     const c64 k = lens_kappa(L, z);
     const double den = 1.0 - norm2(k);
     if (den == 0.0 || !isfinite(den)) break;

@@ -272,3 +272,55 @@ def test_fp32_rays_on_poorly_resolved_near_caustic_images():
     _report("fp32 near-caustic images", rel)
     assert np.all(ref["mag"] > 10)
     assert np.all(rel <= FP32_TOL)
+
+
+def test_full_benchmark_workload_sampled_against_oracle():
+    """The whole 2048-event binary workload (about 5.2 M epochs, FP32 roots and rays,
+    128 limb points, 128 x 512) in the configuration the benchmark times: one handle, one
+    preallocated workspace, output buffers passed in.  Every output is finite, epochs whose
+    limb points lost an image or a root are rare, a second call is bitwise identical, and a
+    seeded sample of epochs (the first and last epoch of the batch and a few flagged ones
+    among them) matches the oracle run end to end on each epoch alone, within the FP32 bar
+    where both choose the same sector count.  (Whether a spurious polynomial root drifts
+    onto an image under Newton's method can differ between the two root paths at the last
+    bit, so the flag itself is compared by its rarity, not epoch by epoch.)"""
+    w = W.metric_workload(2048)
+    h = icrs.Handle(n_lens=2, n_limb=w.n_limb, n_r=w.n_r, n_theta=w.n_theta, ray_precision="fp32",
+                    root_precision="fp32")
+    t = torch.tensor(w.t, device="cuda")
+    mag = torch.empty(w.n_epochs, dtype=torch.float64, device="cuda")
+    status = torch.empty(w.n_epochs, dtype=torch.int32, device="cuda")
+    ws = h.learned_workspace(w.n_events, w.n_epochs)
+    h.magnification(w.params, w.offsets, t, mag, status, ws)
+    first = mag.clone()
+    _, _, ns_all = h.get_sectors(w.n_epochs, ws)
+    h.magnification(w.params, w.offsets, t, mag, status, ws)
+    torch.cuda.synchronize()
+    assert torch.equal(first, mag)
+    m, st = mag.cpu().numpy(), status.cpu().numpy().astype(np.uint32)
+    bits = {name: int(np.count_nonzero(st & v)) for name, v in
+            (("root_nonconv", icrs.ST_ROOT_NONCONV), ("img_count", icrs.ST_IMG_COUNT),
+             ("cap_overflow", icrs.ST_CAP_OVERFLOW), ("clip", icrs.ST_CLIP), ("nan", icrs.ST_NAN))}
+    print(f"full workload: {w.n_epochs} epochs, status bits {bits}", flush=True)
+    assert np.all(np.isfinite(m)) and np.all(m > 0) and bits["nan"] == 0
+    flagged = np.nonzero(st & (icrs.ST_IMG_COUNT | icrs.ST_ROOT_NONCONV))[0]
+    assert flagged.size <= 1e-4 * w.n_epochs
+
+    rng = np.random.default_rng(11)
+    idx = np.unique(np.concatenate([[0, w.n_epochs - 1], rng.choice(w.n_epochs, 46, replace=False),
+                                    flagged[:: max(1, flagged.size // 8)][:8]]))
+    ev = np.searchsorted(w.offsets, idx, side="right") - 1
+    sub = W.Workload("full-sample", 2, w.params[ev], np.arange(idx.size + 1, dtype=np.int64), w.t[idx], w.n_limb,
+                     w.n_r, w.n_theta, "fp32", "fp32")
+    ref = _oracle(sub)
+    ns = ns_all.cpu().numpy()[idx]
+    rel = np.abs(m[idx] / ref["mag"] - 1)
+    same = ns == ref["nsec"]
+    _report("full workload, sampled epochs", rel[same])
+    for e in np.intersect1d(idx, flagged):
+        k = np.searchsorted(idx, e)
+        print(f"flagged epoch {e}: status {st[e]} (oracle {ref['status'][k]}), sectors {ns[k]} (oracle "
+              f"{ref['nsec'][k]}), rel {rel[k]:.2e}", flush=True)
+    print(f"sector-count agreement {same.mean():.3f}", flush=True)
+    assert same.mean() >= 0.9
+    assert np.all(rel[same] <= FP32_TOL)

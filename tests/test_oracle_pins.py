@@ -112,6 +112,26 @@ def test_validated_images_match_bruteforce_newton(n):
         assert imgs.size in ((3, 5) if n == 2 else (4, 6, 8, 10))
 
 
+# planetary binaries (s, q) with a point source just off the central caustic: two of the five
+# polynomial roots are not images, and Newton's method on the lens equation carries them
+# towards a true image; they must not be kept as second copies of it
+_SPURIOUS_ROOT_CASES = [
+    (1.0793728902057527, 0.001167028363938295, complex(-0.008990128174860168, -0.010468223600270318)),
+    (1.089884594939463, 0.0004575128863159917, complex(-0.021429513775496872, 0.01119651425329449)),
+    (0.9083764282993901, 0.007207658833706398, complex(0.1583932445640939, 0.002727332799449043)),
+]
+
+
+@pytest.mark.parametrize("s,q,w", _SPURIOUS_ROOT_CASES)
+def test_spurious_roots_drifting_to_an_image_are_not_counted_twice(s, q, w):
+    eps, a = O.frame(2, O.params(s=s, q=q))
+    imgs, st = O.images(eps, a, w)
+    ref = R.newton_images(eps, a, w)
+    assert ref.size == 3
+    assert st & O.ST_IMG_COUNT == 0
+    assert R.multiset_close(imgs, ref, 1e-8), (imgs, ref)
+
+
 # --- O7: point-source magnification (eqs. amp_point, detJ) ------------------------------
 
 def test_single_lens_point_magnification_closed_form():
