@@ -50,8 +50,8 @@ def kernel_name(rays, n_theta):
 # scaled by the same counters' reading on a plain copy kernel of known size; keyed by
 # (ray precision, events, path).  Filled in from measured counter runs; absent (null) when
 # not measured for the current kernel.
-TRAFFIC = {("fp32", 2048, "plain"): 2.665e11,   # FETCH 70656988 KiB x 2.0 + WRITE 118933661 KiB x 1.0
-           ("fp32", 2048, "learned"): 6.883e10}  # FETCH 22665543 KiB x 2.0 + WRITE 21887251 KiB x 1.0
+TRAFFIC = {("fp32", 2048, "plain"): 2.666e11,   # FETCH 70694665 KiB x 2.0 + WRITE 118944559 KiB x 1.0
+           ("fp32", 2048, "learned"): 6.920e10}  # FETCH 22788467 KiB x 2.0 + WRITE 22001004 KiB x 1.0
 
 
 def cpu_baseline(w, mags, budget_s, seed=0):
