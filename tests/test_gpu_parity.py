@@ -100,6 +100,37 @@ def test_point_images_and_point_magnification():
             assert np.min(np.abs(got - z)) < 1e-9
 
 
+# planetary binaries and source positions where two spurious polynomial roots drift under
+# Newton's method onto a true image (the same cases as the oracle's pins)
+_SPURIOUS_ROOT_CASES = [
+    (1.0793728902057527, 0.001167028363938295, complex(-0.008990128174860168, -0.010468223600270318)),
+    (1.089884594939463, 0.0004575128863159917, complex(-0.021429513775496872, 0.01119651425329449)),
+    (0.9083764282993901, 0.007207658833706398, complex(0.1583932445640939, 0.002727332799449043)),
+]
+
+
+@pytest.mark.parametrize("roots", ["fp32", "fp64"])
+def test_spurious_roots_are_not_kept_as_second_images(roots):
+    """The device's validated images at those positions (trajectory along the real axis
+    through each, alpha = 0) equal the oracle's three, with no image-count flag."""
+    params = np.stack([O.params(s=s, q=q, u0=w.imag, alpha=0.0, t0=0.0, tE=1.0, rho=1e-3, u1=0.5)
+                       for s, q, w in _SPURIOUS_ROOT_CASES])
+    t = np.array([w.real for _, _, w in _SPURIOUS_ROOT_CASES])
+    h = icrs.Handle(n_lens=2, n_limb=128, n_r=128, n_theta=512, ray_precision="fp32", root_precision=roots)
+    img, nimg, _ = h.point_images(params, np.arange(4, dtype=np.int64), torch.tensor(t, device="cuda"))
+    torch.cuda.synchronize()
+    img, nimg = img.cpu().numpy(), nimg.cpu().numpy()
+    for e, (s, q, w) in enumerate(_SPURIOUS_ROOT_CASES):
+        eps, a = O.frame(2, params[e])
+        assert abs(O.source_center(params[e], t[e]) - w) < 1e-15
+        ref, st = O.images(eps, a, w)
+        assert st == 0 and ref.size == 3
+        got = img[e, :nimg[e], 0] + 1j * img[e, :nimg[e], 1]
+        assert nimg[e] == 3, got
+        for z in ref:
+            assert np.min(np.abs(got - z)) < 1e-9
+
+
 def test_ragged_binary_batch_fp64():
     """Uneven events (one empty), planetary mass ratios, FP64 roots and rays at 64 x 256."""
     big = W.binary_batch(2, 8)
