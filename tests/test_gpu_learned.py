@@ -161,3 +161,25 @@ def test_network_gain_over_check_points_alone(small_model):
     st_n, passes_n = res["network"]
     st_c, passes_c = res["check points only"]
     assert st_n["n_fallback"] + passes_n < st_c["n_fallback"] + passes_c
+
+
+def test_learned_results_do_not_depend_on_workspace_contents():
+    """The learned path with the shipped network on a sample of the 2048-event workload: a
+    workspace prefilled with different byte patterns gives bitwise identical magnifications,
+    status words and routing counts."""
+    w = _metric_subset()
+    model = learned.BoundsModel.load()
+    h = icrs.Handle(n_lens=2, n_limb=128, n_r=128, n_theta=512, ray_precision="fp32", root_precision="fp32")
+    t = torch.tensor(w.t, device="cuda")
+    nb = h.learned_workspace(w.n_events, w.n_epochs).numel()
+    out = []
+    for fill in (0x00, 0xFF, 0x3C):
+        ws = torch.full((nb,), fill, dtype=torch.uint8, device="cuda")
+        m, st, stats = h.magnification_learned(w.params, w.offsets, t, model, workspace=ws, n_r=64, n_theta=256,
+                                               gate_rel=3e-3)
+        torch.cuda.synchronize()
+        out.append((m.cpu().numpy(), st.cpu().numpy(), stats))
+    m0, s0, st0 = out[0]
+    assert np.all(np.isfinite(m0)) and st0["n_learned"] > 0
+    for m, s, st in out[1:]:
+        assert np.array_equal(m, m0) and np.array_equal(s, s0) and st == st0
