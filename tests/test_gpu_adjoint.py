@@ -131,3 +131,27 @@ def test_autograd_function_backward_equals_vjp():
     sec, per, ns = h.get_sectors(w.n_epochs)
     grad, _, _ = h.magnification_vjp(w.params, w.offsets, t, sec, per, ns, cotangent=cot)
     assert torch.equal(params.grad, grad.cpu())
+
+
+def test_vjp_does_not_depend_on_workspace_contents():
+    """The reverse-mode call on the forward's sectors, with a workspace prefilled with
+    different byte patterns, gives bitwise identical gradients, Jacobian rows and
+    magnifications (no stale accumulator or counter is read)."""
+    w = _fit_subset(n_events=6, per_event=4)
+    h = icrs.Handle(n_lens=2, n_limb=128, n_r=64, n_theta=256, ray_precision="fp32", root_precision="fp32")
+    t = torch.tensor(w.t, device="cuda")
+    mag, _ = h.magnification(w.params, w.offsets, t)
+    sec, per, ns = h.get_sectors(w.n_epochs)
+    cot = torch.tensor(np.random.default_rng(7).normal(size=w.n_epochs), device="cuda")
+    nb = h.workspace_bytes(w.n_events, w.n_epochs)
+    out = []
+    for fill in (0x00, 0xFF, 0x3C):
+        ws = torch.full((nb,), fill, dtype=torch.uint8, device="cuda")
+        g, j, m = h.magnification_vjp(w.params, w.offsets, t, sec, per, ns, cotangent=cot, jac=True, mag=True,
+                                      workspace=ws)
+        torch.cuda.synchronize()
+        out.append((g.cpu().numpy(), j.cpu().numpy(), m.cpu().numpy()))
+    g0, j0, m0 = out[0]
+    assert np.all(np.isfinite(g0)) and np.all(np.isfinite(j0))
+    for g, j, m in out[1:]:
+        assert np.array_equal(g, g0) and np.array_equal(j, j0) and np.array_equal(m, m0)
