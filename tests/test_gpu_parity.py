@@ -202,6 +202,30 @@ def test_results_do_not_depend_on_workspace_contents(ray):
         assert all(np.array_equal(a, b, equal_nan=True) for a, b in zip(sec, sec0))
 
 
+def test_triple_results_do_not_depend_on_workspace_contents():
+    """The triple-lens workload's configuration (FP64 roots, FP32 rays, 128 x 512) on a few
+    epochs around each event's peak, with differently prefilled workspaces."""
+    big = W.config3(n_events=3, n_epochs=2000)
+    ts, off = [], [0]
+    for i in range(3):
+        seg = big.t[big.offsets[i]:big.offsets[i + 1]][990:1010:4]
+        ts.append(seg)
+        off.append(off[-1] + seg.size)
+    h = icrs.Handle(n_lens=3, n_limb=128, n_r=128, n_theta=512, ray_precision="fp32", root_precision="fp64")
+    t = torch.tensor(np.concatenate(ts), device="cuda")
+    offsets = np.array(off, np.int64)
+    nb = h.workspace_bytes(3, t.numel())
+    out = []
+    for fill in (0x00, 0xFF, 0x3C):
+        ws = torch.full((nb,), fill, dtype=torch.uint8, device="cuda")
+        mag, st = h.magnification(big.params, offsets, t, workspace=ws)
+        torch.cuda.synchronize()
+        out.append((mag.cpu().numpy(), st.cpu().numpy()))
+    assert np.all(np.isfinite(out[0][0]))
+    for m, st in out[1:]:
+        assert np.array_equal(m, out[0][0]) and np.array_equal(st, out[0][1])
+
+
 def test_invalid_arguments_are_rejected_before_launch():
     w = W.config1()
     h = icrs.Handle(n_lens=2)
