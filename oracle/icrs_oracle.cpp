@@ -742,6 +742,15 @@ void widen(Sector& s, int clip) {
   }
 }
 
+// The retry step: every flagged sector widened on its flagged sides, then the list merged to
+// a fixpoint and sorted again (widened sectors may now overlap their neighbours).
+void retry_sectors(std::vector<Sector>& sectors, const std::vector<int>& clips) {
+  for (size_t s = 0; s < sectors.size(); ++s)
+    if (clips[s]) widen(sectors[s], clips[s]);
+  merge_fixpoint(sectors);
+  sort_sectors(sectors);
+}
+
 struct Config {
   int n_limb, n_r, n_theta, max_retries;
   double delta_c;
@@ -788,10 +797,7 @@ double epoch_magnification(const Lens& L, const double* p, double t, const Confi
       st |= ST_CLIP;
       break;
     }
-    for (size_t s = 0; s < sectors.size(); ++s)
-      if (clips[s]) widen(sectors[s], clips[s]);
-    merge_fixpoint(sectors);
-    sort_sectors(sectors);
+    retry_sectors(sectors, clips);
   }
   const double mag = flux / (rho * rho);
   if (!std::isfinite(mag)) st |= ST_NAN;
@@ -1191,6 +1197,23 @@ int orc_build_sectors(int n_pts, const double* r, const double* th, double rho, 
     periodic[s] = S[s].periodic ? 1 : 0;
   }
   if (status) *status = st;
+  return static_cast<int>(S.size());
+}
+
+// O12 retry step on a given list: sec [n][4], periodic [n], clip bits [n] (1 first row,
+// 2 last row, 4 first column, 8 last column); writes the new list and returns its length.
+int orc_retry_sectors(int n, const double* sec, const int* periodic, const int* clips, double* out, int* out_per) {
+  std::vector<Sector> S(n);
+  std::vector<int> c(clips, clips + n);
+  for (int i = 0; i < n; ++i) S[i] = Sector{sec[4 * i], sec[4 * i + 1], sec[4 * i + 2], sec[4 * i + 3], periodic[i] != 0};
+  retry_sectors(S, c);
+  for (size_t i = 0; i < S.size(); ++i) {
+    out[4 * i + 0] = S[i].r_lo;
+    out[4 * i + 1] = S[i].r_hi;
+    out[4 * i + 2] = S[i].th_lo;
+    out[4 * i + 3] = S[i].th_hi;
+    out_per[i] = S[i].periodic ? 1 : 0;
+  }
   return static_cast<int>(S.size());
 }
 

@@ -65,6 +65,8 @@ def lib():
         L.orc_build_sectors.argtypes = [i, P(d), P(d), d, i, P(d), P(i), P(u32)]
         L.orc_build_sectors.restype = i
         L.orc_sector_flux.argtypes = [i, P(d), P(d), P(d), d, d, d, i, i, P(d), i, P(i)]
+        L.orc_retry_sectors.argtypes = [i, P(d), P(i), P(i), P(d), P(i)]
+        L.orc_retry_sectors.restype = i
         L.orc_sector_flux.restype = d
         L.orc_magnification.argtypes = [i, P(d), i64, P(d), i, i, i, d, i, i, P(d), P(u32), P(d), P(u8),
                                         P(i32), P(d)]
@@ -189,6 +191,18 @@ def build_sectors(r, th, rho, cap):
     k = lib().orc_build_sectors(r.size, _p(r), _p(th), float(rho), int(cap), _p(sec), _p(per, ctypes.c_int),
                                 ctypes.byref(st))
     return sec[:k].copy(), per[:k].astype(bool), st.value
+
+
+def retry_sectors(sectors, periodic, clips):
+    """O12 retry step: widen each flagged sector on its flagged sides, merge, sort."""
+    sec = _dbl(sectors).reshape(-1, 4)
+    per = np.ascontiguousarray(periodic, dtype=np.int32).reshape(-1)
+    cl = np.ascontiguousarray(clips, dtype=np.int32).reshape(-1)
+    out = np.zeros((max(sec.shape[0], 1), 4))
+    operi = np.zeros(max(sec.shape[0], 1), dtype=np.int32)
+    k = lib().orc_retry_sectors(sec.shape[0], _p(sec), _p(per, ctypes.c_int), _p(cl, ctypes.c_int), _p(out),
+                                _p(operi, ctypes.c_int))
+    return out[:k].copy(), operi[:k].astype(bool)
 
 
 def sector_flux(eps, a, wc, rho, u1, nr, nth, sector, periodic=False, delta_c=0.1):
