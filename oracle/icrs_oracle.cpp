@@ -1083,6 +1083,172 @@ S sector_flux_t(const LensT<S>& L, const S& wx, const S& wy, const S& rho, const
 }  // namespace
 
 // =======================================================================================
+namespace {
+
+// ---------------------------------------------------------------------------------------
+// O14: point-source magnification as a function of the event parameters and its gradient
+// through the roots (Sec. 3.5).  The images z* are roots of eq. lens_eq_z, P(z*; b) = 0 with
+// coefficients b(params); differentiating that identity gives the paper's root derivative
+//   dz*/db_l = -(z*)^l / P'(z*)        (ascending powers: dP/db_l = z^l),
+// so with the tangents db/dparams of the coefficients (dual numbers through the same
+// construction as O4) each image moves by dz* = -(sum_l z*^l db_l) / P'(z*).  Eq. amp_point
+// then gives A = sum_j 1/|det J(z_j)| with eq. detJ evaluated in dual numbers, through the
+// moved images and the parameter-dependent masses and positions.
+
+// Complex dual number: value and eleven tangents in the real and the imaginary part.
+struct DC {
+  Dual x, y;
+};
+DC operator+(const DC& a, const DC& b) { return {a.x + b.x, a.y + b.y}; }
+DC operator-(const DC& a, const DC& b) { return {a.x - b.x, a.y - b.y}; }
+DC operator*(const DC& a, const DC& b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+DC operator/(const DC& a, const DC& b) {
+  const Dual n = b.x * b.x + b.y * b.y;
+  return {(a.x * b.x + a.y * b.y) / n, (a.y * b.x - a.x * b.y) / n};
+}
+DC dconj(const DC& a) { return {a.x, -a.y}; }
+DC dc(const Dual& x) { return {x, Dual(0.0)}; }
+
+// O4's construction in dual arithmetic: P(z) = (z - w) prod_i D_i - H sum_i eps_i prod_{j!=i} D_j.
+using PolyD = std::vector<DC>;
+PolyD dpmul(const PolyD& a, const PolyD& b) {
+  PolyD c(a.size() + b.size() - 1, dc(Dual(0.0)));
+  for (size_t i = 0; i < a.size(); ++i)
+    for (size_t j = 0; j < b.size(); ++j) c[i + j] = c[i + j] + a[i] * b[j];
+  return c;
+}
+PolyD dpadd(const PolyD& a, const PolyD& b) {
+  PolyD c(std::max(a.size(), b.size()), dc(Dual(0.0)));
+  for (size_t i = 0; i < a.size(); ++i) c[i] = c[i] + a[i];
+  for (size_t i = 0; i < b.size(); ++i) c[i] = c[i] + b[i];
+  return c;
+}
+PolyD dpscale(const PolyD& a, const DC& s) {
+  PolyD c(a);
+  for (auto& x : c) x = x * s;
+  return c;
+}
+PolyD lens_polynomial_dual(const LensT<Dual>& L, const DC& w) {
+  const int n = L.n;
+  const DC one = dc(Dual(1.0));
+  std::vector<DC> a(n);
+  for (int k = 0; k < n; ++k) a[k] = {L.ax[k], L.ay[k]};
+  PolyD H{one};
+  for (int k = 0; k < n; ++k) H = dpmul(H, PolyD{dc(Dual(0.0)) - a[k], one});
+  PolyD G = dpscale(H, dconj(w));
+  for (int k = 0; k < n; ++k) {
+    PolyD Pk{one};
+    for (int j = 0; j < n; ++j)
+      if (j != k) Pk = dpmul(Pk, PolyD{dc(Dual(0.0)) - a[j], one});
+    G = dpadd(G, dpscale(Pk, dc(L.eps[k])));
+  }
+  std::vector<PolyD> D(n);
+  for (int i = 0; i < n; ++i) D[i] = dpadd(G, dpscale(H, dc(Dual(0.0)) - dconj(a[i])));
+  PolyD prodD{one};
+  for (int i = 0; i < n; ++i) prodD = dpmul(prodD, D[i]);
+  PolyD P = dpmul(PolyD{dc(Dual(0.0)) - w, one}, prodD);
+  PolyD S{dc(Dual(0.0))};
+  for (int i = 0; i < n; ++i) {
+    PolyD Q{dc(L.eps[i])};
+    for (int j = 0; j < n; ++j)
+      if (j != i) Q = dpmul(Q, D[j]);
+    S = dpadd(S, Q);
+  }
+  P = dpadd(P, dpscale(dpmul(H, S), dc(Dual(-1.0))));
+  P.resize(n * n + 2, dc(Dual(0.0)));
+  return P;
+}
+
+// A_ps at the source centre of epoch t and dA_ps/dparams (11 entries; rho and u1 do not
+// enter).  Returns the image-finding status bits.
+uint32_t point_mag_jacobian(int n_lens, const double* p, double t, double* A_out, double* jac) {
+  const Lens L = make_lens(n_lens, p);
+  const cplx wc = source_center(p, t);
+  std::vector<cplx> img;
+  const uint32_t st = find_images(L, wc, img);
+  Dual pd[kNT];
+  for (int k = 0; k < kNT; ++k) {
+    pd[k] = Dual(p[k]);
+    pd[k].d[k] = 1.0;
+  }
+  const LensT<Dual> Ld = make_lens_t<Dual>(n_lens, pd);
+  DC w;
+  source_center_t<Dual>(pd, t, &w.x, &w.y);
+  const PolyD B = lens_polynomial_dual(Ld, w);
+  const int deg = static_cast<int>(B.size()) - 1;
+  Dual A(0.0);
+  for (const cplx& z : img) {
+    // P'(z*) from the coefficient values; sum_l z*^l db_l per tangent
+    cplx dP(0.0, 0.0), zl(1.0, 0.0);
+    for (int l = 1; l <= deg; ++l) {
+      dP += static_cast<double>(l) * cplx(B[l].x.v, B[l].y.v) * zl;
+      zl *= z;
+    }
+    DC zd{Dual(z.real()), Dual(z.imag())};
+    for (int k = 0; k < kNT; ++k) {
+      cplx s(0.0, 0.0), zp(1.0, 0.0);
+      for (int l = 0; l <= deg; ++l) {
+        s += cplx(B[l].x.d[k], B[l].y.d[k]) * zp;
+        zp *= z;
+      }
+      const cplx dz = -s / dP;
+      zd.x.d[k] = dz.real();
+      zd.y.d[k] = dz.imag();
+    }
+    // eq. detJ: det J = 1 - |sum_i eps_i / (conj(z) - conj(a_i))^2|^2
+    DC kap = dc(Dual(0.0));
+    for (int i = 0; i < Ld.n; ++i) {
+      const DC d = dconj(zd - DC{Ld.ax[i], Ld.ay[i]});
+      kap = kap + dc(Ld.eps[i]) / (d * d);
+    }
+    const Dual det = Dual(1.0) - (kap.x * kap.x + kap.y * kap.y);
+    A = A + (det.v > 0.0 ? Dual(1.0) / det : Dual(-1.0) / det);
+  }
+  *A_out = A.v;
+  for (int k = 0; k < kNT; ++k) jac[k] = A.d[k];
+  return st;
+}
+
+// ---------------------------------------------------------------------------------------
+// O15: which epochs need the extended-source computation (Sec. 3.4, item iii: only a
+// preselected set of N_ext epochs, e.g. near caustics, is modelled with finite-source
+// effects; the paper gives no selection rule).  Reading: n_check points on the circle of
+// radius guard x rho around the source centre are solved like the centre; the epoch is
+// extended when (1) any of them has a different image count or a root/validation flag (a
+// caustic crosses the circle), (2) the mean of their point-source magnifications differs from
+// the centre's by more than tol A_ps (that mean minus A_ps measures the Laplacian of A_ps,
+// the leading finite-source term), or (3) any one differs by more than vary_max A_ps (a
+// low-order expansion does not hold).  Every other epoch takes A_ps of eq. amp_point.
+constexpr uint32_t ST_POINT = 2048u;  // the epoch took the point-source magnification
+
+bool needs_extended(const Lens& L, const double* p, double t, int n_check, double guard, double tol,
+                    double vary_max, double* A_centre) {
+  const cplx wc = source_center(p, t);
+  std::vector<cplx> img;
+  const uint32_t st = find_images(L, wc, img);
+  double Ac = 0.0;
+  for (const cplx& z : img) Ac += 1.0 / std::abs(1.0 - std::norm(kappa_of(L, z)));
+  *A_centre = Ac;
+  if (st) return true;
+  const double rad = guard * p[6];
+  double sum = 0.0, worst = 0.0;
+  for (int k = 0; k < n_check; ++k) {
+    const double ang = 2.0 * kPi * k / n_check;
+    const cplx w = wc + rad * cplx(std::cos(ang), std::sin(ang));
+    std::vector<cplx> ik;
+    if (find_images(L, w, ik) || ik.size() != img.size()) return true;
+    double Ak = 0.0;
+    for (const cplx& z : ik) Ak += 1.0 / std::abs(1.0 - std::norm(kappa_of(L, z)));
+    sum += Ak;
+    worst = std::max(worst, std::abs(Ak - Ac));
+  }
+  if (std::abs(sum / n_check - Ac) > tol * Ac) return true;
+  if (worst > vary_max * Ac) return true;
+  return false;
+}
+
+}  // namespace
+
 // C entry points for ctypes (tests only).  Complex numbers are passed as (re, im) pairs.
 extern "C" {
 
@@ -1391,6 +1557,53 @@ void orc_disk_mag(int n_lens, const double* params, int64_t n_epochs, const doub
     }
     mag[e] = num / den;
     if (count_changes) count_changes[e] = changes;
+  }
+}
+
+// O14 for a light curve: a_ps [n_epochs], jac [n_epochs][11] = dA_ps/dparams (through the
+// roots, Sec. 3.5), status [n_epochs] (image-finding bits).
+void orc_point_jacobian(int n_lens, const double* params, int64_t n_epochs, const double* t, double* a_ps,
+                        double* jac, uint32_t* status) {
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t e = 0; e < n_epochs; ++e) {
+    const uint32_t st = point_mag_jacobian(n_lens, params, t[e], &a_ps[e], jac + e * kNT);
+    if (status) status[e] = st;
+  }
+}
+
+// O15 for a light curve: extended[e] = 1 for epochs that need the finite-source computation;
+// a_ps [n_epochs] the centre's point-source magnification.
+void orc_hybrid_select(int n_lens, const double* params, int64_t n_epochs, const double* t, int n_check, double guard,
+                       double tol, double vary_max, int32_t* extended, double* a_ps) {
+  const Lens L = make_lens(n_lens, params);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t e = 0; e < n_epochs; ++e) {
+    double Ac = 0.0;
+    extended[e] = needs_extended(L, params, t[e], n_check, guard, tol, vary_max, &Ac) ? 1 : 0;
+    a_ps[e] = Ac;
+  }
+}
+
+// The hybrid light curve (Sec. 3.4, item iii): extended epochs by the full method (as
+// orc_magnification), every other epoch A_ps (status ST_POINT).
+void orc_hybrid(int n_lens, const double* params, int64_t n_epochs, const double* t, int n_check, double guard,
+                double tol, double vary_max, int n_limb, int n_r, int n_theta, double delta_c, int max_retries,
+                double* mag, uint32_t* status) {
+  const Lens L = make_lens(n_lens, params);
+  const Config cfg{n_limb, n_r, n_theta, max_retries, delta_c};
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t e = 0; e < n_epochs; ++e) {
+    double Ac = 0.0;
+    if (needs_extended(L, params, t[e], n_check, guard, tol, vary_max, &Ac)) {
+      std::vector<Sector> S;
+      uint32_t st = 0;
+      double aps = 0.0;
+      mag[e] = epoch_magnification(L, params, t[e], cfg, &st, S, &aps, nullptr);
+      status[e] = st;
+    } else {
+      mag[e] = Ac;
+      status[e] = ST_POINT;
+    }
   }
 }
 

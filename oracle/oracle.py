@@ -21,6 +21,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 N_PARAMS = 11
 ST_ROOT_NONCONV, ST_IMG_COUNT, ST_CAP_OVERFLOW, ST_CLIP, ST_NAN, ST_GIVEN = 1, 2, 4, 8, 16, 64
+ST_POINT = 2048
 
 
 def build(force: bool = True) -> str:
@@ -75,6 +76,9 @@ def lib():
         L.orc_jacobian_given.argtypes = [i, P(d), i64, P(d), i, i, d, i, P(d), P(u8), P(i32), P(d), P(d)]
         L.orc_magnification_frozen.argtypes = [i, P(d), P(d), i64, P(d), i, i, d, i, P(d), P(u8), P(i32), P(d)]
         L.orc_disk_mag.argtypes = [i, P(d), i64, P(d), i, i, P(d), P(i32)]
+        L.orc_point_jacobian.argtypes = [i, P(d), i64, P(d), P(d), P(d), P(u32)]
+        L.orc_hybrid_select.argtypes = [i, P(d), i64, P(d), i, d, d, d, P(i32), P(d)]
+        L.orc_hybrid.argtypes = [i, P(d), i64, P(d), i, d, d, d, i, i, i, d, i, P(d), P(u32)]
         _lib = L
     return _lib
 
@@ -293,3 +297,43 @@ def disk_mag(n_lens, p, t, n_x=32, n_phi=128):
     lib().orc_disk_mag(n_lens, _p(p), n, _p(t), n_x, n_phi, _p(mag), ch.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
     return mag, ch
 
+
+
+def point_jacobian(n_lens, p, t):
+    """Point-source magnification of each epoch's source centre and dA/dparams [E, 11],
+    through the root derivative dz*/db of Sec. 3.5; returns (a_ps, jac, status)."""
+    p = _dbl(p)
+    t = _dbl(np.atleast_1d(t))
+    n = t.size
+    a = np.zeros(n)
+    jac = np.zeros((n, N_PARAMS))
+    st = np.zeros(n, dtype=np.uint32)
+    lib().orc_point_jacobian(n_lens, _p(p), n, _p(t), _p(a), _p(jac), _p(st, ctypes.c_uint32))
+    return a, jac, st
+
+
+def hybrid_select(n_lens, p, t, n_check=16, guard=2.0, tol=1e-4, vary_max=0.1):
+    """Epochs that need the finite-source computation (Sec. 3.4, item iii; selection rule
+    O15); returns (extended bool [E], a_ps [E])."""
+    p = _dbl(p)
+    t = _dbl(np.atleast_1d(t))
+    n = t.size
+    ext = np.zeros(n, dtype=np.int32)
+    a = np.zeros(n)
+    lib().orc_hybrid_select(n_lens, _p(p), n, _p(t), int(n_check), float(guard), float(tol), float(vary_max),
+                            _p(ext, ctypes.c_int32), _p(a))
+    return ext.astype(bool), a
+
+
+def hybrid(n_lens, p, t, n_check=16, guard=2.0, tol=1e-4, vary_max=0.1, n_limb=64, n_r=64, n_theta=256,
+           delta_c=0.1, max_retries=2):
+    """Hybrid light curve: the full method on the selected epochs, A_ps elsewhere (status
+    ST_POINT); returns (mag, status)."""
+    p = _dbl(p)
+    t = _dbl(np.atleast_1d(t))
+    n = t.size
+    mag = np.zeros(n)
+    st = np.zeros(n, dtype=np.uint32)
+    lib().orc_hybrid(n_lens, _p(p), n, _p(t), int(n_check), float(guard), float(tol), float(vary_max), n_limb, n_r,
+                     n_theta, delta_c, max_retries, _p(mag), _p(st, ctypes.c_uint32))
+    return mag, st

@@ -1,0 +1,111 @@
+"""Pins of the oracle's hybrid light curve (Sec. 3.4, item iii: finite-source treatment only
+on preselected epochs, the point-source magnification of eq. amp_point elsewhere) and of the
+point-source gradient through the roots (Sec. 3.5's dz*/db).
+
+* dA_ps/dparams against the closed form of a single lens (a binary whose companion has
+  q = 1e-12) and against central finite differences of A_ps for binary and triple lenses.
+* The selection rule: wherever it keeps the point-source value, that value agrees with the
+  grid-free finite-source magnification (the oracle's source-disk quadrature) to within the
+  rule's tolerance; next to caustic crossings it selects the epoch; the hybrid curve equals
+  the full method on the selected epochs and A_ps on the others.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2510_02639_amd import workloads as W
+from tests import reference_math as R
+
+
+def _dA_du_single(u):
+    return -8.0 / (u * u * (u * u + 4.0) ** 1.5)
+
+
+def test_point_jacobian_single_lens_closed_form():
+    """q = 1e-12: the primary is a unit point lens at the origin (to 1e-12), A = A(u) with
+    u^2 = tau^2 + u0^2, tau = (t - t0)/tE; dA/du0 = A'(u) u0/u, dA/dt0 = -A'(u) tau/(u tE),
+    dA/dtE = -A'(u) tau^2/(u tE), and A does not depend on alpha, rho or u1."""
+    p = O.params(s=1.3, q=1e-12, u0=0.12, alpha=0.7, t0=1.5, tE=17.0, rho=1e-3, u1=0.4)
+    t = np.linspace(-20, 25, 31)
+    a, jac, st = O.point_jacobian(2, p, t)
+    # the companion's own image lies within ~1e-12 of it and is not resolved (count flag);
+    # its magnification is ~1e-24
+    assert not np.any(st & ~np.uint32(O.ST_IMG_COUNT))
+    tau = (t - p[4]) / p[5]
+    u = np.hypot(tau, p[2])
+    A = R.point_lens_mag(u)
+    dA = _dA_du_single(u)
+    assert np.allclose(a, A, rtol=1e-9)
+    assert np.allclose(jac[:, 2], dA * p[2] / u, rtol=1e-6, atol=1e-12)
+    assert np.allclose(jac[:, 4], -dA * tau / (u * p[5]), rtol=1e-6, atol=1e-12)
+    assert np.allclose(jac[:, 5], -dA * tau * tau / (u * p[5]), rtol=1e-6, atol=1e-12)
+    assert np.all(np.abs(jac[:, [3, 6, 7]]) <= 1e-9 * np.abs(jac[:, [2]]) + 1e-12)
+
+
+@pytest.mark.parametrize("n_lens", [2, 3])
+def test_point_jacobian_central_differences(n_lens):
+    """Away from caustics A_ps is smooth: the root-derivative gradient equals central
+    differences of A_ps itself (steps 1e-6 max(|p|, 1))."""
+    if n_lens == 2:
+        p = O.params(s=0.9, q=0.1, u0=0.05, alpha=0.6, t0=0.0, tE=20.0, rho=1e-2, u1=0.5)
+        t = np.array([-30.0, -18.0, -9.0, 7.5, 11.0, 24.0])
+        keys = [0, 1, 2, 3, 4, 5]
+    else:
+        p = O.params(s=1.1, q=0.5, u0=0.05, alpha=np.deg2rad(60), t0=0.0, tE=10.0, rho=1e-3, u1=0.0, q3=0.03,
+                     r3=1.24, psi=np.deg2rad(76))
+        t = np.array([-15.0, -9.0, 8.0, 14.0])
+        keys = [0, 1, 2, 3, 4, 5, 8, 9, 10]
+    a, jac, st = O.point_jacobian(n_lens, p, t)
+    assert not np.any(st)
+    for k in keys:
+        h = 1e-6 * max(abs(p[k]), 1.0)
+        pp, pm = p.copy(), p.copy()
+        pp[k] += h
+        pm[k] -= h
+        fd = (O.point_jacobian(n_lens, pp, t)[0] - O.point_jacobian(n_lens, pm, t)[0]) / (2 * h)
+        scale = np.max(np.abs(jac[:, k])) + 1e-12
+        assert np.max(np.abs(fd - jac[:, k])) <= 1e-6 * scale + 1e-9, (k, fd, jac[:, k])
+
+
+def test_selection_keeps_point_values_only_where_they_hold():
+    """On the planetary batch (rho 1e-3) and the config-1 curve: every epoch the rule leaves
+    to A_ps has a point-source value within 2 tol of the finite-source magnification of the
+    grid-free disk quadrature; epochs within rho tE of a caustic crossing (an image-count
+    change along the path) are selected."""
+    tol = 1e-4
+    checked = 0
+    big = W.binary_batch(2, 12, rho_fixed=1e-3)
+    for i in range(12):
+        t = big.t[big.offsets[i]:big.offsets[i + 1]]
+        lo, hi = t.min() - 3.0, t.max() + 3.0
+        t = np.concatenate([t[:: max(1, t.size // 24)], np.linspace(lo, hi, 24)])
+        ext, aps = O.hybrid_select(2, big.params[i], t, tol=tol)
+        keep = ~ext
+        if np.any(keep):
+            ref, ch = O.disk_mag(2, big.params[i], t[keep], n_x=24, n_phi=144)
+            assert np.all(ch == 0), "a kept epoch has a caustic inside the disk"
+            assert np.all(np.abs(aps[keep] / ref - 1) <= 2 * tol), np.max(np.abs(aps[keep] / ref - 1))
+            checked += int(keep.sum())
+    assert checked > 100
+    # caustic crossings of the config-1 curve: where the image count changes along the path
+    w = W.config1()
+    p = w.params[0]
+    eps, a = O.frame(2, p)
+    tt = np.linspace(-30, 30, 24001)
+    counts = np.array([O.images(eps, a, O.source_center(p, x))[0].size for x in tt])
+    crossings = 0.5 * (tt[1:] + tt[:-1])[np.diff(counts) != 0]
+    assert crossings.size >= 2
+    ext, _ = O.hybrid_select(2, p, w.t, tol=tol)
+    near = np.min(np.abs(w.t[:, None] - crossings[None, :]), axis=1) < p[6] * p[5]
+    assert near.sum() >= 2 and np.all(ext[near])
+    assert 0 < ext.sum() < w.n_epochs
+
+
+def test_hybrid_curve_is_full_method_on_selected_epochs_and_point_elsewhere():
+    w = W.config1()
+    p, t = w.params[0], w.t[::4]
+    mag, st = O.hybrid(2, p, t, n_limb=64, n_r=64, n_theta=256)
+    ext, aps = O.hybrid_select(2, p, t)
+    full = O.magnification(2, p, t[ext], n_limb=64, n_r=64, n_theta=256)
+    assert np.array_equal(mag[ext], full["mag"]) and np.array_equal(st[ext], full["status"])
+    assert np.array_equal(mag[~ext], aps[~ext]) and np.all(st[~ext] == O.ST_POINT)
