@@ -31,9 +31,11 @@
  *   - Argument errors (bad sizes, NULL pointers, out-of-range parameters, unsorted offsets)
  *     return ICRS_EINVAL before anything is enqueued.  A workspace that is too small gives
  *     ICRS_ENOMEM.  A HIP runtime failure gives ICRS_EHIP.
- *   - Work is enqueued asynchronously on the handle's stream; the call may block only to
- *     read small device counters back (clip retries).  Data-dependent failures never fail a
- *     call: they set status bits, and an epoch without a usable result gets NaN.
+ *   - Work is enqueued asynchronously on the handle's stream.  Work list sizes (clip
+ *     retries, learned and fallback epochs) stay on the device, so no call waits for the
+ *     stream unless profiling is on or host statistics are asked for.  Data-dependent
+ *     failures never fail a call: they set status bits, and an epoch without a usable result
+ *     gets NaN.
  *   - A handle must not be used from two threads at once.
  */
 #ifndef ICRS_H_
@@ -49,6 +51,7 @@ extern "C" {
 #define ICRS_ABI_VERSION 1u
 #define ICRS_N_PARAMS 11
 #define ICRS_MAX_SECTORS 10 /* 5(N-1) for N = 3: the sector cap per epoch (Sec. 3.2) */
+#define ICRS_MAX_EPOCHS (1LL << 27) /* epochs per call; more returns ICRS_EINVAL */
 
 typedef enum {
   ICRS_OK = 0,
@@ -65,6 +68,8 @@ typedef enum {
 #define ICRS_ST_CLIP 8u           /* inside rays still touch a sector edge after the retries */
 #define ICRS_ST_NAN 16u           /* the magnification is not finite */
 #define ICRS_ST_GIVEN 64u         /* sectors were supplied by the caller */
+#define ICRS_ST_IMG_RECHECK 512u  /* a kept image failed the final substitution check and was dropped */
+#define ICRS_ST_BAD_SECTORS 1024u /* a given sector count outside 0..ICRS_MAX_SECTORS; result NaN */
 
 /* Ray-loop precision. */
 #define ICRS_FP64 0
@@ -128,7 +133,9 @@ icrs_status icrs_run(icrs_handle* h, const double* t, double* mag, uint32_t* sta
  * [n_epochs][ICRS_MAX_SECTORS][4] doubles (r_lo, r_hi, theta_lo, theta_hi) with
  * 0 <= r_lo < r_hi and theta_lo < theta_hi; periodic: DEVICE [n_epochs][ICRS_MAX_SECTORS]
  * bytes (1 = full ring, theta range 2 pi wrapped); n_sectors: DEVICE [n_epochs] int32 in
- * 0..ICRS_MAX_SECTORS.  Entries past n_sectors[e] are ignored. */
+ * 0..ICRS_MAX_SECTORS.  Entries past n_sectors[e] are ignored.  A count outside that range
+ * (it lives on the device, so the call cannot reject it) shoots no rays and gives the epoch
+ * NaN with ICRS_ST_BAD_SECTORS. */
 icrs_status icrs_magnification_given(icrs_handle* h, int64_t n_events, const double* params,
                                      const int64_t* epoch_offsets, int64_t n_epochs,
                                      const double* t, const double* sectors,
@@ -147,7 +154,8 @@ icrs_status icrs_magnification_given(icrs_handle* h, int64_t n_events, const dou
  * is NULL).  Outputs (DEVICE, any may be NULL but not all): grad [n_events][ICRS_N_PARAMS]
  * = sum over the event's epochs of cotangent[e] * dA_e/dparams; jac [n_epochs][ICRS_N_PARAMS]
  * = dA_e/dparams; mag [n_epochs] = A_e.  Parameter order as in params; entries that do not
- * apply (q3, r3, psi for binaries) are 0.  n_theta must be <= 1024. */
+ * apply (q3, r3, psi for binaries) are 0.  n_theta must be <= 1024.  An epoch whose
+ * n_sectors entry lies outside 0..ICRS_MAX_SECTORS gets NaN in jac and mag. */
 icrs_status icrs_magnification_vjp(icrs_handle* h, int64_t n_events, const double* params,
                                    const int64_t* epoch_offsets, int64_t n_epochs, const double* t,
                                    const double* sectors, const uint8_t* periodic,
@@ -289,12 +297,26 @@ size_t icrs_learned_workspace_bytes(const icrs_handle* h, int64_t n_events, int6
  * ICRS_EUNSUPPORTED).  Same inputs and outputs as icrs_magnification plus the network
  * (packed, params, norm as for icrs_mlp_forward) and optional host stats.  Epochs that
  * fail a check are computed by the plain path of the handle's config inside the call.
- * Synchronises the stream (list sizes are read back). */
+ * The learned, fallback and retry lists keep their sizes on the device: with stats == NULL
+ * (and profiling off) the call only enqueues work on the handle's stream, so it can be
+ * captured into a HIP graph; with stats (HOST) it waits for the stream at the end to fill
+ * them. */
 icrs_status icrs_magnification_learned(icrs_handle* h, int64_t n_events, const double* params,
                                        const int64_t* epoch_offsets, int64_t n_epochs, const double* t,
                                        const icrs_learned_config* lc, const uint16_t* packed,
                                        const float* mlp_params, const float* norm, double* mag, uint32_t* status,
                                        icrs_learned_stats* stats, void* workspace, size_t workspace_bytes);
+
+/* The learned path on the batch that icrs_prepare() uploaded into workspace (which must be
+ * at least icrs_learned_workspace_bytes() long): no host memory is read and, with
+ * stats == NULL and profiling off, nothing waits for the stream, so the call can be
+ * captured into a HIP graph and replayed (Sec. 3.4's batching of many epochs and events in
+ * one pass, with every list size kept on the device).  Arguments otherwise as for
+ * icrs_magnification_learned; n_epochs is the prepared batch's. */
+icrs_status icrs_run_learned(icrs_handle* h, const double* t, const icrs_learned_config* lc,
+                             const uint16_t* packed, const float* mlp_params, const float* norm,
+                             double* mag, uint32_t* status, icrs_learned_stats* stats, void* workspace,
+                             size_t workspace_bytes);
 
 const char* icrs_status_string(icrs_status s);
 

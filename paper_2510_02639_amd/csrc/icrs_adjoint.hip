@@ -106,7 +106,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void a
 #pragma unroll
     for (int a = 0; a < NA; ++a) tot[a] = 0.0;
 
-    const int ns = sec.nsec[e];
+    // a sector count outside 0..kMaxSectors (only from a caller's given list) is not used:
+    // the epoch's derivatives and magnification become NaN
+    const int ns_in = sec.nsec[e];
+    const bool bad_ns = ns_in < 0 || ns_in > kMaxSectors;
+    const int ns = bad_ns ? 0 : ns_in;
     for (int slot = 0; slot < ns; ++slot) {
       const double* sp = sec.sectors + (e * kMaxSectors + slot) * 4;
       const bool per = sec.periodic[e * kMaxSectors + slot] != 0;
@@ -288,8 +292,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void a
       out[5] = -(gx * ca + gy * sa) * tau / p[5];  // tE
       out[6] = tot[NG + 1] * inv_rho2 - 2.0 * A / rho;
       out[7] = tot[NG + 2] * inv_rho2;
-      for (int k = 0; k < kParams; ++k) jac[e * kParams + k] = out[k];
-      if (mag_out) mag_out[e] = A;
+      const double nan = __builtin_nan("");
+      for (int k = 0; k < kParams; ++k) jac[e * kParams + k] = bad_ns ? nan : out[k];
+      if (mag_out) mag_out[e] = bad_ns ? nan : A;
     }
     __syncthreads();
   }

@@ -111,7 +111,8 @@ bool finite_all(const double* p, int n) {
 // host checks of the event parameters and the CSR offsets
 bool events_ok(const icrs_config& c, int64_t n_events, const double* params, const int64_t* off, int64_t n_epochs) {
   if (n_events < 0 || n_epochs < 0) return false;
-  if (n_epochs > 0x7fffffffLL / ICRS_MAX_SECTORS) return false;
+  // FP64-pass work items pack (epoch, sector) as the int32 16 e + slot
+  if (n_epochs > ICRS_MAX_EPOCHS) return false;
   if (n_events > 0x7fffffffLL) return false;
   if (n_events > 0 && (!params || !off)) return false;
   if (n_events == 0) return n_epochs == 0;
@@ -179,8 +180,8 @@ struct Views {
   int32_t* fallback;
   double* jac;
   double* roots;       // [n_epochs][10] complex: roots of the centre's lens polynomial
-  int32_t* counters;   // [0] retry count, [4] FP64 fallback count, [8..9] int64 sector passes,
-                       // [12..13] int64 work queue
+  int32_t* counters;   // [0], [1] retry list counts, [2] cold-redo list count, [4] FP64 fallback
+                       // count, [8..9] int64 sector passes, [12..13] int64 work queue
 };
 
 icrs_status prepare(icrs_handle* h, int64_t n_events, const double* params, const int64_t* off, int64_t n_epochs,
@@ -215,15 +216,44 @@ icrs_status prepare(icrs_handle* h, int64_t n_events, const double* params, cons
   return ICRS_OK;
 }
 
-// rays + finalize with up to max_retries widening passes
+// Views of the batch that icrs_prepare() uploaded into workspace (no host memory is read).
+Views prepared_views(const icrs_handle* h, const double* t, void* workspace) {
+  const Layout L = layout_for(h->prep_events, h->prep_epochs);
+  char* base = (char*)workspace;
+  Views v;
+  v.b.params = (const double*)(base + L.params);
+  v.b.offsets = (const int64_t*)(base + L.offsets);
+  v.b.epoch_event = (const int32_t*)(base + L.epoch_event);
+  v.b.t = t;
+  v.b.n_events = h->prep_events;
+  v.b.n_epochs = h->prep_epochs;
+  v.sec.sectors = (double*)(base + L.sectors);
+  v.sec.periodic = (uint8_t*)(base + L.periodic);
+  v.sec.nsec = (int32_t*)(base + L.nsec);
+  v.partial = (double*)(base + L.partial);
+  v.clip = (uint8_t*)(base + L.clip);
+  v.list_a = (int32_t*)(base + L.list_a);
+  v.list_b = (int32_t*)(base + L.list_b);
+  v.fallback = (int32_t*)(base + L.fallback);
+  v.jac = (double*)(base + L.jac);
+  v.roots = (double*)(base + L.roots);
+  v.counters = (int32_t*)(base + L.counters);
+  return v;
+}
+
 // Which epochs and grid one ray call covers: all epochs on the handle's grid by default.
 struct RaySet {
-  const int32_t* list = nullptr;  // epochs (device), or all when null
-  int64_t n = -1;                 // list length (host-known)
-  int n_r = 0, n_theta = 0;       // grid; 0 = the handle's
+  const int32_t* list = nullptr;   // epochs (device), or all when null
+  int64_t n = -1;                  // list length, or an upper bound of it when n_dev is set
+  const int32_t* n_dev = nullptr;  // device-side list length (read by the kernels only)
+  int n_r = 0, n_theta = 0;        // grid; 0 = the handle's
   const double* add_mag = nullptr;
 };
 
+// Rays + finalize with up to max_retries widening passes, with no host synchronisation:
+// every retry pass is enqueued and finds its work list size on the device (an empty pass
+// ends at once).  With profiling on, kernel timings and the main pass's sector count are
+// read back after the first pass (the only host waits, and only then).
 icrs_status run_rays(icrs_handle* h, const Views& v, int max_retries, double* mag, uint32_t* status,
                      uint32_t extra_status, const RaySet& rs = RaySet{}) {
   icrs_config c = h->cfg;
@@ -232,32 +262,34 @@ icrs_status run_rays(icrs_handle* h, const Views& v, int max_retries, double* ma
   RayWork w;
   w.list = rs.list;
   w.n = rs.list ? rs.n : v.b.n_epochs;
+  w.n_dev = rs.n_dev;
   if (w.n <= 0) return ICRS_OK;
-  int32_t* cur = v.list_a;
-  int32_t* nxt = v.list_b;
+  const int64_t n_bound = w.n;
+  int32_t* lists[2] = {v.list_a, v.list_b};
+  int32_t* counts[2] = {v.counters + 0, v.counters + 1};
   unsigned long long* passes = (unsigned long long*)(v.counters + 8);
+  const bool learned = (extra_status & ICRS_ST_LEARNED) != 0;
   if (h->profiling) ICRS_TRY(icrs::launch_fill_i32(v.counters + 8, 2, 0, h->stream));
   Timer tm(h);
-  for (int attempt = 0;; ++attempt) {
+  for (int attempt = 0; attempt <= max_retries; ++attempt) {
     // stage 0: the main pass (timed on its own for the first attempt); stage 1: FP64 pass
     // over the sectors the FP32 main pass listed
-    ICRS_TRY(tm.begin());
-    ICRS_TRY(icrs::launch_rays(c.n_lens, c.ray_precision, 0, v.b, v.sec, w, c.n_r, c.n_theta, c.delta_c, v.partial,
-                               v.clip, (unsigned long long*)(v.counters + 12), v.fallback, v.counters + 4,
-                               h->stream));
-    const bool learned = (extra_status & ICRS_ST_LEARNED) != 0;
-    ICRS_TRY(tm.end(&h->prof.ms_rays,
-                    attempt == 0 ? (learned ? &h->prof.ms_rays_learned : &h->prof.ms_rays_main) : nullptr));
-    ICRS_TRY(tm.begin());
-    ICRS_TRY(icrs::launch_rays(c.n_lens, c.ray_precision, 1, v.b, v.sec, w, c.n_r, c.n_theta, c.delta_c, v.partial,
-                               v.clip, (unsigned long long*)(v.counters + 12), v.fallback, v.counters + 4,
-                               h->stream));
-    ICRS_TRY(tm.end(&h->prof.ms_rays));
+    for (int stage = 0; stage < 2; ++stage) {
+      ICRS_TRY(tm.begin());
+      ICRS_TRY(icrs::launch_rays(c.n_lens, c.ray_precision, stage, v.b, v.sec, w, c.n_r, c.n_theta, c.delta_c,
+                                 v.partial, v.clip, (unsigned long long*)(v.counters + 12), v.fallback,
+                                 v.counters + 4, h->stream));
+      double* also = nullptr;
+      if (attempt == 0 && stage == 0) also = learned ? &h->prof.ms_rays_learned : &h->prof.ms_rays_main;
+      ICRS_TRY(tm.end(&h->prof.ms_rays, also));
+    }
     h->prof.n_rays_launches += 1;
-    ICRS_TRY(icrs::launch_fill_i32(v.counters, 1, 0, h->stream));
+    int32_t* nxt = lists[attempt & 1];
+    int32_t* ncount = counts[attempt & 1];
+    ICRS_TRY(icrs::launch_fill_i32(ncount, 1, 0, h->stream));
     ICRS_TRY(tm.begin());
-    ICRS_TRY(icrs::launch_finalize(v.b, v.sec, w, v.partial, v.clip, attempt, max_retries, nxt, v.counters, mag,
-                                   status, extra_status, h->profiling ? passes : nullptr, h->stream, rs.add_mag));
+    ICRS_TRY(icrs::launch_finalize(v.b, v.sec, w, v.partial, v.clip, attempt, max_retries, nxt, ncount, mag, status,
+                                   extra_status, h->profiling ? passes : nullptr, h->stream, rs.add_mag));
     ICRS_TRY(tm.end(&h->prof.ms_finalize));
     ICRS_TRY(tm.flush());
     if (h->profiling && attempt == 0) {
@@ -278,59 +310,127 @@ icrs_status run_rays(icrs_handle* h, const Views& v, int max_retries, double* ma
         h->prof.n_main_rays += main * (int64_t)c.n_r * c.n_theta;
       }
     }
-    if (attempt >= max_retries) break;
-    int32_t count = 0;
-    ICRS_TRY(hipMemcpyAsync(&count, v.counters, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
-    ICRS_TRY(hipStreamSynchronize(h->stream));
-    if (count == 0) break;
     w = RayWork{};
     w.list = nxt;
-    w.n = count;
-    int32_t* tmp = cur;
-    cur = nxt;
-    nxt = tmp;
+    w.n = n_bound;
+    w.n_dev = ncount;
   }
   if (h->profiling) {
     unsigned long long np = 0;
+    int64_t ne = rs.list ? rs.n : v.b.n_epochs;
+    int32_t nd = 0;
     ICRS_TRY(hipMemcpyAsync(&np, passes, sizeof(np), hipMemcpyDeviceToHost, h->stream));
+    if (rs.n_dev) ICRS_TRY(hipMemcpyAsync(&nd, rs.n_dev, sizeof(nd), hipMemcpyDeviceToHost, h->stream));
     ICRS_TRY(hipStreamSynchronize(h->stream));
+    if (rs.n_dev) ne = nd;
     h->prof.n_sector_passes += (int64_t)np;
-    h->prof.n_epochs += rs.list ? rs.n : v.b.n_epochs;
+    h->prof.n_epochs += ne;
     h->prof.n_calls += 1;
   }
   return ICRS_OK;
 }
 
-// The whole plain path with no host synchronisation: every retry pass is launched and
-// finds its work list size on the device (an empty pass ends at once).
-icrs_status run_plain_device(icrs_handle* h, const Views& v, double* mag, uint32_t* status) {
+// The plain path: centre images (the limb solves' warm start), limb sectors, rays.
+icrs_status run_plain(icrs_handle* h, const Views& v, double* mag, uint32_t* status) {
   const icrs_config& c = h->cfg;
   const int fp32_roots = c.root_precision == ICRS_FP32;
+  Timer tm(h);
+  ICRS_TRY(tm.begin());
   ICRS_TRY(icrs::launch_centre_images(c.n_lens, fp32_roots, v.b, nullptr, nullptr, nullptr, status, h->stream,
                                       v.roots));
+  ICRS_TRY(tm.end(&h->prof.ms_centre));
+  ICRS_TRY(tm.begin());
   ICRS_TRY(icrs::launch_limb_sectors(c.n_lens, fp32_roots, c.n_limb, v.b, v.sec, status, h->stream, nullptr, 0,
-                                     v.roots));
-  RayWork w;
-  w.n = v.b.n_epochs;
-  int32_t* lists[2] = {v.list_a, v.list_b};
-  int32_t* counts[2] = {v.counters + 0, v.counters + 1};
-  for (int attempt = 0; attempt <= c.max_retries; ++attempt) {
-    for (int stage = 0; stage < 2; ++stage)
-      ICRS_TRY(icrs::launch_rays(c.n_lens, c.ray_precision, stage, v.b, v.sec, w, c.n_r, c.n_theta, c.delta_c,
-                                 v.partial, v.clip, (unsigned long long*)(v.counters + 12), v.fallback,
-                                 v.counters + 4, h->stream));
-    int32_t* nxt = lists[attempt & 1];
-    int32_t* ncount = counts[attempt & 1];
-    ICRS_TRY(icrs::launch_fill_i32(ncount, 1, 0, h->stream));
-    ICRS_TRY(icrs::launch_finalize(v.b, v.sec, w, v.partial, v.clip, attempt, c.max_retries, nxt, ncount, mag,
-                                   status, 0u, nullptr, h->stream));
-    w = RayWork{};
-    w.list = nxt;
-    w.n = v.b.n_epochs;
-    w.n_dev = ncount;
+                                     nullptr, v.roots, v.list_b, v.counters + 2));
+  ICRS_TRY(tm.end(&h->prof.ms_limb_sectors));
+  ICRS_TRY(tm.flush());
+  return run_rays(h, v, c.max_retries, mag, status, 0u);
+}
+
+bool learned_config_ok(const icrs_learned_config* lc) {
+  return lc && lc->n_check >= 8 && lc->n_check <= 64 && lc->n_r >= 4 && lc->n_r <= 4096 && lc->n_theta >= 64 &&
+         lc->n_theta <= 1024 && lc->prune_ratio >= 0.0 && lc->prune_ratio < 0.1 && lc->vary_max > 0.0 &&
+         lc->gate_rel > 0.0 && fabs(lc->log_safety) < 10.0 && lc->margin_frac >= 0.0 && lc->margin_frac <= 1.0;
+}
+
+// The learned path on an uploaded batch (views v over workspace): no host memory is read
+// and, without stats and profiling, nothing waits for the stream.
+icrs_status run_learned(icrs_handle* h, const Views& v, const icrs_learned_config* lc, const uint16_t* packed,
+                        const float* mlp_params, const float* norm, double* mag, uint32_t* status,
+                        icrs_learned_stats* stats, void* workspace) {
+  if (stats) memset(stats, 0, sizeof(*stats));
+  const int64_t n_epochs = v.b.n_epochs;
+  if (n_epochs == 0) return ICRS_OK;
+  const LearnedLayout LL = learned_layout(h->cfg.n_lens, v.b.n_events, n_epochs);
+  char* base = (char*)workspace;
+  const icrs_config& c = h->cfg;
+  const int fp32_roots = c.root_precision == ICRS_FP32;
+  const int MI = c.n_lens * c.n_lens + 1;
+  double* cimg = (double*)(base + LL.cimg);
+  int32_t* cn = (int32_t*)(base + LL.cn);
+  double* a_c = (double*)(base + LL.a_c);
+  double* a_ring = (double*)(base + LL.a_ring);
+  double* add = (double*)(base + LL.add);
+  uint32_t* flags = (uint32_t*)(base + LL.flags);
+  double* ext = (double*)(base + LL.ext);
+  float* feat = (float*)(base + LL.feat);
+  float* y = (float*)(base + LL.y);
+  int32_t* lists = (int32_t*)(base + LL.lists);
+  int32_t* counts = (int32_t*)(base + LL.counts);
+  Timer tm(h);
+  ICRS_TRY(tm.begin());
+  ICRS_TRY(icrs::launch_centre_images(c.n_lens, fp32_roots, v.b, cimg, cn, a_c, status, h->stream, v.roots));
+  ICRS_TRY(tm.end(&h->prof.ms_centre));
+  ICRS_TRY(tm.begin());
+  ICRS_TRY(icrs::launch_image_extents(c.n_lens, fp32_roots, lc->n_check, v.b, cimg, cn, ext, feat, nullptr, a_ring,
+                                      flags, h->stream, v.roots));
+  ICRS_TRY(icrs::mlp::launch_forward(packed, mlp_params, norm, n_epochs * MI, feat, y, h->stream));
+  ICRS_TRY(icrs::launch_fill_i32(counts, 4, 0, h->stream));
+  ICRS_TRY(icrs::launch_learned_sectors(c.n_lens, v.b, cimg, cn, a_c, a_ring, ext, y, lc->log_safety,
+                                        lc->margin_frac, lc->prune_ratio, lc->vary_max, flags, v.sec, add, lists,
+                                        counts, counts + 2, h->stream));
+  ICRS_TRY(tm.end(&h->prof.ms_limb_sectors));
+  ICRS_TRY(tm.flush());
+  // learned epochs: counts[0] of them at lists[0..]; fallback epochs at lists[E..], counts[1]
+  RaySet rs;
+  rs.list = lists;
+  rs.n = n_epochs;
+  rs.n_dev = counts;
+  rs.n_r = lc->n_r;
+  rs.n_theta = lc->n_theta;
+  rs.add_mag = add;
+  icrs_status st = run_rays(h, v, c.max_retries, mag, status, ICRS_ST_LEARNED, rs);
+  if (st != ICRS_OK) return st;
+  // the gate appends the learned epochs it rejects to the fallback list (and counts them
+  // in counts[3])
+  ICRS_TRY(icrs::launch_learned_gate(v.b, lists, counts, n_epochs, a_c, a_ring, mag, status, lc->gate_rel, flags,
+                                     lists, counts, h->stream));
+  const int32_t* fb = lists + n_epochs;
+  ICRS_TRY(tm.begin());
+  ICRS_TRY(icrs::launch_limb_sectors(c.n_lens, fp32_roots, c.n_limb, v.b, v.sec, status, h->stream, fb, n_epochs,
+                                     counts + 1, v.roots, v.list_b, v.counters + 2));
+  ICRS_TRY(tm.end(&h->prof.ms_limb_sectors));
+  ICRS_TRY(tm.flush());
+  RaySet fs;
+  fs.list = fb;
+  fs.n = n_epochs;
+  fs.n_dev = counts + 1;
+  st = run_rays(h, v, c.max_retries, mag, status, ICRS_ST_FALLBACK, fs);
+  if (st != ICRS_OK) return st;
+  if (stats) {
+    // the only host wait of this entry point, and only when statistics are asked for
+    int32_t cnt[4] = {0, 0, 0, 0};
+    ICRS_TRY(hipMemcpyAsync(cnt, counts, sizeof(cnt), hipMemcpyDeviceToHost, h->stream));
+    ICRS_TRY(hipStreamSynchronize(h->stream));
+    stats->n_epochs = n_epochs;
+    stats->n_fallback = cnt[1];
+    stats->n_gate_rejected = cnt[3];
+    stats->n_learned = cnt[0] - stats->n_gate_rejected;
+    stats->n_pruned_images = cnt[2];
   }
   return ICRS_OK;
 }
+
 
 }  // namespace
 
@@ -401,19 +501,7 @@ icrs_status icrs_magnification(icrs_handle* h, int64_t n_events, const double* p
   Views v;
   const icrs_status ps = prepare(h, n_events, params, epoch_offsets, n_epochs, t, workspace, workspace_bytes, &v);
   if (ps != ICRS_OK || n_epochs == 0) return ps;
-  const icrs_config& c = h->cfg;
-  const int fp32_roots = c.root_precision == ICRS_FP32;
-  Timer tm(h);
-  ICRS_TRY(tm.begin());
-  ICRS_TRY(icrs::launch_centre_images(c.n_lens, fp32_roots, v.b, nullptr, nullptr, nullptr, status, h->stream,
-                                      v.roots));
-  ICRS_TRY(tm.end(&h->prof.ms_centre));
-  ICRS_TRY(tm.begin());
-  ICRS_TRY(icrs::launch_limb_sectors(c.n_lens, fp32_roots, c.n_limb, v.b, v.sec, status, h->stream, nullptr, 0,
-                                     v.roots));
-  ICRS_TRY(tm.end(&h->prof.ms_limb_sectors));
-  ICRS_TRY(tm.flush());
-  return run_rays(h, v, c.max_retries, mag, status, 0u);
+  return run_plain(h, v, mag, status);
 }
 
 icrs_status icrs_prepare(icrs_handle* h, int64_t n_events, const double* params, const int64_t* epoch_offsets,
@@ -435,26 +523,13 @@ icrs_status icrs_run(icrs_handle* h, const double* t, double* mag, uint32_t* sta
   const Layout L = layout_for(h->prep_events, h->prep_epochs);
   if (workspace_bytes < L.total) return ICRS_ENOMEM;
   if (h->prep_epochs == 0) return ICRS_OK;
-  char* base = (char*)workspace;
-  Views v;
-  v.b.params = (const double*)(base + L.params);
-  v.b.offsets = (const int64_t*)(base + L.offsets);
-  v.b.epoch_event = (const int32_t*)(base + L.epoch_event);
-  v.b.t = t;
-  v.b.n_events = h->prep_events;
-  v.b.n_epochs = h->prep_epochs;
-  v.sec.sectors = (double*)(base + L.sectors);
-  v.sec.periodic = (uint8_t*)(base + L.periodic);
-  v.sec.nsec = (int32_t*)(base + L.nsec);
-  v.partial = (double*)(base + L.partial);
-  v.clip = (uint8_t*)(base + L.clip);
-  v.list_a = (int32_t*)(base + L.list_a);
-  v.list_b = (int32_t*)(base + L.list_b);
-  v.fallback = (int32_t*)(base + L.fallback);
-  v.jac = (double*)(base + L.jac);
-  v.roots = (double*)(base + L.roots);
-  v.counters = (int32_t*)(base + L.counters);
-  return run_plain_device(h, v, mag, status);
+  const Views v = prepared_views(h, t, workspace);
+  // no host waits: the profiling timers (which wait for the stream) are off here
+  const int prof = h->profiling;
+  h->profiling = 0;
+  const icrs_status st = run_plain(h, v, mag, status);
+  h->profiling = prof;
+  return st;
 }
 
 icrs_status icrs_magnification_given(icrs_handle* h, int64_t n_events, const double* params,
@@ -608,13 +683,9 @@ icrs_status icrs_magnification_learned(icrs_handle* h, int64_t n_events, const d
                                        const icrs_learned_config* lc, const uint16_t* packed,
                                        const float* mlp_params, const float* norm, double* mag, uint32_t* status,
                                        icrs_learned_stats* stats, void* workspace, size_t workspace_bytes) {
-  if (!h || !lc || !events_ok(h->cfg, n_events, params, epoch_offsets, n_epochs)) return ICRS_EINVAL;
-  if (h->cfg.n_lens != 2) return ICRS_EUNSUPPORTED;
-  if (lc->n_check < 8 || lc->n_check > 64 || lc->n_r < 4 || lc->n_r > 4096 || lc->n_theta < 64 ||
-      lc->n_theta > 1024 || !(lc->prune_ratio >= 0.0 && lc->prune_ratio < 0.1) || !(lc->vary_max > 0.0) ||
-      !(lc->gate_rel > 0.0) || !(fabs(lc->log_safety) < 10.0) ||
-      !(lc->margin_frac >= 0.0 && lc->margin_frac <= 1.0))
+  if (!h || !learned_config_ok(lc) || !events_ok(h->cfg, n_events, params, epoch_offsets, n_epochs))
     return ICRS_EINVAL;
+  if (h->cfg.n_lens != 2) return ICRS_EUNSUPPORTED;
   if (n_epochs > 0 && (!t || !mag || !status || !packed || !mlp_params || !norm)) return ICRS_EINVAL;
   if (packed && ((uintptr_t)packed & 15u)) return ICRS_EINVAL;
   const LearnedLayout LL = learned_layout(h->cfg.n_lens, n_events, n_epochs);
@@ -622,76 +693,26 @@ icrs_status icrs_magnification_learned(icrs_handle* h, int64_t n_events, const d
   Views v;
   const icrs_status ps = prepare(h, n_events, params, epoch_offsets, n_epochs, t, workspace, workspace_bytes, &v);
   if (ps != ICRS_OK) return ps;
+  return run_learned(h, v, lc, packed, mlp_params, norm, mag, status, stats, workspace);
+}
+
+icrs_status icrs_run_learned(icrs_handle* h, const double* t, const icrs_learned_config* lc, const uint16_t* packed,
+                             const float* mlp_params, const float* norm, double* mag, uint32_t* status,
+                             icrs_learned_stats* stats, void* workspace, size_t workspace_bytes) {
+  if (!h || !workspace || workspace != h->prep_ws || !learned_config_ok(lc)) return ICRS_EINVAL;
+  if (h->cfg.n_lens != 2) return ICRS_EUNSUPPORTED;
+  if (h->prep_epochs > 0 && (!t || !mag || !status || !packed || !mlp_params || !norm)) return ICRS_EINVAL;
+  if (packed && ((uintptr_t)packed & 15u)) return ICRS_EINVAL;
+  if (workspace_bytes < learned_layout(h->cfg.n_lens, h->prep_events, h->prep_epochs).total) return ICRS_ENOMEM;
   if (stats) memset(stats, 0, sizeof(*stats));
-  if (n_epochs == 0) return ICRS_OK;
-  char* base = (char*)workspace;
-  const icrs_config& c = h->cfg;
-  const int fp32_roots = c.root_precision == ICRS_FP32;
-  const int MI = c.n_lens * c.n_lens + 1;
-  double* cimg = (double*)(base + LL.cimg);
-  int32_t* cn = (int32_t*)(base + LL.cn);
-  double* a_c = (double*)(base + LL.a_c);
-  double* a_ring = (double*)(base + LL.a_ring);
-  double* add = (double*)(base + LL.add);
-  uint32_t* flags = (uint32_t*)(base + LL.flags);
-  double* ext = (double*)(base + LL.ext);
-  float* feat = (float*)(base + LL.feat);
-  float* y = (float*)(base + LL.y);
-  int32_t* lists = (int32_t*)(base + LL.lists);
-  int32_t* counts = (int32_t*)(base + LL.counts);
-  Timer tm(h);
-  ICRS_TRY(tm.begin());
-  ICRS_TRY(icrs::launch_centre_images(c.n_lens, fp32_roots, v.b, cimg, cn, a_c, status, h->stream, v.roots));
-  ICRS_TRY(tm.end(&h->prof.ms_centre));
-  ICRS_TRY(tm.begin());
-  ICRS_TRY(icrs::launch_image_extents(c.n_lens, fp32_roots, lc->n_check, v.b, cimg, cn, ext, feat, nullptr, a_ring,
-                                      flags, h->stream, v.roots));
-  ICRS_TRY(icrs::mlp::launch_forward(packed, mlp_params, norm, n_epochs * MI, feat, y, h->stream));
-  ICRS_TRY(icrs::launch_fill_i32(counts, 4, 0, h->stream));
-  ICRS_TRY(icrs::launch_learned_sectors(c.n_lens, v.b, cimg, cn, a_c, a_ring, ext, y, lc->log_safety,
-                                        lc->margin_frac, lc->prune_ratio, lc->vary_max, flags, v.sec, add, lists,
-                                        counts, counts + 2, h->stream));
-  ICRS_TRY(tm.end(&h->prof.ms_limb_sectors));
-  ICRS_TRY(tm.flush());
-  int32_t cnt[4] = {0, 0, 0, 0};
-  ICRS_TRY(hipMemcpyAsync(cnt, counts, sizeof(cnt), hipMemcpyDeviceToHost, h->stream));
-  ICRS_TRY(hipStreamSynchronize(h->stream));
-  const int64_t n_learned = cnt[0];
-  RaySet rs;
-  rs.list = lists;
-  rs.n = n_learned;
-  rs.n_r = lc->n_r;
-  rs.n_theta = lc->n_theta;
-  rs.add_mag = add;
-  icrs_status st = run_rays(h, v, c.max_retries, mag, status, ICRS_ST_LEARNED, rs);
-  if (st != ICRS_OK) return st;
-  ICRS_TRY(icrs::launch_learned_gate(v.b, lists, counts, n_learned, a_c, a_ring, mag, status, lc->gate_rel, flags,
-                                     lists, counts, h->stream));
-  int32_t cnt2[4] = {0, 0, 0, 0};
-  ICRS_TRY(hipMemcpyAsync(cnt2, counts, sizeof(cnt2), hipMemcpyDeviceToHost, h->stream));
-  ICRS_TRY(hipStreamSynchronize(h->stream));
-  const int64_t n_fb = cnt2[1];
-  if (n_fb > 0) {
-    const int32_t* fb = lists + n_epochs;
-    ICRS_TRY(tm.begin());
-    ICRS_TRY(icrs::launch_limb_sectors(c.n_lens, fp32_roots, c.n_limb, v.b, v.sec, status, h->stream, fb, n_fb,
-                                       v.roots));
-    ICRS_TRY(tm.end(&h->prof.ms_limb_sectors));
-    ICRS_TRY(tm.flush());
-    RaySet fs;
-    fs.list = fb;
-    fs.n = n_fb;
-    st = run_rays(h, v, c.max_retries, mag, status, ICRS_ST_FALLBACK, fs);
-    if (st != ICRS_OK) return st;
-  }
-  if (stats) {
-    stats->n_epochs = n_epochs;
-    stats->n_fallback = n_fb;
-    stats->n_gate_rejected = n_fb - cnt[1];
-    stats->n_learned = n_learned - stats->n_gate_rejected;
-    stats->n_pruned_images = cnt[2];
-  }
-  return ICRS_OK;
+  if (h->prep_epochs == 0) return ICRS_OK;
+  const Views v = prepared_views(h, t, workspace);
+  // no host waits: the profiling timers (which wait for the stream) are off here
+  const int prof = h->profiling;
+  h->profiling = 0;
+  const icrs_status st = run_learned(h, v, lc, packed, mlp_params, norm, mag, status, stats, workspace);
+  h->profiling = prof;
+  return st;
 }
 
 const char* icrs_status_string(icrs_status s) {

@@ -29,6 +29,9 @@ constexpr uint32_t kStNan = 16u;
 constexpr uint32_t kStGiven = 64u;
 constexpr uint32_t kStLearned = 128u;
 constexpr uint32_t kStFallback = 256u;
+constexpr uint32_t kStImgRecheck = 512u;
+constexpr uint32_t kStBadSectors = 1024u;
+constexpr uint32_t kStRedo = 1u << 30;  // internal: the epoch's limb solves are redone cold in FP64
 
 // parameter vector layout: [s, q, u0, alpha, t0, tE, rho, u_ld, q3, r3, psi]
 constexpr int kParams = 11;
@@ -377,29 +380,96 @@ __device__ __forceinline__ bool count_ok(int c) {
   return c >= lo && c <= hi && ((c - lo) & 1) == 0;
 }
 
+// The image list lives in registers: every access below uses a compile-time index (the
+// loops are unrolled and the slot is chosen by predication), so no write depends on a
+// lane-varying register index.
 template <int N, int M>
 __device__ inline void accept_image(const Lens<N>& L, c64 w, c64 z0, c64 (&img)[M], int& n) {
   const c64 z = polish(L, w, z0);
   const c64 F = lens_map(L, z) - w;
   if (!(norm2(F) <= 1e-20)) return;
   const double lim = 1e-9 * fmax(1.0, sqrt(norm2(z)));
-  for (int j = 0; j < n; ++j)
-    if (norm2(z - img[j]) <= lim * lim) return;
-  if (n < M) img[n++] = z;
+  bool dup = false;
+#pragma unroll
+  for (int j = 0; j < M; ++j) dup = dup || (j < n && norm2(z - img[j]) <= lim * lim);
+  if (dup || n >= M) return;
+#pragma unroll
+  for (int j = 0; j < M; ++j)
+    if (j == n) img[j] = z;
+  ++n;
+}
+
+// Final substitution check of the kept list: every image is put through eq. lens_eq once
+// more and dropped (with kStImgRecheck) unless it still satisfies |F| <= 1e-10.  The
+// acceptance test above already guarantees this; the check makes a list that breaks it
+// visible in the status word instead of passing it on.
+template <int N, int M>
+__device__ inline uint32_t recheck_images(const Lens<N>& L, c64 w, c64 (&img)[M], int& n) {
+  c64 out[M];
+  int m = 0;
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    out[j] = mk(0.0, 0.0);
+    if (j < n && norm2(lens_map(L, img[j]) - w) <= 1e-20) {
+#pragma unroll
+      for (int k = 0; k < M; ++k)
+        if (k == m) out[k] = img[j];
+      ++m;
+    }
+  }
+  const uint32_t st = (m == n) ? 0u : kStImgRecheck;
+#pragma unroll
+  for (int j = 0; j < M; ++j) img[j] = out[j];
+  n = m;
+  return st;
+}
+
+// Validation of the D roots zr (Sec. 2.1): polish and keep each as described above; if the
+// count is not one of N+1, N+3, .., 5(N-1), try the leading-order images next to each lens,
+// z = a_k - eps_k / conj(w' - a_k) with w' shifted by the other lenses' deflection at a_k.
+// Returns the status bits of the list (kStImgCount if the count stays invalid).
+template <int N>
+__device__ inline uint32_t validate_roots(const Lens<N>& L, c64 w, const c64 (&zr)[N * N + 1],
+                                          c64 (&img)[N * N + 1], int& n_img) {
+  constexpr int D = N * N + 1;
+  uint32_t st = 0;
+  n_img = 0;
+#pragma unroll
+  for (int k = 0; k < D; ++k) accept_image<N, D>(L, w, zr[k], img, n_img);
+  if (!count_ok<N>(n_img)) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      c64 wk = w;
+#pragma unroll
+      for (int j = 0; j < N; ++j)
+        if (j != k) wk = wk + L.eps[j] * recip(conj(L.a[k] - L.a[j]));
+      const c64 seed = L.a[k] - L.eps[k] * recip(conj(wk - L.a[k]));
+      accept_image<N, D>(L, w, seed, img, n_img);
+    }
+    if (!count_ok<N>(n_img)) st |= kStImgCount;
+  }
+  const uint32_t rc = recheck_images<N, D>(L, w, img, n_img);
+  if (rc && !count_ok<N>(n_img)) st |= kStImgCount;
+  return st | rc;
 }
 
 // All validated images of the point source at w.  Cold start: EA in precision T (FP32 roots
 // are then refined by FP64 EA).  With warm (the D roots of a nearby point's polynomial, e.g.
 // the source centre's for a limb point) FP64 EA starts there and needs a few iterations; a
-// warm start that does not converge falls back to the cold path.  roots_out, if given,
+// warm start that does not converge, or two of whose roots coincide, falls back to the cold
+// path.  With kCold64Retry, a cold FP32 solve whose roots validate to a forbidden image count
+// is redone by FP64 EA from the Cauchy circle: inside a cluster of roots next to a low-mass
+// lens, FP32 iterates can merge before the FP64 stage separates them.  (The limb kernels
+// handle a warm start that validates to a forbidden count by re-running the epoch cold in
+// FP64; a retry here would cost the limb kernel its register budget.)  roots_out, if given,
 // receives the D polynomial roots.  Returns status bits.
 constexpr int kEAWarmIter = 50;
+constexpr int kEAMaxIterCold64 = 500;
 
-template <int N, typename T>
+template <int N, typename T, bool kCold64Retry = false>
 __device__ inline uint32_t find_images(const Lens<N>& L, c64 w, c64 (&img)[N * N + 1], int& n_img, int max_iter,
                                        const c64* warm = nullptr, c64* roots_out = nullptr) {
   constexpr int D = N * N + 1;
-  uint32_t st = 0;
   c64 P[D + 1];
   lens_polynomial<N>(L, w, P);
   c64 zr[D];
@@ -434,27 +504,17 @@ __device__ inline uint32_t find_images(const Lens<N>& L, c64 w, c64 (&img)[N * N
       conv = conv64;
     }
   }
+  uint32_t st = validate_roots<N>(L, w, zr, img, n_img) | (conv ? 0u : kStRootNonconv);
+  if constexpr (kCold64Retry && sizeof(T) == 4) {
+    if (!warm && (st & (kStImgCount | kStRootNonconv))) {
+      bool conv64 = true;
+      ehrlich_aberth<double, D>(P, zr, kEAMaxIterCold64, &conv64);
+      st = validate_roots<N>(L, w, zr, img, n_img) | (conv64 ? 0u : kStRootNonconv);
+    }
+  }
   if (roots_out) {
 #pragma unroll
     for (int k = 0; k < D; ++k) roots_out[k] = zr[k];
-  }
-  if (!conv) st |= kStRootNonconv;
-  n_img = 0;
-#pragma unroll
-  for (int k = 0; k < D; ++k) accept_image<N, D>(L, w, zr[k], img, n_img);
-  if (!count_ok<N>(n_img)) {
-    // leading-order image next to lens k: z = a_k - eps_k / conj(w' - a_k), with w'
-    // shifted by the other lenses' deflection at a_k
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-      c64 wk = w;
-#pragma unroll
-      for (int j = 0; j < N; ++j)
-        if (j != k) wk = wk + L.eps[j] * recip(conj(L.a[k] - L.a[j]));
-      const c64 seed = L.a[k] - L.eps[k] * recip(conj(wk - L.a[k]));
-      accept_image<N, D>(L, w, seed, img, n_img);
-    }
-    if (!count_ok<N>(n_img)) st |= kStImgCount;
   }
   return st;
 }

@@ -30,11 +30,16 @@ hipError_t launch_centre_images(int n_lens, int root_fp32, const Batch& b, doubl
                                 double* a_ps, uint32_t* status, hipStream_t s, double* roots = nullptr);
 
 // limb images + sectors (one workgroup per epoch); ORs status bits.  With list, only the
-// n_list epochs it names.  With roots (the centre polynomial's, from launch_centre_images), the
-// limb points' root solves start there.
+// n_list epochs it names (with n_list_dev, the list's length is read on the device and
+// n_list is only its upper bound).  With roots (the centre polynomial's, from
+// launch_centre_images), the limb points' root solves start there, and an epoch where such
+// a solve ends with a forbidden image count or an unconverged root is queued in redo_list
+// (count in *redo_count, zeroed here; n_epochs entries) and redone from the Cauchy circle
+// in FP64 by a second launch.
 hipError_t launch_limb_sectors(int n_lens, int root_fp32, int n_limb, const Batch& b, const SectorBuf& out,
                                uint32_t* status, hipStream_t s, const int32_t* list = nullptr, int64_t n_list = 0,
-                               const double* roots = nullptr);
+                               const int32_t* n_list_dev = nullptr, const double* roots = nullptr,
+                               int32_t* redo_list = nullptr, int32_t* redo_count = nullptr);
 
 struct RayWork {
   const int32_t* list = nullptr;    // epochs to process (all their sectors), or nullptr = 0..n-1

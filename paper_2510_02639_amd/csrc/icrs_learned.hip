@@ -285,6 +285,7 @@ __global__ void learned_gate_kernel(Batch b, const int32_t* __restrict__ learned
     flags[e] |= f;
     status[e] &= ~(kStClip | kStNan | kStLearned);
     lists[b.n_epochs + atomicAdd(&counts[1], 1)] = (int32_t)e;
+    atomicAdd(&counts[3], 1);
   }
 }
 

@@ -50,7 +50,7 @@ __global__ __launch_bounds__(256) void centre_images_kernel(Batch b, double* __r
   c64 img[MI], zr[MI];
   int n = 0;
   const uint32_t st =
-      find_images<N, T>(L, wc, img, n, sizeof(T) == 8 ? kEAMaxIterFP64 : kEAMaxIterFP32, nullptr, zr);
+      find_images<N, T, true>(L, wc, img, n, sizeof(T) == 8 ? kEAMaxIterFP64 : kEAMaxIterFP32, nullptr, zr);
   if (roots)
     for (int j = 0; j < MI; ++j) {
       roots[(e * kMaxRoots + j) * 2 + 0] = zr[j].x;
@@ -73,7 +73,8 @@ __global__ __launch_bounds__(256) void centre_images_kernel(Batch b, double* __r
 template <int N, typename T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(N == 2 ? 4 : 1))) void limb_sectors_kernel(
     Batch b, int n_limb, SectorBuf out, uint32_t* __restrict__ status, const int32_t* __restrict__ list,
-    const double* __restrict__ roots) {
+    int64_t n_list, const int32_t* __restrict__ n_list_dev, const double* __restrict__ roots,
+    int32_t* __restrict__ redo_list, int32_t* __restrict__ redo_count) {
   constexpr int MI = N * N + 1;  // images per source point at most
   constexpr int cap = 5 * (N - 1);
   extern __shared__ double pts[];  // [blockDim.x * MI] r, then [blockDim.x * MI] theta
@@ -88,8 +89,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(N == 2 ? 4 
   __shared__ int ccount[kMaxCand];
   __shared__ uint32_t st_sh;
 
-  const int64_t e = list ? (int64_t)list[blockIdx.x] : (int64_t)blockIdx.x;
   const int tid = threadIdx.x;
+  // one workgroup per list entry; with a device-side list length the grid covers its upper
+  // bound and the workgroups past the end leave at once
+  const int64_t li = blockIdx.x;
+  if (li >= (n_list_dev ? (int64_t)(*n_list_dev) : n_list)) return;
+  const int64_t e = list ? (int64_t)list[li] : li;
   const double* p = b.params + (int64_t)b.epoch_event[e] * kParams;
   const double rho = p[6];
   if (tid == 0) {
@@ -112,8 +117,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(N == 2 ? 4 
     c64 img[MI], warm[MI];
     if (roots)
       for (int j = 0; j < MI; ++j) warm[j] = mk(roots[(e * kMaxRoots + j) * 2], roots[(e * kMaxRoots + j) * 2 + 1]);
-    const uint32_t st = find_images<N, T>(L, w, img, n, sizeof(T) == 8 ? kEAMaxIterFP64 : kEAMaxIterFP32,
-                                          roots ? warm : nullptr);
+    uint32_t st = find_images<N, T>(L, w, img, n, sizeof(T) == 8 ? kEAMaxIterFP64 : kEAMaxIterFP32,
+                                    roots ? warm : nullptr);
+    // a warm-started solve that ends with a forbidden image count or an unconverged root
+    // (two iterates settled on one root of a cluster): the epoch is queued for a cold FP64
+    // pass, which decides its sectors and its status bits
+    if (redo_list && (st & (kStImgCount | kStRootNonconv))) {
+      st &= ~(kStImgCount | kStRootNonconv);
+      st |= kStRedo;
+    }
     if (st) atomicOr(&st_sh, st);
     for (int j = 0; j < n; ++j) {
       const double r = hypot(img[j].x, img[j].y);
@@ -197,6 +209,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(N == 2 ? 4 
   // 5. margins, merge to a fixpoint, cap at 5(N-1), sort (lane 0; a handful of boxes)
   if (tid == 0) {
     uint32_t st = st_sh;
+    if (st & kStRedo) {
+      st &= ~kStRedo;
+      redo_list[atomicAdd(redo_count, 1)] = (int32_t)e;
+    }
     int ns = 0;
     for (int rr = 0; rr < n_rr; ++rr)
       for (int tr = 0; tr < n_tr; ++tr) {
@@ -276,25 +292,55 @@ hipError_t launch_centre_images(int n_lens, int root_fp32, const Batch& b, doubl
   return hipGetLastError();
 }
 
+namespace {
+template <int N, typename T>
+void limb_launch(dim3 g, dim3 blk, size_t lds, hipStream_t s, const Batch& b, int n_limb, const SectorBuf& out,
+                 uint32_t* status, const int32_t* list, int64_t n, const int32_t* n_list_dev, const double* roots,
+                 int32_t* redo_list, int32_t* redo_count) {
+  hipLaunchKernelGGL((limb_sectors_kernel<N, T>), g, blk, lds, s, b, n_limb, out, status, list, n, n_list_dev, roots,
+                     redo_list, redo_count);
+}
+}  // namespace
+
 hipError_t launch_limb_sectors(int n_lens, int root_fp32, int n_limb, const Batch& b, const SectorBuf& out,
                                uint32_t* status, hipStream_t s, const int32_t* list, int64_t n_list,
-                               const double* roots) {
+                               const int32_t* n_list_dev, const double* roots, int32_t* redo_list,
+                               int32_t* redo_count) {
   const int64_t n = list ? n_list : b.n_epochs;
   if (n <= 0) return hipSuccess;
+  if (roots && (!redo_list || !redo_count)) return hipErrorInvalidValue;
   const int bs = ((n_limb + 63) / 64) * 64;
+  // one workgroup per epoch (n is the list's upper bound when its length is on the device)
+  if (n > 0x7fffffffLL) return hipErrorInvalidValue;
   const dim3 g((unsigned)n), blk(bs);
   const size_t lds = std::max((size_t)bs * (n_lens * n_lens + 1) * 2 * sizeof(double), kMaxCand * sizeof(Sector));
+  if (roots) {
+    hipError_t e = launch_fill_i32(redo_count, 1, 0, s);
+    if (e != hipSuccess) return e;
+  }
+  // warm-started pass (or the cold pass when no roots are given)
   if (n_lens == 2) {
     if (root_fp32)
-      hipLaunchKernelGGL((limb_sectors_kernel<2, float>), g, blk, lds, s, b, n_limb, out, status, list, roots);
+      limb_launch<2, float>(g, blk, lds, s, b, n_limb, out, status, list, n, n_list_dev, roots, redo_list, redo_count);
     else
-      hipLaunchKernelGGL((limb_sectors_kernel<2, double>), g, blk, lds, s, b, n_limb, out, status, list, roots);
+      limb_launch<2, double>(g, blk, lds, s, b, n_limb, out, status, list, n, n_list_dev, roots, redo_list, redo_count);
   } else {
     if (root_fp32)
-      hipLaunchKernelGGL((limb_sectors_kernel<3, float>), g, blk, lds, s, b, n_limb, out, status, list, roots);
+      limb_launch<3, float>(g, blk, lds, s, b, n_limb, out, status, list, n, n_list_dev, roots, redo_list, redo_count);
     else
-      hipLaunchKernelGGL((limb_sectors_kernel<3, double>), g, blk, lds, s, b, n_limb, out, status, list, roots);
+      limb_launch<3, double>(g, blk, lds, s, b, n_limb, out, status, list, n, n_list_dev, roots, redo_list, redo_count);
   }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !roots) return e;
+  // the epochs it queued, again from the Cauchy circle in FP64 (a handful per million); the
+  // grid covers every epoch and the workgroups past the queue's end leave at once
+  const dim3 g2((unsigned)n);
+  if (n_lens == 2)
+    limb_launch<2, double>(g2, blk, lds, s, b, n_limb, out, status, redo_list, n, redo_count, nullptr, nullptr,
+                           nullptr);
+  else
+    limb_launch<3, double>(g2, blk, lds, s, b, n_limb, out, status, redo_list, n, redo_count, nullptr, nullptr,
+                           nullptr);
   return hipGetLastError();
 }
 

@@ -568,6 +568,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MAP::kMinWa
       e = w.list ? (int64_t)w.list[idx] : (int64_t)idx;
       s0 = 0;
       s1 = sec.nsec[e];
+      if (s1 < 0 || s1 > kMaxSectors) s1 = 0;  // out of range: no rays (finalize flags the epoch)
     }
     const double* p = b.params + (int64_t)b.epoch_event[e] * kParams;
     const Lens<N> L = make_lens<N>(p);
@@ -616,7 +617,10 @@ __global__ void finalize_kernel(Batch b, SectorBuf sec, RayWork w, const double*
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (w.n_dev ? (int64_t)(*w.n_dev) : w.n)) return;
   const int64_t e = w.list ? (int64_t)w.list[idx] : idx;
-  const int ns = sec.nsec[e];
+  // a sector count outside 0..kMaxSectors (only from a caller's given list) is not used
+  const int ns_in = sec.nsec[e];
+  const bool bad_ns = ns_in < 0 || ns_in > kMaxSectors;
+  const int ns = bad_ns ? 0 : ns_in;
   if (passes && ns) atomicAdd(passes, (unsigned long long)ns);
   double flux = 0.0;
   int clips[kMaxSectors];
@@ -653,7 +657,8 @@ __global__ void finalize_kernel(Batch b, SectorBuf sec, RayWork w, const double*
   const double rho = b.params[(int64_t)b.epoch_event[e] * kParams + 6];
   uint32_t st = status[e] | extra_status;
   if (any) st |= kStClip;
-  const double m = flux / (rho * rho) + (add_mag ? add_mag[e] : 0.0);
+  const double m = bad_ns ? __builtin_nan("") : flux / (rho * rho) + (add_mag ? add_mag[e] : 0.0);
+  if (bad_ns) st |= kStBadSectors;
   if (!isfinite(m)) st |= kStNan;
   mag[e] = m;
   status[e] = st;

@@ -120,6 +120,9 @@ def lib():
     L.icrs_magnification_learned.argtypes = [vp, i64, vp, vp, i64, vp, ctypes.POINTER(icrs_learned_config), vp, vp,
                                              vp, vp, vp, ctypes.POINTER(icrs_learned_stats), vp, sz]
     L.icrs_magnification_learned.restype = ctypes.c_int
+    L.icrs_run_learned.argtypes = [vp, vp, ctypes.POINTER(icrs_learned_config), vp, vp, vp, vp, vp,
+                                   ctypes.POINTER(icrs_learned_stats), vp, sz]
+    L.icrs_run_learned.restype = ctypes.c_int
     L.icrs_status_string.argtypes = [ctypes.c_int]
     L.icrs_status_string.restype = ctypes.c_char_p
     _lib = L
@@ -127,12 +130,15 @@ def lib():
 
 
 EXPORTED = ["icrs_default_config", "icrs_create", "icrs_destroy", "icrs_workspace_bytes", "icrs_magnification",
+
             "icrs_magnification_given", "icrs_magnification_vjp", "icrs_get_sectors", "icrs_point_images",
             "icrs_prepare", "icrs_run", "icrs_set_profiling",
             "icrs_get_profile", "icrs_mlp_pack", "icrs_mlp_forward", "icrs_mlp_workspace_bytes",
             "icrs_mlp_loss_grad", "icrs_mlp_adamw", "icrs_image_bounds", "icrs_default_learned_config",
-            "icrs_learned_workspace_bytes", "icrs_magnification_learned", "icrs_status_string"]
-ST_LEARNED, ST_FALLBACK = 128, 256
+            "icrs_learned_workspace_bytes", "icrs_magnification_learned", "icrs_run_learned",
+            "icrs_status_string"]
+ST_LEARNED, ST_FALLBACK, ST_IMG_RECHECK, ST_BAD_SECTORS = 128, 256, 512, 1024
+ICRS_MAX_EPOCHS = 1 << 27
 MLP_PARAM_FLOATS, MLP_PACKED_HALFS, MLP_NORM_FLOATS = 39312, 75776, 32
 
 
@@ -299,11 +305,27 @@ class Handle:
 
     def magnification_learned(self, params, offsets, t, model, mag=None, status=None, workspace=None,
                               n_check=16, n_r=None, n_theta=None, prune_ratio=1e-6, vary_max=0.1, gate_rel=1e-3,
-                              margin_frac=0.02):
-        """Learned-bounds path; model: a learned.BoundsModel.  Returns (mag, status, stats dict)."""
+                              margin_frac=0.02, stats=True):
+        """Learned-bounds path; model: a learned.BoundsModel.  Returns (mag, status, stats dict);
+        with stats=False the call enqueues device work only (no host wait, capturable) and the
+        dict is None."""
         p, o = _host_events(params, offsets)
         t = _dev(t, torch.float64)
         n = t.numel()
+        lc = self._learned_config(model, n_check, n_r, n_theta, prune_ratio, vary_max, gate_rel, margin_frac)
+        mag = mag if mag is not None else torch.empty(n, dtype=torch.float64, device=t.device)
+        status = status if status is not None else torch.empty(n, dtype=torch.int32, device=t.device)
+        ws = workspace if workspace is not None else self.learned_workspace(p.shape[0], n)
+        st = icrs_learned_stats() if stats else None
+        _check(lib().icrs_magnification_learned(self._h, p.shape[0], _ptr(p), _ptr(o), n, _ptr(t), ctypes.byref(lc),
+                                                _ptr(model.packed), _ptr(model.params), _ptr(model.norm),
+                                                _ptr(mag), _ptr(status), ctypes.byref(st) if stats else None,
+                                                _ptr(ws), ws.numel()),
+               "icrs_magnification_learned")
+        return mag, status, (st.as_dict() if stats else None)
+
+    def _learned_config(self, model, n_check=16, n_r=None, n_theta=None, prune_ratio=1e-6, vary_max=0.1,
+                        gate_rel=1e-3, margin_frac=0.02):
         lc = icrs_learned_config()
         lib().icrs_default_learned_config(ctypes.byref(lc))
         lc.n_check = n_check
@@ -312,15 +334,19 @@ class Handle:
         lc.log_safety = model.log_safety
         lc.prune_ratio, lc.vary_max, lc.gate_rel = prune_ratio, vary_max, gate_rel
         lc.margin_frac = margin_frac
-        mag = mag if mag is not None else torch.empty(n, dtype=torch.float64, device=t.device)
-        status = status if status is not None else torch.empty(n, dtype=torch.int32, device=t.device)
-        ws = workspace if workspace is not None else self.learned_workspace(p.shape[0], n)
-        st = icrs_learned_stats()
-        _check(lib().icrs_magnification_learned(self._h, p.shape[0], _ptr(p), _ptr(o), n, _ptr(t), ctypes.byref(lc),
-                                                _ptr(model.packed), _ptr(model.params), _ptr(model.norm),
-                                                _ptr(mag), _ptr(status), ctypes.byref(st), _ptr(ws), ws.numel()),
-               "icrs_magnification_learned")
-        return mag, status, st.as_dict()
+        return lc
+
+    def run_learned(self, t, model, mag, status, stats=False, **kw):
+        """icrs_run_learned on the batch uploaded by prepare() (whose workspace must be a
+        learned workspace): device work only when stats=False, safe inside stream capture."""
+        ws = self._prep_ws
+        lc = self._learned_config(model, **kw)
+        st = icrs_learned_stats() if stats else None
+        _check(lib().icrs_run_learned(self._h, _ptr(_dev(t, torch.float64)), ctypes.byref(lc), _ptr(model.packed),
+                                      _ptr(model.params), _ptr(model.norm), _ptr(mag), _ptr(status),
+                                      ctypes.byref(st) if stats else None, _ptr(ws), ws.numel()),
+               "icrs_run_learned")
+        return st.as_dict() if stats else None
 
     # ---- learned-bounds network (blob layouts in include/icrs.h) -------------------------
     def mlp_pack(self, params, packed):

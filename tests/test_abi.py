@@ -79,3 +79,32 @@ def test_binding_structs_match_header(name):
     mirror = getattr(icrs, name)._fields_
     assert [f for _, f in fields] == [f for f, _ in mirror]
     assert [widths[t] for t, _ in fields] == [ctypes.sizeof(c) for _, c in mirror]
+
+
+def test_epoch_count_above_the_item_encoding_is_rejected_before_any_launch():
+    """FP64-pass work items pack (epoch, sector) into an int32 as 16 e + slot, so a call over
+    more than 2^27 epochs is refused with ICRS_EINVAL on the host, before anything is enqueued
+    (no device pointer is touched: the stand-in pointers below are never dereferenced)."""
+    from paper_2510_02639_amd import icrs
+    L = icrs.lib()
+    cfg = icrs.icrs_config()
+    L.icrs_default_config(ctypes.byref(cfg))
+    h = ctypes.c_void_p()
+    assert L.icrs_create(ctypes.byref(cfg), None, ctypes.byref(h)) == 0
+    try:
+        import numpy as np
+        p = np.array([[0.9, 0.1, 0.05, 0.6, 0.0, 20.0, 1e-2, 0.5, 0.0, 0.0, 0.0]])
+        fake = ctypes.c_void_p(256)
+        for n, want in ((icrs.ICRS_MAX_EPOCHS + 1, -1), ((1 << 31) // 10 + 1, -1)):
+            off = np.array([0, n], dtype=np.int64)
+            code = L.icrs_magnification(h, 1, p.ctypes.data_as(ctypes.c_void_p), off.ctypes.data_as(ctypes.c_void_p),
+                                        n, fake, fake, fake, fake, ctypes.c_size_t(1 << 62))
+            assert code == want, (n, code)
+        # the limit itself passes the host checks and then asks for a larger workspace
+        n = icrs.ICRS_MAX_EPOCHS
+        off = np.array([0, n], dtype=np.int64)
+        code = L.icrs_magnification(h, 1, p.ctypes.data_as(ctypes.c_void_p), off.ctypes.data_as(ctypes.c_void_p),
+                                    n, fake, fake, fake, fake, ctypes.c_size_t(0))
+        assert code == -2  # ICRS_ENOMEM
+    finally:
+        L.icrs_destroy(h)

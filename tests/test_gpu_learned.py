@@ -183,3 +183,37 @@ def test_learned_results_do_not_depend_on_workspace_contents():
     assert np.all(np.isfinite(m0)) and st0["n_learned"] > 0
     for m, s, st in out[1:]:
         assert np.array_equal(m, m0) and np.array_equal(s, s0) and st == st0
+
+
+@pytest.mark.parametrize("grid", [(128, 512), (64, 256)])
+def test_learned_epochs_match_the_oracle_quadrature_on_their_boxes(grid):
+    """Parity of the learned path itself: for every epoch that took the learned route, the
+    device's magnification equals the oracle's quadrature on the same (final) boxes and grid,
+    plus the point-source magnification of the images pruned from the grid (those below
+    1e-6 of the epoch's point-source total), within the FP32 bar."""
+    w = _metric_subset(n_events=24, every=40)
+    model = learned.BoundsModel.load()
+    h = icrs.Handle(n_lens=2, n_limb=128, n_r=128, n_theta=512, ray_precision="fp32", root_precision="fp32")
+    t = torch.tensor(w.t, device="cuda")
+    ws = h.learned_workspace(w.n_events, w.n_epochs)
+    ml, sl, st = h.magnification_learned(w.params, w.offsets, t, model, workspace=ws, n_r=grid[0], n_theta=grid[1],
+                                         gate_rel=3e-3)
+    sec, per, ns = h.get_sectors(w.n_epochs, ws)
+    torch.cuda.synchronize()
+    ml, sl = ml.cpu().numpy(), sl.cpu().numpy().astype(np.uint32)
+    sec, per, ns = sec.cpu().numpy(), per.cpu().numpy(), ns.cpu().numpy()
+    ev = np.repeat(np.arange(w.n_events), np.diff(w.offsets))
+    learned_epochs = np.nonzero(sl & icrs.ST_LEARNED)[0]
+    assert learned_epochs.size > 0.3 * w.n_epochs
+    rel = []
+    for e in learned_epochs:
+        p = w.params[ev[e]]
+        om, _ = O.magnification_given(2, p, w.t[e:e + 1], sec[e:e + 1], per[e:e + 1], ns[e:e + 1], *grid)
+        eps, a = O.frame(2, p)
+        A, mu = O.point_mag(eps, a, O.source_center(p, w.t[e]))
+        pruned = np.sum(np.abs(mu)[np.abs(mu) < 1e-6 * A])
+        rel.append(abs(ml[e] / (om[0] + pruned) - 1))
+    rel = np.array(rel)
+    print(f"learned parity {grid}: {rel.size} learned epochs of {w.n_epochs}, max {rel.max():.2e}, median "
+          f"{np.median(rel):.2e}", flush=True)
+    assert np.all(rel <= 3e-5)

@@ -44,6 +44,30 @@ def _report(name, rel):
     print(f"{name}: n={rel.size} max rel {np.max(rel):.3e} median {np.median(rel):.3e}", flush=True)
 
 
+def _check_every_epoch(w, mag, sec, per, ns, ref, tol, name, n_r=None, n_theta=None, min_same=0.9):
+    """Value check of every epoch.  Where the device and the oracle chose the same sector
+    count, the device's magnification is compared with the oracle's end-to-end result;
+    where they did not (image-limb points on the other side of a bin edge after last-bit
+    differences of the two root paths), it is compared with the oracle's quadrature on the
+    device's own final sectors on the same grid, so no epoch goes unchecked.  Returns the
+    per-epoch relative errors."""
+    n_r = n_r or w.n_r
+    n_theta = n_theta or w.n_theta
+    same = ns == ref["nsec"]
+    rel = np.abs(mag / ref["mag"] - 1)
+    ev_of = np.repeat(np.arange(w.n_events), np.diff(w.offsets))
+    for e in np.nonzero(~same)[0]:
+        om, _ = O.magnification_given(w.n_lens, w.params[ev_of[e]], w.t[e:e + 1], sec[e:e + 1], per[e:e + 1],
+                                      ns[e:e + 1], n_r, n_theta)
+        rel[e] = abs(mag[e] / om[0] - 1)
+    print(f"{name}: sector-count agreement {same.mean():.3f} ({np.count_nonzero(~same)} epochs checked on the "
+          f"device's own sectors)", flush=True)
+    _report(name, rel)
+    assert same.mean() >= min_same
+    assert np.all(rel <= tol), np.nonzero(rel > tol)
+    return rel
+
+
 def test_config1_end_to_end_fp64():
     w = W.config1()
     mag, st, sec, per, ns, _ = _run(w)
@@ -145,11 +169,7 @@ def test_ragged_binary_batch_fp64():
     w = W.Workload("ragged", 2, sub.params, np.array(off, np.int64), np.concatenate(ts), 64, 64, 256, "fp64", "fp64")
     mag, st, sec, per, ns, _ = _run(w)
     ref = _oracle(w)
-    rel = np.abs(mag / ref["mag"] - 1)
-    _report("ragged fp64", rel)
-    same = ns == ref["nsec"]
-    assert same.mean() >= 0.95
-    assert np.all(rel[same] <= FP64_TOL)
+    _check_every_epoch(w, mag, sec, per, ns, ref, FP64_TOL, "ragged fp64", min_same=0.95)
 
 
 def test_triple_fp64_small():
@@ -163,11 +183,7 @@ def test_triple_fp64_small():
                    "fp64", "fp64")
     mag, st, sec, per, ns, _ = _run(w)
     ref = _oracle(w)
-    rel = np.abs(mag / ref["mag"] - 1)
-    _report("triple fp64", rel)
-    same = ns == ref["nsec"]
-    assert same.mean() >= 0.9
-    assert np.all(rel[same] <= FP64_TOL)
+    _check_every_epoch(w, mag, sec, per, ns, ref, FP64_TOL, "triple fp64")
 
 
 def test_run_to_run_bitwise_determinism():
@@ -287,12 +303,7 @@ def test_fp32_end_to_end_planetary():
     w = _planetary_subset()
     mag, st, sec, per, ns, _ = _run(w, ray="fp32", root="fp32")
     ref = _oracle(w)
-    rel = np.abs(mag / ref["mag"] - 1)
-    _report("e2e fp32 planetary", rel)
-    same = ns == ref["nsec"]
-    print(f"sector-count agreement {same.mean():.3f}", flush=True)
-    assert same.mean() >= 0.95
-    assert np.all(rel[same] <= FP32_TOL)
+    _check_every_epoch(w, mag, sec, per, ns, ref, FP32_TOL, "e2e fp32 planetary", min_same=0.95)
 
 
 def test_fp32_rays_fall_back_to_fp64_next_to_a_planet():
@@ -354,16 +365,23 @@ def test_fp32_rays_on_poorly_resolved_near_caustic_images():
     assert np.all(rel <= FP32_TOL)
 
 
+# epochs of the 2048-event workload (event 2035, q = 1.4e-5) where one limb point lies inside
+# the planetary caustic while the source centre does not: warm-started from the centre's
+# roots, two Ehrlich-Aberth iterates settled in the root cluster next to the planet on one
+# root, one of the five images went missing and the epoch carried a false image-count flag
+_LOST_ROOT_EPOCHS = np.array([5083418, 5083483, 5083637, 5083769, 5083922, 5084692, 5085325])
+
+
 def test_full_benchmark_workload_sampled_against_oracle():
     """The whole 2048-event binary workload (about 5.2 M epochs, FP32 roots and rays,
     128 limb points, 128 x 512) in the configuration the benchmark times: one handle, one
     preallocated workspace, output buffers passed in.  Every output is finite, epochs whose
     limb points lost an image or a root are rare, a second call is bitwise identical, and a
     seeded sample of epochs (the first and last epoch of the batch and a few flagged ones
-    among them) matches the oracle run end to end on each epoch alone, within the FP32 bar
-    where both choose the same sector count.  (Whether a spurious polynomial root drifts
-    onto an image under Newton's method can differ between the two root paths at the last
-    bit, so the flag itself is compared by its rarity, not epoch by epoch.)"""
+    among them, and the epochs where a warm-started limb solve once lost an image) matches
+    the oracle run end to end on each epoch alone: the image-count flag epoch by epoch, and
+    every magnification at the FP32 bar (on the oracle's sectors where the sector counts
+    agree, else on the device's own)."""
     w = W.metric_workload(2048)
     h = icrs.Handle(n_lens=2, n_limb=w.n_limb, n_r=w.n_r, n_theta=w.n_theta, ray_precision="fp32",
                     root_precision="fp32")
@@ -373,7 +391,7 @@ def test_full_benchmark_workload_sampled_against_oracle():
     ws = h.learned_workspace(w.n_events, w.n_epochs)
     h.magnification(w.params, w.offsets, t, mag, status, ws)
     first = mag.clone()
-    _, _, ns_all = h.get_sectors(w.n_epochs, ws)
+    sec_all, per_all, ns_all = h.get_sectors(w.n_epochs, ws)
     h.magnification(w.params, w.offsets, t, mag, status, ws)
     torch.cuda.synchronize()
     assert torch.equal(first, mag)
@@ -383,24 +401,113 @@ def test_full_benchmark_workload_sampled_against_oracle():
              ("cap_overflow", icrs.ST_CAP_OVERFLOW), ("clip", icrs.ST_CLIP), ("nan", icrs.ST_NAN))}
     print(f"full workload: {w.n_epochs} epochs, status bits {bits}", flush=True)
     assert np.all(np.isfinite(m)) and np.all(m > 0) and bits["nan"] == 0
-    flagged = np.nonzero(st & (icrs.ST_IMG_COUNT | icrs.ST_ROOT_NONCONV))[0]
-    assert flagged.size <= 1e-4 * w.n_epochs
+    flagged = np.nonzero(st & (icrs.ST_IMG_COUNT | icrs.ST_ROOT_NONCONV | icrs.ST_IMG_RECHECK))[0]
+    assert flagged.size <= 64 and bits["img_count"] <= 64   # every flagged epoch is checked below
+    assert not np.any(st & icrs.ST_IMG_RECHECK)
 
     rng = np.random.default_rng(11)
-    idx = np.unique(np.concatenate([[0, w.n_epochs - 1], rng.choice(w.n_epochs, 46, replace=False),
-                                    flagged[:: max(1, flagged.size // 8)][:8]]))
+    idx = np.unique(np.concatenate([[0, w.n_epochs - 1], rng.choice(w.n_epochs, 46, replace=False), flagged,
+                                    _LOST_ROOT_EPOCHS]))
     ev = np.searchsorted(w.offsets, idx, side="right") - 1
     sub = W.Workload("full-sample", 2, w.params[ev], np.arange(idx.size + 1, dtype=np.int64), w.t[idx], w.n_limb,
                      w.n_r, w.n_theta, "fp32", "fp32")
     ref = _oracle(sub)
-    ns = ns_all.cpu().numpy()[idx]
-    rel = np.abs(m[idx] / ref["mag"] - 1)
-    same = ns == ref["nsec"]
-    _report("full workload, sampled epochs", rel[same])
+    di = torch.tensor(idx, device="cuda")
+    sec, per, ns = sec_all[di].cpu().numpy(), per_all[di].cpu().numpy(), ns_all[di].cpu().numpy()
     for e in np.intersect1d(idx, flagged):
         k = np.searchsorted(idx, e)
         print(f"flagged epoch {e}: status {st[e]} (oracle {ref['status'][k]}), sectors {ns[k]} (oracle "
-              f"{ref['nsec'][k]}), rel {rel[k]:.2e}", flush=True)
-    print(f"sector-count agreement {same.mean():.3f}", flush=True)
-    assert same.mean() >= 0.9
-    assert np.all(rel[same] <= FP32_TOL)
+              f"{ref['nsec'][k]})", flush=True)
+    # the image-count flag is the oracle's, epoch by epoch
+    assert np.array_equal(st[idx] & icrs.ST_IMG_COUNT, ref["status"] & icrs.ST_IMG_COUNT)
+    _check_every_epoch(sub, m[idx], sec, per, ns, ref, FP32_TOL, "full workload, sampled epochs")
+
+
+def test_repeated_calls_are_bitwise_identical_and_images_validated():
+    """Planetary events at rho = 1e-3 with FP32 roots (the configuration in which earlier
+    builds returned run-dependent results): twelve eager calls and twelve prepare/run calls,
+    with FP32 and with FP64 rays, all give bitwise identical magnifications and status words;
+    no kept image ever fails the final substitution check; and the centre images equal the
+    oracle's on every epoch (same count, each within 1e-9)."""
+    w = _planetary_subset(n_events=8, per_event=12, rho=1e-3)
+    t = torch.tensor(w.t, device="cuda")
+    for ray in ("fp32", "fp64"):
+        h = icrs.Handle(n_lens=2, n_limb=128, n_r=128, n_theta=512, ray_precision=ray, root_precision="fp32")
+        ref_m, ref_s = (x.clone() for x in h.magnification(w.params, w.offsets, t))
+        for _ in range(11):
+            m, s = h.magnification(w.params, w.offsets, t)
+            assert torch.equal(m, ref_m) and torch.equal(s, ref_s)
+        ws = h.prepare(w.params, w.offsets, w.n_epochs)
+        m = torch.empty_like(ref_m)
+        s = torch.empty_like(ref_s)
+        for _ in range(12):
+            m.fill_(-1.0)
+            s.fill_(-1)
+            h.run(t, m, s)
+            torch.cuda.synchronize()
+            assert torch.equal(m, ref_m) and torch.equal(s, ref_s)
+        st = ref_s.cpu().numpy().astype(np.uint32)
+        assert not np.any(st & (icrs.ST_IMG_RECHECK | icrs.ST_NAN))
+    h = icrs.Handle(n_lens=2, n_limb=128, n_r=128, n_theta=512, ray_precision="fp32", root_precision="fp32")
+    img, nimg, aps = h.point_images(w.params, w.offsets, t)
+    torch.cuda.synchronize()
+    img, nimg = img.cpu().numpy(), nimg.cpu().numpy()
+    for i in range(w.n_events):
+        eps, a = O.frame(2, w.params[i])
+        for e in range(w.offsets[i], w.offsets[i + 1]):
+            ref, _ = O.images(eps, a, O.source_center(w.params[i], w.t[e]))
+            got = img[e, :nimg[e], 0] + 1j * img[e, :nimg[e], 1]
+            assert nimg[e] == ref.size, (e, got, ref)
+            for z in ref:
+                assert np.min(np.abs(got - z)) < 1e-9
+            # every kept image satisfies the lens equation
+            wc = O.source_center(w.params[i], w.t[e])
+            for z in got:
+                assert abs(z - np.sum(eps / np.conj(z - a)) - wc) < 1e-9
+
+
+def test_out_of_range_sector_counts_give_nan_and_a_status_bit():
+    """icrs_magnification_given and the reverse mode take the sector counts from device memory;
+    a count outside 0..10 shoots no rays and marks that epoch (NaN, ICRS_ST_BAD_SECTORS), and
+    the other epochs are unchanged."""
+    w = W.config1()
+    ref = _oracle(w)
+    h = icrs.Handle(n_lens=2, n_limb=64, n_r=64, n_theta=256)
+    t = torch.tensor(w.t, device="cuda")
+    sec = torch.tensor(ref["sectors"], device="cuda")
+    per = torch.tensor(ref["periodic"], device="cuda")
+    ns_ok = torch.tensor(ref["nsec"], device="cuda")
+    good, _ = h.magnification_given(w.params, w.offsets, t, sec, per, ns_ok)
+    ns_bad = ns_ok.clone()
+    bad_idx = [3, 50, 120]
+    ns_bad[3], ns_bad[50], ns_bad[120] = 11, -1, 1 << 20
+    m, s = h.magnification_given(w.params, w.offsets, t, sec, per, ns_bad)
+    _, J, M = h.magnification_vjp(w.params, w.offsets, t, sec, per, ns_bad, jac=True, mag=True)
+    torch.cuda.synchronize()
+    m, s, good = m.cpu().numpy(), s.cpu().numpy().astype(np.uint32), good.cpu().numpy()
+    J, M = J.cpu().numpy(), M.cpu().numpy()
+    mask = np.zeros(w.n_epochs, bool)
+    mask[bad_idx] = True
+    assert np.all(np.isnan(m[mask])) and np.all(s[mask] & icrs.ST_BAD_SECTORS)
+    assert np.array_equal(m[~mask], good[~mask]) and not np.any(s[~mask] & icrs.ST_BAD_SECTORS)
+    assert np.all(np.isnan(J[mask])) and np.all(np.isnan(M[mask]))
+    assert np.all(np.isfinite(J[~mask])) and np.all(np.abs(M[~mask] / good[~mask] - 1) <= FP64_TOL)
+
+
+def test_triple_config3_end_to_end_fp32_rays():
+    """The triple-lens workload's configuration end to end (FP64 roots, FP32 rays, 128 limb
+    points, 128 x 512 grids) on epochs around each of four events' peaks and on their first
+    epochs, every epoch value-checked at the FP32 bar."""
+    big = W.config3(n_events=4, n_epochs=2000)
+    ts, off = [], [0]
+    for i in range(4):
+        seg = big.t[big.offsets[i]:big.offsets[i + 1]]
+        seg = np.concatenate([seg[:2], seg[980:1020:5]])
+        ts.append(seg)
+        off.append(off[-1] + seg.size)
+    w = W.Workload("triple-config3", 3, big.params, np.array(off, np.int64), np.concatenate(ts), 128, 128, 512,
+                   "fp32", "fp64")
+    mag, st, sec, per, ns, _ = _run(w, ray="fp32", root="fp64")
+    ref = _oracle(w)
+    assert np.all(np.isfinite(mag))
+    _check_every_epoch(w, mag, sec, per, ns, ref, FP32_TOL, "triple config3 e2e")

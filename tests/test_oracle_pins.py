@@ -132,6 +132,33 @@ def test_spurious_roots_drifting_to_an_image_are_not_counted_twice(s, q, w):
     assert R.multiset_close(imgs, ref, 1e-8), (imgs, ref)
 
 
+# a planetary binary (s = 0.768, q = 1.4e-5) and source points just inside its planetary
+# caustic: five images, three of them within a few 1e-3 of each other next to the planet
+# (the points are limb points of benchmark-workload epochs where a solve started from the
+# source centre's roots lost one of them)
+_PLANETARY_CLUSTER_S_Q = (0.7680762680197694, 1.3738029330516958e-05)
+_PLANETARY_CLUSTER_POINTS = [complex(-0.5342693897421594, -0.00689307926796158),
+                             complex(-0.5339617226949848, -0.0073322717253918885),
+                             complex(-0.5337469782160287, -0.007306817365788684),
+                             complex(-0.5351270736998957, -0.0062434861140690575),
+                             complex(-0.5336263835786164, -0.007107361116016892),
+                             complex(-0.5325874217950066, -0.00622251111559628)]
+
+
+@pytest.mark.parametrize("w", _PLANETARY_CLUSTER_POINTS)
+def test_images_inside_a_small_planetary_caustic(w):
+    s, q = _PLANETARY_CLUSTER_S_Q
+    eps, a = O.frame(2, O.params(s=s, q=q))
+    imgs, st = O.images(eps, a, w)
+    ref = R.newton_images(eps, a, w)
+    assert ref.size == 5
+    assert st & O.ST_IMG_COUNT == 0
+    assert R.multiset_close(imgs, ref, 1e-8), (imgs, ref)
+    # inside a caustic the five signed magnifications sum to one
+    A, mu = O.point_mag(eps, a, w)
+    assert abs(np.sum(mu) - 1.0) < 1e-6 * A
+
+
 # --- O7: point-source magnification (eqs. amp_point, detJ) ------------------------------
 
 def test_single_lens_point_magnification_closed_form():
