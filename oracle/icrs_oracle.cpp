@@ -186,22 +186,28 @@ void horner(const Poly& P, cplx z, cplx* p, cplx* dp) {
   *dp = d;
 }
 
-bool ea_roots(const Poly& P, std::vector<cplx>& z, int* iters_out) {
+// With continue_from set, the iteration restarts from the estimates already in z (no Cauchy
+// circle), runs at most cap iterations and stops a root on its step test only: the
+// validation's last resort when the image count is still forbidden (see find_images).
+bool ea_roots(const Poly& P, std::vector<cplx>& z, int* iters_out, bool continue_from = false, int cap = 500) {
   const int n = static_cast<int>(P.size()) - 1;
-  z.assign(n, cplx(0.0, 0.0));
-  double R = 0.0;
-  for (int j = 0; j < n; ++j) R = std::max(R, std::abs(P[j] / P[n]));
-  R += 1.0;
-  for (int k = 0; k < n; ++k) {
-    const double ang = 2.0 * kPi * k / n + kPi / (2.0 * n);
-    z[k] = cplx(R * std::cos(ang), R * std::sin(ang));
+  if (!continue_from) {
+    z.assign(n, cplx(0.0, 0.0));
+    double R = 0.0;
+    for (int j = 0; j < n; ++j) R = std::max(R, std::abs(P[j] / P[n]));
+    R += 1.0;
+    for (int k = 0; k < n; ++k) {
+      const double ang = 2.0 * kPi * k / n + kPi / (2.0 * n);
+      z[k] = cplx(R * std::cos(ang), R * std::sin(ang));
+    }
   }
+  const bool noise_stop = !continue_from;
   // A root is finished once its step is below 1e-14 max(1,|z|) or |P(z)| is down to the
   // rounding noise of evaluating P there, 8 n u sum_j |b_j| |z|^j with u = 2^-53 (clustered
   // roots never reach the first test).  Finished roots are no longer moved.
   std::vector<char> done(n, 0);
   std::vector<cplx> step(n);
-  for (int it = 0; it < 500; ++it) {
+  for (int it = 0; it < cap; ++it) {
     for (int k = 0; k < n; ++k) {
       step[k] = cplx(0.0, 0.0);
       if (done[k]) continue;
@@ -211,7 +217,7 @@ bool ea_roots(const Poly& P, std::vector<cplx>& z, int* iters_out) {
       const double az = std::abs(z[k]);
       for (int j = n; j >= 0; --j) noise = noise * az + std::abs(P[j]);
       noise *= 8.0 * n * 1.1102230246251565e-16;
-      if (std::abs(p) <= noise) {
+      if (noise_stop && std::abs(p) <= noise) {
         done[k] = 1;
         continue;
       }
@@ -233,7 +239,7 @@ bool ea_roots(const Poly& P, std::vector<cplx>& z, int* iters_out) {
       return true;
     }
   }
-  if (iters_out) *iters_out = 500;
+  if (iters_out) *iters_out = cap;
   return false;
 }
 
@@ -289,15 +295,28 @@ uint32_t find_images(const Lens& L, cplx w, std::vector<cplx>& images) {
   std::vector<cplx> roots;
   int iters = 0;
   if (!ea_roots(P, roots, &iters)) st |= ST_ROOT_NONCONV;
-  for (const cplx& r : roots) try_accept(L, w, r, images);
-  if (!count_ok(L.n, static_cast<int>(images.size()))) {
-    for (int k = 0; k < L.n; ++k) {
-      cplx wk = w;
-      for (int j = 0; j < L.n; ++j)
-        if (j != k) wk += L.eps[j] / std::conj(L.a[k] - L.a[j]);
-      try_accept(L, w, L.a[k] - L.eps[k] / std::conj(wk - L.a[k]), images);
+  auto validate = [&]() {
+    images.clear();
+    for (const cplx& r : roots) try_accept(L, w, r, images);
+    if (!count_ok(L.n, static_cast<int>(images.size()))) {
+      for (int k = 0; k < L.n; ++k) {
+        cplx wk = w;
+        for (int j = 0; j < L.n; ++j)
+          if (j != k) wk += L.eps[j] / std::conj(L.a[k] - L.a[j]);
+        try_accept(L, w, L.a[k] - L.eps[k] / std::conj(wk - L.a[k]), images);
+      }
     }
-    if (!count_ok(L.n, static_cast<int>(images.size()))) st |= ST_IMG_COUNT;
+    return count_ok(L.n, static_cast<int>(images.size()));
+  };
+  if (!validate()) {
+    // Two estimates that stopped on the rounding-noise test inside one root's neighbourhood
+    // (a tight cluster of roots next to a low-mass lens) leave a root, and its image, unfound.
+    // Last resort: continue the simultaneous iteration from the current estimates with the
+    // step test only (the repulsion term of Sec. 3.1 then separates the pair), at most 100
+    // iterations, and validate again.
+    int it2 = 0;
+    ea_roots(P, roots, &it2, true, 100);
+    if (!validate()) st |= ST_IMG_COUNT;
   }
   return st;
 }
