@@ -1109,8 +1109,8 @@ namespace {
 // through the roots (Sec. 3.5).  The images z* are roots of eq. lens_eq_z, P(z*; b) = 0 with
 // coefficients b(params); differentiating that identity gives the paper's root derivative
 //   dz*/db_l = -(z*)^l / P'(z*)        (ascending powers: dP/db_l = z^l),
-// so with the tangents db/dparams of the coefficients (dual numbers through the same
-// construction as O4) each image moves by dz* = -(sum_l z*^l db_l) / P'(z*).  Eq. amp_point
+// so with the tangents db/dparams of the coefficients (dual numbers through O4's
+// construction) each image moves by dz* = -(sum_l z*^l db_l) / P'(z*).  Eq. amp_point
 // then gives A = sum_j 1/|det J(z_j)| with eq. detJ evaluated in dual numbers, through the
 // moved images and the parameter-dependent masses and positions.
 
@@ -1128,7 +1128,7 @@ DC operator/(const DC& a, const DC& b) {
 DC dconj(const DC& a) { return {a.x, -a.y}; }
 DC dc(const Dual& x) { return {x, Dual(0.0)}; }
 
-// O4's construction in dual arithmetic: P(z) = (z - w) prod_i D_i - H sum_i eps_i prod_{j!=i} D_j.
+// Polynomials with dual-number coefficients (O4's factors in dual arithmetic).
 using PolyD = std::vector<DC>;
 PolyD dpmul(const PolyD& a, const PolyD& b) {
   PolyD c(a.size() + b.size() - 1, dc(Dual(0.0)));
@@ -1147,39 +1147,24 @@ PolyD dpscale(const PolyD& a, const DC& s) {
   for (auto& x : c) x = x * s;
   return c;
 }
-PolyD lens_polynomial_dual(const LensT<Dual>& L, const DC& w) {
-  const int n = L.n;
-  const DC one = dc(Dual(1.0));
-  std::vector<DC> a(n);
-  for (int k = 0; k < n; ++k) a[k] = {L.ax[k], L.ay[k]};
-  PolyD H{one};
-  for (int k = 0; k < n; ++k) H = dpmul(H, PolyD{dc(Dual(0.0)) - a[k], one});
-  PolyD G = dpscale(H, dconj(w));
-  for (int k = 0; k < n; ++k) {
-    PolyD Pk{one};
-    for (int j = 0; j < n; ++j)
-      if (j != k) Pk = dpmul(Pk, PolyD{dc(Dual(0.0)) - a[j], one});
-    G = dpadd(G, dpscale(Pk, dc(L.eps[k])));
+// Value and z-derivative of a polynomial (ascending coefficients) at z, by Horner.
+void horner_vd(const PolyD& c, const DC& z, DC* v, DC* d) {
+  DC val = c.back(), der = dc(Dual(0.0));
+  for (int j = static_cast<int>(c.size()) - 2; j >= 0; --j) {
+    der = der * z + val;
+    val = val * z + c[j];
   }
-  std::vector<PolyD> D(n);
-  for (int i = 0; i < n; ++i) D[i] = dpadd(G, dpscale(H, dc(Dual(0.0)) - dconj(a[i])));
-  PolyD prodD{one};
-  for (int i = 0; i < n; ++i) prodD = dpmul(prodD, D[i]);
-  PolyD P = dpmul(PolyD{dc(Dual(0.0)) - w, one}, prodD);
-  PolyD S{dc(Dual(0.0))};
-  for (int i = 0; i < n; ++i) {
-    PolyD Q{dc(L.eps[i])};
-    for (int j = 0; j < n; ++j)
-      if (j != i) Q = dpmul(Q, D[j]);
-    S = dpadd(S, Q);
-  }
-  P = dpadd(P, dpscale(dpmul(H, S), dc(Dual(-1.0))));
-  P.resize(n * n + 2, dc(Dual(0.0)));
-  return P;
+  *v = val;
+  *d = der;
 }
 
 // A_ps at the source centre of epoch t and dA_ps/dparams (11 entries; rho and u1 do not
-// enter).  Returns the image-finding status bits.
+// enter).  Returns the image-finding status bits.  The root derivative needs
+// sum_l z*^l db_l = dP/dparams at fixed z and P'(z*).  Both are evaluated at the root
+// through O4's factors rather than through the expanded coefficients: the expanded sum
+// cancels to a small fraction of its terms at clustered roots (a low-mass companion),
+// while each factor (degree <= N) keeps its own rounding small.
+//   P = (z - w) prod_i D_i - H sum_i eps_i prod_{j != i} D_j
 uint32_t point_mag_jacobian(int n_lens, const double* p, double t, double* A_out, double* jac) {
   const Lens L = make_lens(n_lens, p);
   const cplx wc = source_center(p, t);
@@ -1193,29 +1178,56 @@ uint32_t point_mag_jacobian(int n_lens, const double* p, double t, double* A_out
   const LensT<Dual> Ld = make_lens_t<Dual>(n_lens, pd);
   DC w;
   source_center_t<Dual>(pd, t, &w.x, &w.y);
-  const PolyD B = lens_polynomial_dual(Ld, w);
-  const int deg = static_cast<int>(B.size()) - 1;
+  const int n = Ld.n;
+  const DC one = dc(Dual(1.0)), zero = dc(Dual(0.0));
+  std::vector<DC> a(n);
+  for (int k = 0; k < n; ++k) a[k] = {Ld.ax[k], Ld.ay[k]};
+  PolyD H{one};
+  for (int k = 0; k < n; ++k) H = dpmul(H, PolyD{zero - a[k], one});
+  PolyD G = dpscale(H, dconj(w));
+  for (int k = 0; k < n; ++k) {
+    PolyD Pk{one};
+    for (int j = 0; j < n; ++j)
+      if (j != k) Pk = dpmul(Pk, PolyD{zero - a[j], one});
+    G = dpadd(G, dpscale(Pk, dc(Ld.eps[k])));
+  }
+  std::vector<PolyD> D(n);
+  for (int i = 0; i < n; ++i) D[i] = dpadd(G, dpscale(H, zero - dconj(a[i])));
   Dual A(0.0);
   for (const cplx& z : img) {
-    // P'(z*) from the coefficient values; sum_l z*^l db_l per tangent
-    cplx dP(0.0, 0.0), zl(1.0, 0.0);
-    for (int l = 1; l <= deg; ++l) {
-      dP += static_cast<double>(l) * cplx(B[l].x.v, B[l].y.v) * zl;
-      zl *= z;
+    const DC zz{Dual(z.real()), Dual(z.imag())};
+    DC Hv, Hd;
+    horner_vd(H, zz, &Hv, &Hd);
+    std::vector<DC> Dv(n), Dd(n);
+    for (int i = 0; i < n; ++i) horner_vd(D[i], zz, &Dv[i], &Dd[i]);
+    // P(z) and P'(z) by the product rule on the factors
+    DC prodD = one, dprodD = zero;
+    for (int i = 0; i < n; ++i) {
+      dprodD = dprodD * Dv[i] + prodD * Dd[i];
+      prodD = prodD * Dv[i];
     }
+    DC S = zero, dS = zero;  // sum_i eps_i prod_{j != i} D_j and its z-derivative
+    for (int i = 0; i < n; ++i) {
+      DC q = dc(Ld.eps[i]), dq = zero;
+      for (int j = 0; j < n; ++j) {
+        if (j == i) continue;
+        dq = dq * Dv[j] + q * Dd[j];
+        q = q * Dv[j];
+      }
+      S = S + q;
+      dS = dS + dq;
+    }
+    const DC Pz = (zz - w) * prodD - Hv * S;                      // tangents: dP/dparams at z
+    const DC Pp = prodD + (zz - w) * dprodD - Hd * S - Hv * dS;   // value: P'(z)
+    const cplx dP(Pp.x.v, Pp.y.v);
     DC zd{Dual(z.real()), Dual(z.imag())};
     for (int k = 0; k < kNT; ++k) {
-      cplx s(0.0, 0.0), zp(1.0, 0.0);
-      for (int l = 0; l <= deg; ++l) {
-        s += cplx(B[l].x.d[k], B[l].y.d[k]) * zp;
-        zp *= z;
-      }
-      const cplx dz = -s / dP;
+      const cplx dz = -cplx(Pz.x.d[k], Pz.y.d[k]) / dP;  // dz*/db . db/dparams (Sec. 3.5)
       zd.x.d[k] = dz.real();
       zd.y.d[k] = dz.imag();
     }
     // eq. detJ: det J = 1 - |sum_i eps_i / (conj(z) - conj(a_i))^2|^2
-    DC kap = dc(Dual(0.0));
+    DC kap = zero;
     for (int i = 0; i < Ld.n; ++i) {
       const DC d = dconj(zd - DC{Ld.ax[i], Ld.ay[i]});
       kap = kap + dc(Ld.eps[i]) / (d * d);

@@ -109,3 +109,25 @@ def test_hybrid_curve_is_full_method_on_selected_epochs_and_point_elsewhere():
     full = O.magnification(2, p, t[ext], n_limb=64, n_r=64, n_theta=256)
     assert np.array_equal(mag[ext], full["mag"]) and np.array_equal(st[ext], full["status"])
     assert np.array_equal(mag[~ext], aps[~ext]) and np.all(st[~ext] == O.ST_POINT)
+
+
+def test_point_jacobian_next_to_low_mass_companions():
+    """Triple lenses of the triple-lens workload (companions of 1e-4..1e-2): clustered roots
+    next to a companion, where the root derivative is evaluated through the polynomial's
+    factors; it must still equal central differences of A_ps (steps 1e-7 max(|p|, 1))."""
+    big = W.config3(n_events=3, n_epochs=2000)
+    w = big.sample_epochs(50)
+    for i in range(w.n_events):
+        sl = slice(w.offsets[i], w.offsets[i + 1])
+        t, p = w.t[sl], w.params[i]
+        a, jac, st = O.point_jacobian(3, p, t)
+        ok = st == 0
+        assert ok.mean() > 0.9
+        for k in (0, 1, 2, 3, 4, 5, 8, 9, 10):
+            h = 1e-7 * max(abs(p[k]), 1.0)
+            pp, pm = p.copy(), p.copy()
+            pp[k] += h
+            pm[k] -= h
+            fd = (O.point_jacobian(3, pp, t)[0] - O.point_jacobian(3, pm, t)[0]) / (2 * h)
+            scale = np.abs(jac[ok, k]).max() + 1e-300
+            assert np.max(np.abs(fd[ok] - jac[ok, k])) <= 1e-6 * scale, (i, k)
