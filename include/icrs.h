@@ -265,9 +265,10 @@ icrs_status icrs_image_bounds(icrs_handle* h, int64_t n_events, const double* pa
  * scaled by exp(log_safety); images with mu < prune_ratio x A_ps get no grid and add mu;
  * epochs whose ring-average point-source magnification differs from the centre's by more
  * than vary_max (relative) go to the plain path before any ray; the drift gate sends back
- * results with |A - A_est| > gate_rel A_ps + |A_ring - A_ps|; each box is widened by
+ * results with |A - A_est| > gate_rel A_ps + gate_slack |A_ring - A_ps| (A_est = A_ps +
+ * w2 (A_ring - A_ps), w2 the limb-darkened profile's mean squared radius); each box is widened by
  * margin_frac of its extent plus the plain floors (rho/100 in r, rho/(100 r_mid) in theta).
- * icrs_default_learned_config: 16, 128, 512, 0, 0.0, 1e-6, 0.1, 1e-3, 0.02. */
+ * icrs_default_learned_config: 16, 128, 512, 0, 0.0, 1e-6, 0.1, 1e-3, 0.02, 0.0. */
 typedef struct icrs_learned_config {
   int32_t n_check;
   int32_t n_r;
@@ -278,6 +279,7 @@ typedef struct icrs_learned_config {
   double vary_max;
   double gate_rel;
   double margin_frac;
+  double gate_slack;  /* >= 0 */
 } icrs_learned_config;
 
 typedef struct icrs_learned_stats {
@@ -317,6 +319,77 @@ icrs_status icrs_run_learned(icrs_handle* h, const double* t, const icrs_learned
                              const uint16_t* packed, const float* mlp_params, const float* norm,
                              double* mag, uint32_t* status, icrs_learned_stats* stats, void* workspace,
                              size_t workspace_bytes);
+
+/* ---- hybrid light curve (Sec. 3.4, item iii) -----------------------------------------
+ * The paper computes finite-source magnifications only on a preselected set of epochs
+ * (e.g. near caustics) and the point-source magnification of eq. amp_point elsewhere; it
+ * gives no selection rule.  The rule here: n_check points on the circle of radius
+ * guard x rho around the source centre are solved like the centre; an epoch is "extended"
+ * when one of them changes the image count or carries a root flag (a caustic crosses the
+ * circle), when their mean point-source magnification differs from the centre's A_ps by
+ * more than tol x A_ps (the Laplacian of A_ps, which leads the finite-source correction),
+ * or when one of them differs by more than vary_max x A_ps.  Extended epochs go through the
+ * plain path with the handle's config; every other epoch gets mag = A_ps and status
+ * ICRS_ST_POINT.  icrs_default_hybrid_config: 16, 0, 2.0, 1e-4, 0.1. */
+typedef struct icrs_hybrid_config {
+  int32_t n_check;  /* 4..64 */
+  int32_t reserved;
+  double guard;     /* >= 1 */
+  double tol;
+  double vary_max;
+} icrs_hybrid_config;
+
+#define ICRS_ST_POINT 2048u /* the epoch took the point-source magnification (hybrid curve) */
+
+void icrs_default_hybrid_config(icrs_hybrid_config* hc);
+/* Workspace of icrs_magnification_hybrid (device, 256-byte aligned). */
+size_t icrs_hybrid_workspace_bytes(const icrs_handle* h, int64_t n_events, int64_t n_epochs);
+/* Hybrid light curves.  Inputs and outputs as for icrs_magnification; workspace of
+ * icrs_hybrid_workspace_bytes().  The extended epochs' list size stays on the device (no
+ * host wait).  Final sectors can be read with icrs_get_sectors() (0 sectors for point
+ * epochs), as the input of icrs_hybrid_vjp. */
+icrs_status icrs_magnification_hybrid(icrs_handle* h, int64_t n_events, const double* params,
+                                      const int64_t* epoch_offsets, int64_t n_epochs, const double* t,
+                                      const icrs_hybrid_config* hc, double* mag, uint32_t* status,
+                                      void* workspace, size_t workspace_bytes);
+/* Point-source magnification of every epoch's source centre and its derivatives: a_ps
+ * [n_epochs] (DEVICE, may be NULL), jac [n_epochs][ICRS_N_PARAMS] (DEVICE) = dA_ps/dparams
+ * through the images (Sec. 3.5's implicit root derivative, taken on eq. lens_eq, whose
+ * solutions are the validated roots), status [n_epochs] (DEVICE, may be NULL) the image-
+ * finding bits.  rho and u_ld columns are 0.  Workspace as for icrs_magnification. */
+icrs_status icrs_point_jacobian(icrs_handle* h, int64_t n_events, const double* params,
+                                const int64_t* epoch_offsets, int64_t n_epochs, const double* t,
+                                double* a_ps, double* jac, uint32_t* status, void* workspace,
+                                size_t workspace_bytes);
+/* Reverse mode of the hybrid curve: status (DEVICE [n_epochs]) from the forward call selects
+ * the rule per epoch -- ICRS_ST_POINT epochs are differentiated through their images, the
+ * others on their frozen sectors (as icrs_magnification_vjp; point epochs must have
+ * n_sectors 0, as the forward leaves them).  cotangent, grad, jac as for
+ * icrs_magnification_vjp (grad needs cotangent; at least one of grad, jac).  Workspace as
+ * for icrs_magnification. */
+icrs_status icrs_hybrid_vjp(icrs_handle* h, int64_t n_events, const double* params,
+                            const int64_t* epoch_offsets, int64_t n_epochs, const double* t,
+                            const uint32_t* status, const double* sectors, const uint8_t* periodic,
+                            const int32_t* n_sectors, const double* cotangent, double* grad, double* jac,
+                            void* workspace, size_t workspace_bytes);
+
+/* ---- marginalised light-curve likelihood (App. B, eq. NLL) ------------------------------
+ * Each event is one data set: fluxes F = (A - 1) F_S + F_base with independent Gaussian noise
+ * sigma, and a Gaussian prior on the linear parameters beta = (F_S, F_base) with mean
+ * (mu_S, mu_B) and standard deviations (sigma_S, sigma_B).  Marginalising beta gives
+ *   NLL = 1/2 r^T (C + M Lambda M^T)^{-1} r + 1/2 ln |C + M Lambda M^T|,  r = F - M mu,
+ * M = [A - 1, 1], evaluated through the appendix's Woodbury forms (the constant n/2 ln 2 pi
+ * is left out, as in eq. NLL).  mag, flux, sigma: DEVICE [n_epochs]; epoch_offsets: HOST
+ * [n_events + 1] CSR as elsewhere; prior: HOST [n_events][4] = (mu_S, mu_B, sigma_S,
+ * sigma_B), sigma_S, sigma_B > 0.  Outputs (DEVICE): nll [n_events]; beta [n_events][5]
+ * (may be NULL) = posterior mean (F_S, F_base) and covariance (SS, SB, BB); dnll_dmag
+ * [n_epochs] (may be NULL) = dNLL/dA per epoch, the cotangent for icrs_magnification_vjp
+ * or icrs_hybrid_vjp.  Workspace: DEVICE, icrs_marginal_nll_workspace_bytes(n_events). */
+size_t icrs_marginal_nll_workspace_bytes(int64_t n_events);
+icrs_status icrs_marginal_nll(icrs_handle* h, int64_t n_events, const int64_t* epoch_offsets, int64_t n_epochs,
+                              const double* mag, const double* flux, const double* sigma, const double* prior,
+                              double* nll, double* beta, double* dnll_dmag, void* workspace,
+                              size_t workspace_bytes);
 
 const char* icrs_status_string(icrs_status s);
 

@@ -348,7 +348,12 @@ hipError_t launch_adjoint(int n_lens, const Batch& b, const SectorBuf& sec, int 
   hipError_t e = (n_lens == 2) ? launch_adjoint_n<2>(b, sec, n_r, n_theta, delta_c, jac, mag, queue, s)
                                : launch_adjoint_n<3>(b, sec, n_r, n_theta, delta_c, jac, mag, queue, s);
   if (e != hipSuccess || !cot || !grad) return e;
+  return launch_contract(b, jac, cot, grad, s);
+}
+
+hipError_t launch_contract(const Batch& b, const double* jac, const double* cot, double* grad, hipStream_t s) {
   const int64_t n = b.n_events * kParams;
+  if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(contract_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, b, jac, cot, grad);
   return hipGetLastError();
 }

@@ -350,7 +350,8 @@ icrs_status run_plain(icrs_handle* h, const Views& v, double* mag, uint32_t* sta
 bool learned_config_ok(const icrs_learned_config* lc) {
   return lc && lc->n_check >= 8 && lc->n_check <= 64 && lc->n_r >= 4 && lc->n_r <= 4096 && lc->n_theta >= 64 &&
          lc->n_theta <= 1024 && lc->prune_ratio >= 0.0 && lc->prune_ratio < 0.1 && lc->vary_max > 0.0 &&
-         lc->gate_rel > 0.0 && fabs(lc->log_safety) < 10.0 && lc->margin_frac >= 0.0 && lc->margin_frac <= 1.0;
+         lc->gate_rel > 0.0 && fabs(lc->log_safety) < 10.0 && lc->margin_frac >= 0.0 && lc->margin_frac <= 1.0 &&
+         lc->gate_slack >= 0.0 && lc->gate_slack <= 10.0;
 }
 
 // The learned path on an uploaded batch (views v over workspace): no host memory is read
@@ -403,7 +404,8 @@ icrs_status run_learned(icrs_handle* h, const Views& v, const icrs_learned_confi
   if (st != ICRS_OK) return st;
   // the gate appends the learned epochs it rejects to the fallback list (and counts them
   // in counts[3])
-  ICRS_TRY(icrs::launch_learned_gate(v.b, lists, counts, n_epochs, a_c, a_ring, mag, status, lc->gate_rel, flags,
+  ICRS_TRY(icrs::launch_learned_gate(v.b, lists, counts, n_epochs, a_c, a_ring, mag, status, lc->gate_rel,
+                                     lc->gate_slack, flags,
                                      lists, counts, h->stream));
   const int32_t* fb = lists + n_epochs;
   ICRS_TRY(tm.begin());
@@ -654,6 +656,7 @@ void icrs_default_learned_config(icrs_learned_config* lc) {
   lc->prune_ratio = 1e-6;
   lc->vary_max = 0.1;
   lc->gate_rel = 1e-3;
+  lc->gate_slack = 0.0;
   lc->margin_frac = 0.02;
 }
 
@@ -713,6 +716,131 @@ icrs_status icrs_run_learned(icrs_handle* h, const double* t, const icrs_learned
   const icrs_status st = run_learned(h, v, lc, packed, mlp_params, norm, mag, status, stats, workspace);
   h->profiling = prof;
   return st;
+}
+
+void icrs_default_hybrid_config(icrs_hybrid_config* hc) {
+  if (!hc) return;
+  memset(hc, 0, sizeof(*hc));
+  hc->n_check = 16;
+  hc->guard = 2.0;
+  hc->tol = 1e-4;
+  hc->vary_max = 0.1;
+}
+
+size_t icrs_hybrid_workspace_bytes(const icrs_handle* h, int64_t n_events, int64_t n_epochs) {
+  if (!h || n_events < 0 || n_epochs < 0) return 0;
+  return learned_layout(h->cfg.n_lens, n_events, n_epochs).total;
+}
+
+icrs_status icrs_magnification_hybrid(icrs_handle* h, int64_t n_events, const double* params,
+                                      const int64_t* epoch_offsets, int64_t n_epochs, const double* t,
+                                      const icrs_hybrid_config* hc, double* mag, uint32_t* status, void* workspace,
+                                      size_t workspace_bytes) {
+  if (!h || !hc || !events_ok(h->cfg, n_events, params, epoch_offsets, n_epochs)) return ICRS_EINVAL;
+  if (hc->n_check < 4 || hc->n_check > 64 || !(hc->guard >= 1.0 && hc->guard <= 100.0) || !(hc->tol > 0.0) ||
+      !(hc->vary_max > 0.0))
+    return ICRS_EINVAL;
+  if (n_epochs > 0 && (!t || !mag || !status)) return ICRS_EINVAL;
+  const LearnedLayout LL = learned_layout(h->cfg.n_lens, n_events, n_epochs);
+  if (workspace && workspace_bytes < LL.total) return ICRS_ENOMEM;
+  Views v;
+  const icrs_status ps = prepare(h, n_events, params, epoch_offsets, n_epochs, t, workspace, workspace_bytes, &v);
+  if (ps != ICRS_OK || n_epochs == 0) return ps;
+  char* base = (char*)workspace;
+  const icrs_config& c = h->cfg;
+  const int fp32_roots = c.root_precision == ICRS_FP32;
+  int32_t* cn = (int32_t*)(base + LL.cn);
+  double* a_c = (double*)(base + LL.a_c);
+  int32_t* ext = (int32_t*)(base + LL.lists);
+  int32_t* counts = (int32_t*)(base + LL.counts);
+  Timer tm(h);
+  ICRS_TRY(tm.begin());
+  ICRS_TRY(icrs::launch_centre_images(c.n_lens, fp32_roots, v.b, nullptr, cn, a_c, status, h->stream, v.roots));
+  ICRS_TRY(icrs::launch_fill_i32(counts, 1, 0, h->stream));
+  ICRS_TRY(icrs::launch_hybrid_select(c.n_lens, fp32_roots, hc->n_check, hc->guard, hc->tol, hc->vary_max, v.b, cn,
+                                      a_c, v.roots, mag, status, v.sec.nsec, ext, counts, h->stream));
+  ICRS_TRY(tm.end(&h->prof.ms_centre));
+  ICRS_TRY(tm.begin());
+  ICRS_TRY(icrs::launch_limb_sectors(c.n_lens, fp32_roots, c.n_limb, v.b, v.sec, status, h->stream, ext, n_epochs,
+                                     counts, v.roots, v.list_b, v.counters + 2));
+  ICRS_TRY(tm.end(&h->prof.ms_limb_sectors));
+  ICRS_TRY(tm.flush());
+  RaySet rs;
+  rs.list = ext;
+  rs.n = n_epochs;
+  rs.n_dev = counts;
+  return run_rays(h, v, c.max_retries, mag, status, 0u, rs);
+}
+
+icrs_status icrs_point_jacobian(icrs_handle* h, int64_t n_events, const double* params, const int64_t* epoch_offsets,
+                                int64_t n_epochs, const double* t, double* a_ps, double* jac, uint32_t* status,
+                                void* workspace, size_t workspace_bytes) {
+  if (!h || !events_ok(h->cfg, n_events, params, epoch_offsets, n_epochs)) return ICRS_EINVAL;
+  if (n_epochs > 0 && (!t || !jac)) return ICRS_EINVAL;
+  Views v;
+  const icrs_status ps = prepare(h, n_events, params, epoch_offsets, n_epochs, t, workspace, workspace_bytes, &v);
+  if (ps != ICRS_OK || n_epochs == 0) return ps;
+  return hip_status(icrs::launch_point_jacobian(h->cfg.n_lens, h->cfg.root_precision == ICRS_FP32, v.b, a_ps, jac,
+                                                status, nullptr, 0u, h->stream));
+}
+
+icrs_status icrs_hybrid_vjp(icrs_handle* h, int64_t n_events, const double* params, const int64_t* epoch_offsets,
+                            int64_t n_epochs, const double* t, const uint32_t* status, const double* sectors,
+                            const uint8_t* periodic, const int32_t* n_sectors, const double* cotangent, double* grad,
+                            double* jac, void* workspace, size_t workspace_bytes) {
+  if (!h || !events_ok(h->cfg, n_events, params, epoch_offsets, n_epochs)) return ICRS_EINVAL;
+  if (n_epochs > 0 && (!t || !status || !sectors || !periodic || !n_sectors)) return ICRS_EINVAL;
+  if ((grad && !cotangent) || (!grad && !jac)) return ICRS_EINVAL;
+  if (h->cfg.n_theta > 1024) return ICRS_EUNSUPPORTED;
+  Views v;
+  const icrs_status ps = prepare(h, n_events, params, epoch_offsets, n_epochs, t, workspace, workspace_bytes, &v);
+  if (ps != ICRS_OK || n_epochs == 0) return ps;
+  const size_t E = (size_t)n_epochs;
+  ICRS_TRY(hipMemcpyAsync(v.sec.sectors, sectors, E * ICRS_MAX_SECTORS * 4 * sizeof(double),
+                          hipMemcpyDeviceToDevice, h->stream));
+  ICRS_TRY(hipMemcpyAsync(v.sec.periodic, periodic, E * ICRS_MAX_SECTORS, hipMemcpyDeviceToDevice, h->stream));
+  ICRS_TRY(hipMemcpyAsync(v.sec.nsec, n_sectors, E * sizeof(int32_t), hipMemcpyDeviceToDevice, h->stream));
+  double* J = jac ? jac : v.jac;
+  // extended epochs on their frozen sectors (point epochs carry no sectors and get zero
+  // rows here), then the point epochs' rows through their images, then the contraction
+  ICRS_TRY(icrs::launch_adjoint(h->cfg.n_lens, v.b, v.sec, h->cfg.n_r, h->cfg.n_theta, h->cfg.delta_c, nullptr, J,
+                                nullptr, nullptr, (unsigned long long*)(v.counters + 12), h->stream));
+  ICRS_TRY(icrs::launch_point_jacobian(h->cfg.n_lens, h->cfg.root_precision == ICRS_FP32, v.b, nullptr, J, nullptr,
+                                       status, ICRS_ST_POINT, h->stream));
+  if (grad) ICRS_TRY(icrs::launch_contract(v.b, J, cotangent, grad, h->stream));
+  return ICRS_OK;
+}
+
+size_t icrs_marginal_nll_workspace_bytes(int64_t n_events) {
+  if (n_events < 0) return 0;
+  return align_up((size_t)(n_events + 1) * sizeof(int64_t)) + align_up((size_t)n_events * 4 * sizeof(double));
+}
+
+icrs_status icrs_marginal_nll(icrs_handle* h, int64_t n_events, const int64_t* epoch_offsets, int64_t n_epochs,
+                              const double* mag, const double* flux, const double* sigma, const double* prior,
+                              double* nll, double* beta, double* dnll_dmag, void* workspace,
+                              size_t workspace_bytes) {
+  if (!h || n_events < 0 || n_epochs < 0 || n_epochs > ICRS_MAX_EPOCHS || n_events > 0x7fffffffLL)
+    return ICRS_EINVAL;
+  if (n_events == 0) return n_epochs == 0 ? ICRS_OK : ICRS_EINVAL;
+  if (!epoch_offsets || !prior || !nll || !workspace) return ICRS_EINVAL;
+  if (n_epochs > 0 && (!mag || !flux || !sigma)) return ICRS_EINVAL;
+  if (epoch_offsets[0] != 0 || epoch_offsets[n_events] != n_epochs) return ICRS_EINVAL;
+  for (int64_t i = 0; i < n_events; ++i)
+    if (epoch_offsets[i + 1] < epoch_offsets[i]) return ICRS_EINVAL;
+  for (int64_t i = 0; i < n_events; ++i) {
+    const double* q = prior + 4 * i;
+    if (!finite_all(q, 4) || !(q[2] > 0.0) || !(q[3] > 0.0)) return ICRS_EINVAL;
+  }
+  if (((uintptr_t)workspace & (kAlign - 1)) != 0) return ICRS_EINVAL;
+  if (workspace_bytes < icrs_marginal_nll_workspace_bytes(n_events)) return ICRS_ENOMEM;
+  char* base = (char*)workspace;
+  int64_t* off = (int64_t*)base;
+  double* pr = (double*)(base + align_up((size_t)(n_events + 1) * sizeof(int64_t)));
+  ICRS_TRY(hipMemcpyAsync(off, epoch_offsets, (size_t)(n_events + 1) * sizeof(int64_t), hipMemcpyHostToDevice,
+                          h->stream));
+  ICRS_TRY(hipMemcpyAsync(pr, prior, (size_t)n_events * 4 * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  return hip_status(icrs::launch_nll(n_events, off, mag, flux, sigma, pr, nll, beta, dnll_dmag, h->stream));
 }
 
 const char* icrs_status_string(icrs_status s) {

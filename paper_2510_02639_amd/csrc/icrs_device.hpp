@@ -31,6 +31,7 @@ constexpr uint32_t kStLearned = 128u;
 constexpr uint32_t kStFallback = 256u;
 constexpr uint32_t kStImgRecheck = 512u;
 constexpr uint32_t kStBadSectors = 1024u;
+constexpr uint32_t kStPoint = 2048u;
 constexpr uint32_t kStRedo = 1u << 30;  // internal: the epoch's limb solves are redone cold in FP64
 
 // parameter vector layout: [s, q, u0, alpha, t0, tE, rho, u_ld, q3, r3, psi]
@@ -283,7 +284,7 @@ __device__ __forceinline__ void sincos_t(float a, float* s, float* c) { sincosf(
 
 template <typename T, int D>
 __device__ inline int ehrlich_aberth(const cx<T> (&b)[D + 1], cx<T> (&z)[D], int max_iter, bool* conv,
-                                     bool warm = false) {
+                                     bool warm = false, bool noise_stop = true) {
   T absb[D + 1];
 #pragma unroll
   for (int j = 0; j <= D; ++j) absb[j] = sqrt(norm2(b[j]));
@@ -322,7 +323,7 @@ __device__ inline int ehrlich_aberth(const cx<T> (&b)[D + 1], cx<T> (&z)[D], int
 #pragma unroll
       for (int j = D - 1; j >= 0; --j) noise = noise * az + absb[j];
       noise *= T(8 * D) * EAConst<T>::unit;
-      if (norm2(p) <= noise * noise) {
+      if (noise_stop && norm2(p) <= noise * noise) {
         done |= 1u << k;
         continue;
       }
@@ -465,6 +466,7 @@ __device__ inline uint32_t validate_roots(const Lens<N>& L, c64 w, const c64 (&z
 // receives the D polynomial roots.  Returns status bits.
 constexpr int kEAWarmIter = 50;
 constexpr int kEAMaxIterCold64 = 500;
+constexpr int kEAContinueIter = 100;
 
 template <int N, typename T, bool kCold64Retry = false>
 __device__ inline uint32_t find_images(const Lens<N>& L, c64 w, c64 (&img)[N * N + 1], int& n_img, int max_iter,
@@ -473,7 +475,7 @@ __device__ inline uint32_t find_images(const Lens<N>& L, c64 w, c64 (&img)[N * N
   c64 P[D + 1];
   lens_polynomial<N>(L, w, P);
   c64 zr[D];
-  bool conv = false;
+  bool conv = false, conv_warm = false;
   if (warm) {
 #pragma unroll
     for (int k = 0; k < D; ++k) zr[k] = warm[k];
@@ -486,6 +488,7 @@ __device__ inline uint32_t find_images(const Lens<N>& L, c64 w, c64 (&img)[N * N
 #pragma unroll
       for (int j = i + 1; j < D; ++j)
         if (norm2(zr[i] - zr[j]) <= 1e-24 * fmax(1.0, norm2(zr[i]))) conv = false;
+    conv_warm = conv;
   }
   if (!conv) {
     cx<T> b[D + 1];
@@ -505,11 +508,25 @@ __device__ inline uint32_t find_images(const Lens<N>& L, c64 w, c64 (&img)[N * N
     }
   }
   uint32_t st = validate_roots<N>(L, w, zr, img, n_img) | (conv ? 0u : kStRootNonconv);
+  bool fp64_cold = sizeof(T) == 8 && !(warm && conv_warm);
   if constexpr (kCold64Retry && sizeof(T) == 4) {
     if (!warm && (st & (kStImgCount | kStRootNonconv))) {
       bool conv64 = true;
       ehrlich_aberth<double, D>(P, zr, kEAMaxIterCold64, &conv64);
       st = validate_roots<N>(L, w, zr, img, n_img) | (conv64 ? 0u : kStRootNonconv);
+      fp64_cold = true;
+    }
+  }
+  if constexpr (sizeof(T) == 8 || kCold64Retry) {
+    // Two estimates that stopped on the rounding-noise test inside one root's neighbourhood
+    // (a tight cluster next to a low-mass lens) leave a root, and its image, unfound.  Last
+    // resort of a cold FP64 solve: continue the iteration from the current estimates with the
+    // step test only (the repulsion then separates the pair), at most 100 iterations, and
+    // validate again.
+    if (fp64_cold && (st & kStImgCount)) {
+      bool conv64 = true;
+      ehrlich_aberth<double, D>(P, zr, kEAContinueIter, &conv64, true, false);
+      st = validate_roots<N>(L, w, zr, img, n_img) | (st & kStRootNonconv);
     }
   }
   if (roots_out) {

@@ -87,7 +87,29 @@ hipError_t launch_learned_sectors(int n_lens, const Batch& b, const double* cimg
                                   int32_t* counts, int32_t* n_pruned, hipStream_t s);
 hipError_t launch_learned_gate(const Batch& b, const int32_t* learned, const int32_t* n_learned, int64_t n_max,
                                const double* a_c, const double* a_ring, const double* mag, uint32_t* status,
-                               double gate_rel, uint32_t* flags, int32_t* lists, int32_t* counts, hipStream_t s);
+                               double gate_rel, double gate_slack, uint32_t* flags, int32_t* lists,
+                               int32_t* counts, hipStream_t s);
+
+// hybrid light curve (icrs_hybrid.hip): epochs whose check circle shows no caustic and a
+// point-source magnification flat to tol get mag = A_ps and ICRS_ST_POINT; the others are
+// appended to ext_list (count in *ext_count, zeroed by the caller); nsec[e] = 0 for all.
+hipError_t launch_hybrid_select(int n_lens, int root_fp32, int n_check, double guard, double tol, double vary_max,
+                                const Batch& b, const int32_t* cn, const double* a_c, const double* roots,
+                                double* mag, uint32_t* status, int32_t* nsec, int32_t* ext_list, int32_t* ext_count,
+                                hipStream_t s);
+// A_ps and dA_ps/dparams [n_epochs][11] of every epoch (with only_status, only epochs whose
+// status_in has that bit); status_out (or null) gets the image-finding bits.
+hipError_t launch_point_jacobian(int n_lens, int root_fp32, const Batch& b, double* a_ps, double* jac,
+                                 uint32_t* status_out, const uint32_t* status_in, uint32_t only_status,
+                                 hipStream_t s);
+// grad[ev][k] = sum over the event's epochs of cot[e] jac[e][k] (fixed order)
+hipError_t launch_contract(const Batch& b, const double* jac, const double* cot, double* grad, hipStream_t s);
+
+// marginalised likelihood (icrs_likelihood.hip): per event NLL, posterior moments (or null)
+// and dNLL/dmag per epoch (or null); offsets and prior are device arrays
+hipError_t launch_nll(int64_t n_events, const int64_t* offsets, const double* mag, const double* flux,
+                      const double* sigma, const double* prior, double* nll, double* beta, double* dnll,
+                      hipStream_t s);
 
 namespace mlp {
 // learned-bounds network: FP32 master blob (param_floats()), packed bf16 weights

@@ -263,11 +263,14 @@ __global__ void learned_sectors_kernel(Batch b, const double* __restrict__ cimg,
 
 // Drift gate over the learned list: compare with A_c + w2 (A_ring - A_c), the source-size
 // estimate from the centre and the limb ring (w2 = <r~^2> of the limb-darkened profile,
-// (15 - 7u)/(10 (3 - u))); reject clipped results too.  Rejected epochs are appended to
+// (15 - 7u)/(10 (3 - u))), within gate_rel A_c plus gate_slack |A_ring - A_c| (the estimate's
+// own error grows with that difference; 0 holds every epoch to gate_rel); reject clipped
+// results too.  Rejected epochs are appended to
 // the fallback list.
 __global__ void learned_gate_kernel(Batch b, const int32_t* __restrict__ learned, const int32_t* __restrict__ n_learned,
                                     const double* __restrict__ a_c, const double* __restrict__ a_ring,
                                     const double* __restrict__ mag, uint32_t* __restrict__ status, double gate_rel,
+                                    double gate_slack,
                                     uint32_t* __restrict__ flags, int32_t* __restrict__ lists,
                                     int32_t* __restrict__ counts) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -280,7 +283,7 @@ __global__ void learned_gate_kernel(Batch b, const int32_t* __restrict__ learned
   const double est = a_c[e] + w2 * dA;
   uint32_t f = 0u;
   if (status[e] & kStClip) f |= kLfClip;
-  if (!(fabs(mag[e] - est) <= gate_rel * a_c[e] + fabs(dA))) f |= kLfGate;
+  if (!(fabs(mag[e] - est) <= gate_rel * a_c[e] + gate_slack * fabs(dA))) f |= kLfGate;
   if (f) {
     flags[e] |= f;
     status[e] &= ~(kStClip | kStNan | kStLearned);
@@ -341,10 +344,11 @@ hipError_t launch_learned_sectors(int n_lens, const Batch& b, const double* cimg
 
 hipError_t launch_learned_gate(const Batch& b, const int32_t* learned, const int32_t* n_learned, int64_t n_max,
                                const double* a_c, const double* a_ring, const double* mag, uint32_t* status,
-                               double gate_rel, uint32_t* flags, int32_t* lists, int32_t* counts, hipStream_t s) {
+                               double gate_rel, double gate_slack, uint32_t* flags, int32_t* lists,
+                               int32_t* counts, hipStream_t s) {
   if (n_max == 0) return hipSuccess;
   hipLaunchKernelGGL(learned_gate_kernel, dim3(blocks_for(n_max, 256)), dim3(256), 0, s, b, learned, n_learned, a_c,
-                     a_ring, mag, status, gate_rel, flags, lists, counts);
+                     a_ring, mag, status, gate_rel, gate_slack, flags, lists, counts);
   return hipGetLastError();
 }
 

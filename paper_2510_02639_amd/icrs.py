@@ -48,7 +48,8 @@ class icrs_profile(ctypes.Structure):
 class icrs_learned_config(ctypes.Structure):
     _fields_ = [("n_check", ctypes.c_int32), ("n_r", ctypes.c_int32), ("n_theta", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("log_safety", ctypes.c_double), ("prune_ratio", ctypes.c_double),
-                ("vary_max", ctypes.c_double), ("gate_rel", ctypes.c_double), ("margin_frac", ctypes.c_double)]
+                ("vary_max", ctypes.c_double), ("gate_rel", ctypes.c_double), ("margin_frac", ctypes.c_double),
+                ("gate_slack", ctypes.c_double)]
 
 
 class icrs_learned_stats(ctypes.Structure):
@@ -57,6 +58,11 @@ class icrs_learned_stats(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class icrs_hybrid_config(ctypes.Structure):
+    _fields_ = [("n_check", ctypes.c_int32), ("reserved", ctypes.c_int32), ("guard", ctypes.c_double),
+                ("tol", ctypes.c_double), ("vary_max", ctypes.c_double)]
 
 
 class icrs_config(ctypes.Structure):
@@ -123,6 +129,20 @@ def lib():
     L.icrs_run_learned.argtypes = [vp, vp, ctypes.POINTER(icrs_learned_config), vp, vp, vp, vp, vp,
                                    ctypes.POINTER(icrs_learned_stats), vp, sz]
     L.icrs_run_learned.restype = ctypes.c_int
+    L.icrs_default_hybrid_config.argtypes = [ctypes.POINTER(icrs_hybrid_config)]
+    L.icrs_hybrid_workspace_bytes.argtypes = [vp, i64, i64]
+    L.icrs_hybrid_workspace_bytes.restype = sz
+    L.icrs_magnification_hybrid.argtypes = [vp, i64, vp, vp, i64, vp, ctypes.POINTER(icrs_hybrid_config), vp, vp,
+                                            vp, sz]
+    L.icrs_magnification_hybrid.restype = ctypes.c_int
+    L.icrs_point_jacobian.argtypes = [vp, i64, vp, vp, i64, vp, vp, vp, vp, vp, sz]
+    L.icrs_point_jacobian.restype = ctypes.c_int
+    L.icrs_hybrid_vjp.argtypes = [vp, i64, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz]
+    L.icrs_hybrid_vjp.restype = ctypes.c_int
+    L.icrs_marginal_nll_workspace_bytes.argtypes = [i64]
+    L.icrs_marginal_nll_workspace_bytes.restype = sz
+    L.icrs_marginal_nll.argtypes = [vp, i64, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, sz]
+    L.icrs_marginal_nll.restype = ctypes.c_int
     L.icrs_status_string.argtypes = [ctypes.c_int]
     L.icrs_status_string.restype = ctypes.c_char_p
     _lib = L
@@ -136,8 +156,10 @@ EXPORTED = ["icrs_default_config", "icrs_create", "icrs_destroy", "icrs_workspac
             "icrs_get_profile", "icrs_mlp_pack", "icrs_mlp_forward", "icrs_mlp_workspace_bytes",
             "icrs_mlp_loss_grad", "icrs_mlp_adamw", "icrs_image_bounds", "icrs_default_learned_config",
             "icrs_learned_workspace_bytes", "icrs_magnification_learned", "icrs_run_learned",
+            "icrs_default_hybrid_config", "icrs_hybrid_workspace_bytes", "icrs_magnification_hybrid",
+            "icrs_point_jacobian", "icrs_hybrid_vjp", "icrs_marginal_nll_workspace_bytes", "icrs_marginal_nll",
             "icrs_status_string"]
-ST_LEARNED, ST_FALLBACK, ST_IMG_RECHECK, ST_BAD_SECTORS = 128, 256, 512, 1024
+ST_LEARNED, ST_FALLBACK, ST_IMG_RECHECK, ST_BAD_SECTORS, ST_POINT = 128, 256, 512, 1024, 2048
 ICRS_MAX_EPOCHS = 1 << 27
 MLP_PARAM_FLOATS, MLP_PACKED_HALFS, MLP_NORM_FLOATS = 39312, 75776, 32
 
@@ -282,6 +304,78 @@ class Handle:
         _check(code, "icrs_magnification_vjp")
         return grad, J, M
 
+    # ---- hybrid light curve (Sec. 3.4 item iii) and point-source gradient ------------------
+    def hybrid_workspace(self, n_events, n_epochs):
+        n = lib().icrs_hybrid_workspace_bytes(self._h, n_events, n_epochs)
+        return torch.empty(max(n, 256), dtype=torch.uint8, device="cuda")
+
+    def magnification_hybrid(self, params, offsets, t, mag=None, status=None, workspace=None, n_check=16, guard=2.0,
+                             tol=1e-4, vary_max=0.1):
+        """Hybrid light curve: the plain path on the epochs the selection rule marks, the
+        point-source magnification (status ST_POINT) elsewhere.  Returns (mag, status)."""
+        p, o = _host_events(params, offsets)
+        t = _dev(t, torch.float64)
+        n = t.numel()
+        hc = icrs_hybrid_config()
+        lib().icrs_default_hybrid_config(ctypes.byref(hc))
+        hc.n_check, hc.guard, hc.tol, hc.vary_max = n_check, guard, tol, vary_max
+        mag = torch.empty(n, dtype=torch.float64, device=t.device) if mag is None else mag
+        status = torch.empty(n, dtype=torch.int32, device=t.device) if status is None else status
+        ws = workspace if workspace is not None else self.hybrid_workspace(p.shape[0], n)
+        self._hyb_ws = ws
+        _check(lib().icrs_magnification_hybrid(self._h, p.shape[0], _ptr(p), _ptr(o), n, _ptr(t), ctypes.byref(hc),
+                                               _ptr(mag), _ptr(status), _ptr(ws), ws.numel()),
+               "icrs_magnification_hybrid")
+        return mag, status
+
+    def point_jacobian(self, params, offsets, t, workspace=None):
+        """(a_ps [E], jac [E, 11], status [E]) of every epoch's source centre, CUDA."""
+        p, o = _host_events(params, offsets)
+        t = _dev(t, torch.float64)
+        n = t.numel()
+        a = torch.empty(n, dtype=torch.float64, device=t.device)
+        J = torch.empty((n, ICRS_N_PARAMS), dtype=torch.float64, device=t.device)
+        st = torch.empty(n, dtype=torch.int32, device=t.device)
+        ws = workspace if workspace is not None else self.workspace(p.shape[0], n)
+        _check(lib().icrs_point_jacobian(self._h, p.shape[0], _ptr(p), _ptr(o), n, _ptr(t), _ptr(a), _ptr(J),
+                                         _ptr(st), _ptr(ws), ws.numel()), "icrs_point_jacobian")
+        return a, J, st
+
+    def hybrid_vjp(self, params, offsets, t, status, sectors, periodic, nsec, cotangent=None, jac=False,
+                   workspace=None):
+        """Reverse mode of the hybrid curve: (grad [V, 11] or None, jac [E, 11] or None)."""
+        p, o = _host_events(params, offsets)
+        t = _dev(t, torch.float64)
+        n = t.numel()
+        grad = None
+        if cotangent is not None:
+            cotangent = _dev(cotangent, torch.float64)
+            grad = torch.empty((p.shape[0], ICRS_N_PARAMS), dtype=torch.float64, device=t.device)
+        J = torch.empty((n, ICRS_N_PARAMS), dtype=torch.float64, device=t.device) if jac else None
+        ws = workspace if workspace is not None else self.workspace(p.shape[0], n)
+        _check(lib().icrs_hybrid_vjp(self._h, p.shape[0], _ptr(p), _ptr(o), n, _ptr(t), _ptr(_dev(status, torch.int32)),
+                                     _ptr(_dev(sectors, torch.float64)), _ptr(_dev(periodic, torch.uint8)),
+                                     _ptr(_dev(nsec, torch.int32)), _ptr(cotangent), _ptr(grad), _ptr(J), _ptr(ws),
+                                     ws.numel()), "icrs_hybrid_vjp")
+        return grad, J
+
+    # ---- marginalised likelihood (App. B) --------------------------------------------------
+    def marginal_nll(self, offsets, mag, flux, sigma, prior, beta=False, grad=True):
+        """eq. NLL per event; returns (nll [V], beta [V, 5] or None, dnll/dmag [E] or None)."""
+        o = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64).reshape(-1))
+        pr = np.ascontiguousarray(np.asarray(prior, dtype=np.float64).reshape(-1, 4))
+        mag = _dev(mag, torch.float64)
+        n_ev = o.size - 1
+        nll = torch.empty(n_ev, dtype=torch.float64, device=mag.device)
+        b = torch.empty((n_ev, 5), dtype=torch.float64, device=mag.device) if beta else None
+        g = torch.empty(mag.numel(), dtype=torch.float64, device=mag.device) if grad else None
+        nb = lib().icrs_marginal_nll_workspace_bytes(n_ev)
+        ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=mag.device)
+        _check(lib().icrs_marginal_nll(self._h, n_ev, _ptr(o), mag.numel(), _ptr(mag), _ptr(_dev(flux, torch.float64)),
+                                       _ptr(_dev(sigma, torch.float64)), _ptr(pr), _ptr(nll), _ptr(b), _ptr(g),
+                                       _ptr(ws), ws.numel()), "icrs_marginal_nll")
+        return nll, b, g
+
     # ---- learned-bounds path ----------------------------------------------------------------
     def learned_workspace(self, n_events, n_epochs):
         n = lib().icrs_learned_workspace_bytes(self._h, n_events, n_epochs)
@@ -305,14 +399,15 @@ class Handle:
 
     def magnification_learned(self, params, offsets, t, model, mag=None, status=None, workspace=None,
                               n_check=16, n_r=None, n_theta=None, prune_ratio=1e-6, vary_max=0.1, gate_rel=1e-3,
-                              margin_frac=0.02, stats=True):
+                              margin_frac=0.02, stats=True, gate_slack=0.0):
         """Learned-bounds path; model: a learned.BoundsModel.  Returns (mag, status, stats dict);
         with stats=False the call enqueues device work only (no host wait, capturable) and the
         dict is None."""
         p, o = _host_events(params, offsets)
         t = _dev(t, torch.float64)
         n = t.numel()
-        lc = self._learned_config(model, n_check, n_r, n_theta, prune_ratio, vary_max, gate_rel, margin_frac)
+        lc = self._learned_config(model, n_check, n_r, n_theta, prune_ratio, vary_max, gate_rel, margin_frac,
+                                  gate_slack)
         mag = mag if mag is not None else torch.empty(n, dtype=torch.float64, device=t.device)
         status = status if status is not None else torch.empty(n, dtype=torch.int32, device=t.device)
         ws = workspace if workspace is not None else self.learned_workspace(p.shape[0], n)
@@ -325,7 +420,7 @@ class Handle:
         return mag, status, (st.as_dict() if stats else None)
 
     def _learned_config(self, model, n_check=16, n_r=None, n_theta=None, prune_ratio=1e-6, vary_max=0.1,
-                        gate_rel=1e-3, margin_frac=0.02):
+                        gate_rel=1e-3, margin_frac=0.02, gate_slack=0.0):
         lc = icrs_learned_config()
         lib().icrs_default_learned_config(ctypes.byref(lc))
         lc.n_check = n_check
@@ -334,6 +429,7 @@ class Handle:
         lc.log_safety = model.log_safety
         lc.prune_ratio, lc.vary_max, lc.gate_rel = prune_ratio, vary_max, gate_rel
         lc.margin_frac = margin_frac
+        lc.gate_slack = gate_slack
         return lc
 
     def run_learned(self, t, model, mag, status, stats=False, **kw):
@@ -428,3 +524,46 @@ class ICRSFunction(torch.autograd.Function):
         grad, _, _ = ctx.handle.magnification_vjp(params.detach().cpu().numpy(), ctx.offsets, ctx.t, sec, per, ns,
                                                   cotangent=grad_mag.contiguous().to(torch.float64))
         return grad.to(params.device), None, None, None
+
+
+class HybridFunction(torch.autograd.Function):
+    """mag = HybridFunction.apply(params, handle, offsets, t): hybrid light curves (the full
+    method on the selected epochs, the point-source magnification elsewhere) with a
+    reverse-mode gradient for params (CPU float64 [n_events, 11]): point epochs through their
+    images, the others on the forward's frozen sectors."""
+
+    @staticmethod
+    def forward(ctx, params, handle, offsets, t):
+        p = params.detach().cpu().numpy()
+        mag, status = handle.magnification_hybrid(p, offsets, t)
+        ctx.frozen = handle.get_sectors(t.numel(), handle._hyb_ws)
+        ctx.handle, ctx.offsets, ctx.t, ctx.status = handle, offsets, t, status
+        ctx.save_for_backward(params)
+        return mag
+
+    @staticmethod
+    def backward(ctx, grad_mag):
+        (params,) = ctx.saved_tensors
+        sec, per, ns = ctx.frozen
+        grad, _ = ctx.handle.hybrid_vjp(params.detach().cpu().numpy(), ctx.offsets, ctx.t, ctx.status, sec, per, ns,
+                                        cotangent=grad_mag.contiguous().to(torch.float64))
+        return grad.to(params.device), None, None, None
+
+
+def light_curve_nll_and_grad(handle, params, offsets, t, flux, sigma, prior, hybrid=False):
+    """Fit objective of App. B: total eq. NLL over the events and its gradient with respect
+    to the event parameters [V, 11] (dNLL/dmag from the likelihood kernel, contracted by the
+    frozen-structure reverse mode of the plain or hybrid path).  Returns (nll [V], grad)."""
+    p, o = _host_events(params, offsets)
+    if hybrid:
+        mag, status = handle.magnification_hybrid(p, o, t)
+        sec, per, ns = handle.get_sectors(t.numel(), handle._hyb_ws)
+    else:
+        mag, status = handle.magnification(p, o, t)
+        sec, per, ns = handle.get_sectors(t.numel())
+    nll, _, g = handle.marginal_nll(o, mag, flux, sigma, prior)
+    if hybrid:
+        grad, _ = handle.hybrid_vjp(p, o, t, status, sec, per, ns, cotangent=g)
+    else:
+        grad, _, _ = handle.magnification_vjp(p, o, t, sec, per, ns, cotangent=g)
+    return nll, grad

@@ -69,7 +69,8 @@ def _struct_fields(name):
     return out
 
 
-@pytest.mark.parametrize("name", ["icrs_config", "icrs_profile", "icrs_learned_config", "icrs_learned_stats"])
+@pytest.mark.parametrize("name", ["icrs_config", "icrs_profile", "icrs_learned_config", "icrs_learned_stats",
+                                  "icrs_hybrid_config"])
 def test_binding_structs_match_header(name):
     """The ctypes mirrors of the ABI structs list the header's fields in order, with the same
     widths, so the library and the binding agree on every offset."""
