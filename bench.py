@@ -4,22 +4,28 @@
 Workload: 2048 binary planetary-regime events (log10 q in [-5,-2], s in [0.5,2], u0 in
 [0,0.3], linear limb darkening u in [0.3,0.7]) with rho = 1e-3 and 100..5000 epochs each,
 clustered within +-3 rho tE of caustic crossings (about 5.1 million epochs); 128 limb points,
-128 x 512 polar grids, FP32 ray loop, FP32 Ehrlich-Aberth with FP64 polish.  One step is one
-full pass of the path over the whole batch with inputs resident in HBM.  Two paths are
-timed on the same batch:
-  * batched+learned (the headline `value`): centre images, 16 check points per epoch, the
-    bounds network on the matrix cores, per-image boxes, rays, drift gate, and the plain
-    path for every epoch the checks hand back -- all inside the step.  Its grid is the
-    autotuner's choice (untimed, on a 1% calibration subset): the smallest grid whose
-    error is no worse than the plain path's at 128 x 512, in median and 99th percentile
-    (grid and drift-gate tolerance tuned together);
-  * plain: centre images, 128 limb points, sectors, rays, clip retries.
+FP32 ray loop, FP32 Ehrlich-Aberth with FP64 polish.  One step is one full pass of the path
+over the whole batch with inputs resident in HBM.  Grids come from the autotuner, untimed,
+on a 1% calibration subset of the same batch:
+  * plain grid: the smallest grid whose median error is within 3e-5 of the same path
+    converged (FP64, 512 x 1024, epochs whose reference passes a Richardson check);
+  * learned grid and drift gate: the fastest pair whose error is no worse than the plain
+    path's at the plain grid, in median and 99th percentile.
+Lines:
+  * batched+learned (the headline `value`): the batch uploaded once (icrs_prepare), each step
+    one replay of a captured HIP graph of the learned path (centre images, 16 check points,
+    the bounds network on the matrix cores, per-image boxes, rays, drift gate, and the plain
+    path for every epoch the checks hand back -- list sizes stay on the device);
+  * plain: one eager icrs_magnification call per step over the batch (profiled: the main ray
+    pass is one launch per step); batched+plain: the same path as a graph replay;
+    plain_per_event: one call per event on the first 128 events.
 
-Printed: one JSON line with both throughputs, the ray kernel's roofline position (its main
-pass timed live with HIP events on the library's stream, plain path: one launch per step),
-the oracle's CPU throughput on a sample of the same epochs, and, on that sample, each
-path's agreement with the oracle and its error against the oracle's grid-free source-disk
-quadrature (the exact finite-source magnification where no caustic crosses the disk).
+Printed: one JSON line with the throughputs, the dominant kernel's roofline position (timed
+live with HIP events on the library's stream), the oracle's CPU throughput on a sample of the
+same epochs, and, on that sample, each path's agreement with the oracle and its error
+against the oracle's grid-free source-disk quadrature (the exact finite-source magnification
+where no caustic crosses the disk), with the 1e-4 accuracy bar stated as met or not; and the
+learned path against the plain path on every epoch.
 """
 from __future__ import annotations
 
@@ -89,7 +95,7 @@ def cpu_baseline(w, mags, budget_s, seed=0):
         err = np.abs(g[idx][good] / ref[good] - 1.0)
         acc[name] = {"vs_oracle_max": float(rel.max()), "vs_oracle_median": float(np.median(rel)),
                      "vs_disk_median": float(np.median(err)), "vs_disk_p99": float(np.quantile(err, 0.99)),
-                     "vs_disk_frac_le_1e-4": float(np.mean(err <= 1e-4))}
+                     "vs_disk_max": float(err.max()), "vs_disk_frac_le_1e-4": float(np.mean(err <= 1e-4))}
     return {
         "value": idx.size / dt, "unit": "epochs/s", "cores": O.num_threads(), "kind": "oracle",
         "sample": f"{idx.size} epochs drawn uniformly (seed {seed}) from the same workload, FP64 oracle "
@@ -101,7 +107,7 @@ PLAIN_LADDER = [(128, 512), (256, 512), (256, 1024), (512, 1024)]
 LEARNED_LADDER = [(64, 256), (128, 512), (256, 512), (256, 1024)]
 
 
-def accuracy_sweep(w, model, gate_rel, idx, ref, every=10):
+def accuracy_sweep(w, model, gate_rel, idx, ref, every=10, gate_slack=0.0):
     """Throughput against true accuracy: each path on a ladder of grids, its error against the
     grid-free disk quadrature on the sampled epochs, and its rate on every `every`-th epoch of
     the workload (inputs resident, one warm-up call, then one timed call).  The learned rungs
@@ -143,10 +149,11 @@ def accuracy_sweep(w, model, gate_rel, idx, ref, every=10):
                 r = rate(lambda: hg.magnification(sub.params, sub.offsets, t_sub, workspace=ws))
             else:
                 m = hg.magnification_learned(one.params, one.offsets, t_one, model, n_r=n_r, n_theta=n_theta,
-                                             gate_rel=gate_rel)[0].cpu().numpy()
+                                             gate_rel=gate_rel, gate_slack=gate_slack)[0].cpu().numpy()
                 ws = hg.learned_workspace(sub.n_events, sub.n_epochs)
                 r = rate(lambda: hg.magnification_learned(sub.params, sub.offsets, t_sub, model, workspace=ws,
-                                                          n_r=n_r, n_theta=n_theta, gate_rel=gate_rel))
+                                                          n_r=n_r, n_theta=n_theta, gate_rel=gate_rel,
+                                                          gate_slack=gate_slack, stats=False))
             rows.append({"grid": [n_r, n_theta], "epochs_per_s": r, **stats(m)})
             print(f"[bench] sweep {name} {n_r}x{n_theta}: {r:.3g} epochs/s, median err {rows[-1]['median']:.2e}",
                   file=sys.stderr, flush=True)
@@ -177,6 +184,51 @@ def timed_steps(fn, steps, warmup, label, after_warmup=None):
     return out, time.perf_counter() - t0
 
 
+def timed_graph(capture, steps, warmup, label, stream):
+    """Capture one step into a HIP graph on stream (the handle's; after one eager warm-up of
+    capture()), then replay: warmup untimed replays, steps timed replays bracketed by device
+    synchronisation."""
+    import torch
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        capture()
+    stream.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        capture()
+    for k in range(warmup):
+        g.replay()
+        torch.cuda.synchronize()
+        print(f"[bench] {label}: warmup replay {k + 1}/{warmup} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        g.replay()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(f"[bench] {label}: {steps} replays in {dt:.3f} s", file=sys.stderr, flush=True)
+    return dt
+
+
+def per_event_plain(h, w, t, n_events=128):
+    """The plain path launched event by event (one call per event, no batching across
+    events), on the first n_events events; epochs/s."""
+    import torch
+    sub = w.subset(range(min(n_events, w.n_events)))
+    ts = torch.tensor(sub.t, device="cuda")
+    ws = h.workspace(1, int(np.max(np.diff(sub.offsets))))
+    calls = [(sub.params[i:i + 1], np.array([0, sub.offsets[i + 1] - sub.offsets[i]], np.int64),
+              ts[sub.offsets[i]:sub.offsets[i + 1]]) for i in range(sub.n_events)]
+    for p, o, tt in calls[:4]:
+        h.magnification(p, o, tt, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p, o, tt in calls:
+        h.magnification(p, o, tt, workspace=ws)
+    torch.cuda.synchronize()
+    return sub.n_epochs / (time.perf_counter() - t0), sub.n_events
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -189,6 +241,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the accuracy/throughput sweep over grids")
     ap.add_argument("--plain-only", action="store_true", help="time the plain path only (profiling runs)")
+    ap.add_argument("--learned-only", action="store_true", help="time the batched+learned path only (profiling runs)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -207,60 +260,95 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_each_way": src.numel() * 4, "launches": 3}), flush=True)
         return
-    from paper_2510_02639_amd import icrs, learned, workloads
+    from paper_2510_02639_amd import autotune, icrs, learned, workloads
 
     t_gen = time.perf_counter()
     w = workloads.metric_workload(args.events)
     print(f"[bench] workload {w.name}: {w.n_events} events, {w.n_epochs} epochs "
           f"(generated in {time.perf_counter() - t_gen:.1f} s)", file=sys.stderr, flush=True)
-    h = icrs.Handle(n_lens=2, n_limb=w.n_limb, n_r=w.n_r, n_theta=w.n_theta, ray_precision=args.rays,
-                    root_precision=args.roots)
     t = torch.tensor(w.t, device="cuda")
     mag = torch.empty(w.n_epochs, dtype=torch.float64, device="cuda")
     status = torch.empty(w.n_epochs, dtype=torch.int32, device="cuda")
+
+    # plain grid: the autotuner's smallest grid whose median error on a 1% calibration subset
+    # is within 3e-5 of the same path converged (FP64, 512 x 1024, Richardson-trusted epochs)
+    t_tune = time.perf_counter()
+    ptune = autotune.tune(w, tol=3e-5, every=100, stat="median", roots=args.roots)
+    t_tune = time.perf_counter() - t_tune
+    grid = (ptune.n_r, ptune.n_theta)
+    print(f"[bench] plain grid {grid[0]} x {grid[1]} (tuned in {t_tune:.1f} s)", file=sys.stderr, flush=True)
+    hs = torch.cuda.Stream()   # the library's stream: eager calls and graph capture
+    h = icrs.Handle(n_lens=2, n_limb=w.n_limb, n_r=grid[0], n_theta=grid[1], ray_precision=args.rays,
+                    root_precision=args.roots, stream=hs)
     ws = h.learned_workspace(w.n_events, w.n_epochs)
 
-    # plain path, profiled after the warm-up: the main ray pass is one launch per step
+    # plain path, one eager call per step over the whole batch, profiled after the warm-up
     def start_profile():
         h.set_profiling(True)
         h.get_profile(reset=True)
 
-    _, dt_plain = timed_steps(lambda: h.magnification(w.params, w.offsets, t, mag, status, ws), args.steps,
-                              args.warmup, "plain", start_profile)
-    prof = h.get_profile()
-    h.set_profiling(False)
-    gm_plain = mag.cpu().numpy()
-    st = status.cpu().numpy().astype(np.uint32)
-    plain_value = w.n_epochs * args.steps / dt_plain
-
     line = {"metric": METRIC}
+    plain = {}
+    if not args.learned_only:
+        _, dt_plain = timed_steps(lambda: h.magnification(w.params, w.offsets, t, mag, status, ws), args.steps,
+                                  args.warmup, "plain", start_profile)
+        prof = h.get_profile()
+        h.set_profiling(False)
+        gm_plain = mag.cpu().numpy()
+        st = status.cpu().numpy().astype(np.uint32)
+        plain_value = w.n_epochs * args.steps / dt_plain
+        # batched+plain: the same path prepared once and replayed as one captured graph
+        h.prepare(w.params, w.offsets, w.n_epochs, workspace=ws)
+        dt_bp = timed_graph(lambda: h.run(t, mag, status), args.steps, args.warmup, "batched+plain", hs)
+        bp_equal = bool(np.array_equal(mag.cpu().numpy(), gm_plain))
+        pe_rate, pe_events = per_event_plain(h, w, t)
+        plain = {"value": plain_value, "ms_per_step": dt_plain * 1e3 / args.steps, "grid": list(grid),
+                 "rays_per_s": prof["n_sector_passes"] * grid[0] * grid[1] / dt_plain,
+                 "breakdown_ms_per_step": {k: prof[k] / args.steps for k in
+                                           ("ms_centre", "ms_limb_sectors", "ms_rays", "ms_rays_main",
+                                            "ms_finalize")},
+                 "sectors_per_epoch": prof["n_sector_passes"] / max(prof["n_epochs"], 1),
+                 "status_counts": {name: int(np.sum((st & bit) != 0)) for name, bit in
+                                   [("root_nonconv", 1), ("img_count", 2), ("cap_overflow", 4), ("clip", 8),
+                                    ("nan", 16)]},
+                 "autotune": {"target": "median rel err <= 3e-5 vs FP64 512x1024 (converged, Richardson-trusted)",
+                              "calibration_epochs": ptune.n_calibration, "trusted": ptune.n_trusted,
+                              "tried": ptune.errors, "seconds": t_tune}}
+        line["batched+plain"] = {"value": w.n_epochs * args.steps / dt_bp, "ms_per_step": dt_bp * 1e3 / args.steps,
+                                 "graph": True, "bitwise_equal_to_eager": bp_equal}
+        line["plain_per_event"] = {"value": pe_rate, "events_timed": pe_events,
+                                   "launch": "one icrs_magnification call per event"}
+
+    value, dt_value = (plain.get("value"), None)
     if not args.plain_only:
-        from paper_2510_02639_amd import autotune
         model = learned.BoundsModel.load()
-        # learned grid: the autotuner's choice on a 1% calibration subset (untimed)
-        t_tune = time.perf_counter()
-        tune = autotune.tune_learned(w, model, plain_grid=(w.n_r, w.n_theta), every=100)
-        t_tune = time.perf_counter() - t_tune
-        print(f"[bench] learned grid {tune.n_r} x {tune.n_theta}, gate {tune.gate_rel:g} (tuned in {t_tune:.1f} s)",
+        # learned grid and gate: the autotuner's fastest pair whose error on the calibration
+        # subset is no worse than the plain path's at the plain grid (median and p99)
+        t_lt = time.perf_counter()
+        tune = autotune.tune_learned(w, model, plain_grid=grid, every=100)
+        t_lt = time.perf_counter() - t_lt
+        print(f"[bench] learned grid {tune.n_r} x {tune.n_theta}, gate {tune.gate_rel:g}/{tune.gate_slack:g} "
+              f"(tuned in {t_lt:.1f} s)",
               file=sys.stderr, flush=True)
+        kw = dict(n_r=tune.n_r, n_theta=tune.n_theta, gate_rel=tune.gate_rel, gate_slack=tune.gate_slack)
         mag_l = torch.empty_like(mag)
         status_l = torch.empty_like(status)
-        (_, _, lstats), dt_learned = timed_steps(
-            lambda: h.magnification_learned(w.params, w.offsets, t, model, mag_l, status_l, ws, n_r=tune.n_r,
-                                            n_theta=tune.n_theta, gate_rel=tune.gate_rel), args.steps, args.warmup,
-            "batched+learned")
+        # batched+learned (the headline): prepared once, one captured graph per step
+        h.prepare(w.params, w.offsets, w.n_epochs, workspace=ws)
+        dt_learned = timed_graph(lambda: h.run_learned(t, model, mag_l, status_l, **kw), args.steps, args.warmup,
+                                 "batched+learned", hs)
         gm_learned = mag_l.cpu().numpy()
         value, dt_value = w.n_epochs * args.steps / dt_learned, dt_learned
-        # one more (untimed) learned step, profiled: the learned boxes' main ray pass
+        # statistics and the profiled learned main pass, from one more (eager, untimed) step
         h.set_profiling(True)
         h.get_profile(reset=True)
-        h.magnification_learned(w.params, w.offsets, t, model, mag_l, status_l, ws, n_r=tune.n_r,
-                                n_theta=tune.n_theta, gate_rel=tune.gate_rel)
+        _, _, lstats = h.magnification_learned(w.params, w.offsets, t, model, mag_l, status_l, ws, **kw)
         torch.cuda.synchronize()
         lprof = h.get_profile()
         h.set_profiling(False)
+        eager_equal = bool(np.array_equal(mag_l.cpu().numpy(), gm_learned))
     else:
-        value, dt_value = plain_value, dt_plain
+        dt_value = plain["ms_per_step"] * args.steps / 1e3
 
     peak = PEAK_TFLOPS[args.rays]
 
@@ -271,50 +359,62 @@ def main():
                 "flops_per_ray": FLOPS_PER_RAY[2], "rays_per_launch_avg": n_rays / max(n_launch, 1),
                 "kernel_ms_per_launch_avg": ms / max(n_launch, 1), "path_timed": timed}
 
-    roof_plain = roofline(prof["n_main_rays"], prof["ms_rays_main"], prof["n_main_launches"], w.n_theta, "plain",
-                          "plain (one main-pass launch per step)")
+    if plain:
+        plain["roofline"] = roofline(prof["n_main_rays"], prof["ms_rays_main"], prof["n_main_launches"], grid[1],
+                                     "plain", "plain (one main-pass launch per step)")
     line.update({
         "value": value, "unit": "epochs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": dt_value * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32" if args.rays == "fp32" else "f64", "data": "synthetic",
         "config": {"workload": w.name, "n_events": w.n_events, "n_epochs": w.n_epochs, "n_limb": w.n_limb,
-                   "grid": [w.n_r, w.n_theta], "ray_precision": args.rays,
+                   "plain_grid": list(grid), "ray_precision": args.rays,
                    "root_precision": "fp32+fp64-polish" if args.roots == "fp32" else "fp64",
                    "path": "plain" if args.plain_only else "batched+learned", "rho": 1e-3,
-                   "learned_grid": None if args.plain_only else [tune.n_r, tune.n_theta]},
-        "plain": {"value": plain_value, "ms_per_step": dt_plain * 1e3 / args.steps,
-                  "rays_per_s": prof["n_sector_passes"] * w.n_r * w.n_theta / dt_plain,
-                  "breakdown_ms_per_step": {k: prof[k] / args.steps for k in
-                                            ("ms_centre", "ms_limb_sectors", "ms_rays", "ms_rays_main",
-                                             "ms_finalize")},
-                  "sectors_per_epoch": prof["n_sector_passes"] / max(prof["n_epochs"], 1),
-                  "status_counts": {name: int(np.sum((st & bit) != 0)) for name, bit in
-                                    [("root_nonconv", 1), ("img_count", 2), ("cap_overflow", 4), ("clip", 8),
-                                     ("nan", 16)]},
-                  "roofline": roof_plain},
+                   "learned_grid": None if args.plain_only else [tune.n_r, tune.n_theta],
+                   "graph": not args.plain_only},
     })
+    if plain:
+        line["plain"] = plain
     # the dominant kernel of the timed step: the learned boxes' main ray pass (the plain
     # path's main pass when only that path runs)
-    line["roofline"] = roof_plain if args.plain_only else roofline(
+    line["roofline"] = plain["roofline"] if args.plain_only else roofline(
         lprof["n_learned_rays"], lprof["ms_rays_learned"], lprof["n_learned_launches"], tune.n_theta, "learned",
         "batched+learned (the learned boxes' main ray pass, one launch per step; profiled on one extra step)")
     if not args.plain_only:
         line["learned"] = {"stats_per_step": lstats, "model": "paper_2510_02639_amd/data/bounds_mlp.npz",
                            "log_safety": model.log_safety, "grid": [tune.n_r, tune.n_theta],
-                           "gate_rel": tune.gate_rel,
+                           "gate_rel": tune.gate_rel, "gate_slack": tune.gate_slack,
+                           "graph_equal_to_eager": eager_equal,
                            "autotune": {"plain_error_median_p99": tune.plain_error, "tried": tune.errors,
                                         "calibration_epochs": tune.n_calibration, "rates": tune.rates,
-                                        "seconds": t_tune}}
+                                        "seconds": t_lt}}
+        if plain:
+            d = np.abs(gm_learned / gm_plain - 1.0)
+            line["learned"]["vs_plain_all_epochs"] = {
+                "max": float(d.max()), "median": float(np.median(d)), "p99": float(np.quantile(d, 0.99)),
+                "frac_above_1e-4": float(np.mean(d > 1e-4)), "plain_grid": list(grid),
+                "learned_grid": [tune.n_r, tune.n_theta]}
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
-        mags = {"plain": gm_plain}
+        mags = {}
+        if plain:
+            mags["plain"] = gm_plain
         if not args.plain_only:
             mags["batched+learned"] = gm_learned
-        base, acc, (s_idx, s_ref) = cpu_baseline(w, mags, args.cpu_seconds)
+        wb = workloads.Workload(w.name, w.n_lens, w.params, w.offsets, w.t, w.n_limb, grid[0], grid[1], w.ray_precision,
+                                w.root_precision)
+        base, acc, (s_idx, s_ref) = cpu_baseline(wb, mags, args.cpu_seconds)
         line["cpu_baseline"] = base
         line["accuracy"] = acc
-        if not args.plain_only and not args.no_sweep:
-            line["accuracy_sweep"] = accuracy_sweep(w, model, tune.gate_rel, s_idx, s_ref)
+        hl = acc.get("batched+learned")
+        if hl:
+            line["accuracy_bar"] = {
+                "target_rel_err": 1e-4, "reference": "grid-free source-disk quadrature (oracle), sampled epochs",
+                "headline_median": hl["vs_disk_median"], "headline_p99": hl["vs_disk_p99"],
+                "headline_max": hl["vs_disk_max"], "frac_le_1e-4": hl["vs_disk_frac_le_1e-4"],
+                "met_by_median": hl["vs_disk_median"] <= 1e-4, "met_by_every_epoch": hl["vs_disk_max"] <= 1e-4}
+        if not args.plain_only and not args.no_sweep and plain:
+            line["accuracy_sweep"] = accuracy_sweep(w, model, tune.gate_rel, s_idx, s_ref, gate_slack=tune.gate_slack)
     print(json.dumps(line), flush=True)
 
 

@@ -5,9 +5,16 @@
             forward and of the VJP, and the VJP's ray rate;
   triple    the triple-lens workload (256 events x 2000 epochs, FP64 roots, FP32 rays);
   train     device training of the bounds network: rows/s of loss+gradient+AdamW steps;
-  serve     the serving loop at 200 events/s for a few seconds (p50/p99 latency).
+  serve     the serving loop at 200 events/s for a few seconds (p50/p99 latency);
+  hybrid    the hybrid light curve (Sec. 3.4, item iii) on a survey cadence (512 events x 8640
+            epochs, 72 d at 12 min): the selected fraction, epochs/s of the hybrid curve and of
+            the plain path on every epoch of the same batch;
+  nll       the fit objective of App. B (marginalised NLL and its gradient through the
+            reverse mode) on the cadence batch with the hybrid curve;
+  fig2      the triple-lens gradient example of Fig. 2 (1000 epochs, 500 x 500, FP64):
+            forward and Jacobian time.
 
-    python -m paper_2510_02639_amd.perf [adjoint triple train serve]
+    python -m paper_2510_02639_amd.perf [adjoint triple train serve hybrid nll fig2]
 
 Inputs are resident in HBM before each timed region; times are wall-clock around
 synchronised device work.
@@ -98,9 +105,61 @@ def serving(seconds=6.0):
     return {"measure": "serve", "rate_events_per_s": 200.0, "seconds": seconds, **out}
 
 
+def hybrid(n_events=512):
+    w = workloads.cadence_workload(n_events)
+    h = icrs.Handle(n_lens=2, n_limb=128, n_r=128, n_theta=512, ray_precision="fp32", root_precision="fp32")
+    t = torch.tensor(w.t, device="cuda")
+    ws = h.hybrid_workspace(w.n_events, w.n_epochs)
+    mag = torch.empty(w.n_epochs, dtype=torch.float64, device="cuda")
+    st = torch.empty(w.n_epochs, dtype=torch.int32, device="cuda")
+    _, dt_h = _timed(lambda: h.magnification_hybrid(w.params, w.offsets, t, mag, st, ws))
+    n_point = int(((st & icrs.ST_POINT) != 0).sum().item())
+    # the plain path on every epoch, timed on every 8th event (same epoch mix)
+    sub = w.subset(range(0, w.n_events, 8))
+    ts = torch.tensor(sub.t, device="cuda")
+    wsp = h.workspace(sub.n_events, sub.n_epochs)
+    _, dt_p = _timed(lambda: h.magnification(sub.params, sub.offsets, ts, workspace=wsp), reps=2)
+    return {"measure": "hybrid", "workload": w.name, "n_events": w.n_events, "n_epochs": w.n_epochs,
+            "grid": [128, 512], "point_fraction": n_point / w.n_epochs, "hybrid_epochs_per_s": w.n_epochs / dt_h,
+            "hybrid_ms": dt_h * 1e3, "plain_all_epochs_per_s": sub.n_epochs / dt_p,
+            "selection": {"n_check": 16, "guard": 2.0, "tol": 1e-4, "vary_max": 0.1}}
+
+
+def nll(n_events=512):
+    w = workloads.cadence_workload(n_events)
+    h = icrs.Handle(n_lens=2, n_limb=128, n_r=128, n_theta=512, ray_precision="fp32", root_precision="fp32")
+    t = torch.tensor(w.t, device="cuda")
+    rng = np.random.default_rng(52)
+    sigma = torch.tensor(rng.uniform(0.005, 0.02, w.n_epochs), device="cuda")
+    m, _ = h.magnification_hybrid(w.params, w.offsets, t)
+    flux = (m - 1.0) + 10.0 + torch.randn_like(m) * sigma
+    prior = np.tile([1.0, 10.0, 0.5, 2.0], (w.n_events, 1))
+    (v, g), dt = _timed(lambda: icrs.light_curve_nll_and_grad(h, w.params, w.offsets, t, flux, sigma, prior,
+                                                             hybrid=True), reps=2)
+    nll_only = lambda: h.marginal_nll(w.offsets, m, flux, sigma, prior)
+    _, dt_n = _timed(nll_only)
+    return {"measure": "nll", "workload": w.name, "n_events": w.n_events, "n_epochs": w.n_epochs,
+            "objective_and_gradient_ms": dt * 1e3, "objective_and_gradient_epochs_per_s": w.n_epochs / dt,
+            "likelihood_kernel_ms": dt_n * 1e3, "grad_finite": bool(torch.isfinite(g).all().item())}
+
+
+def fig2():
+    w = workloads.fig2_triple()
+    h = icrs.Handle(n_lens=3, n_limb=128, n_r=w.n_r, n_theta=w.n_theta, ray_precision="fp64", root_precision="fp64")
+    t = torch.tensor(w.t, device="cuda")
+    ws = h.workspace(w.n_events, w.n_epochs)
+    _, dt_f = _timed(lambda: h.magnification(w.params, w.offsets, t, workspace=ws))
+    sec, per, ns = h.get_sectors(w.n_epochs, ws)
+    _, dt_j = _timed(lambda: h.magnification_vjp(w.params, w.offsets, t, sec, per, ns, jac=True, workspace=ws))
+    return {"measure": "fig2", "workload": w.name, "n_epochs": w.n_epochs, "grid": [w.n_r, w.n_theta],
+            "forward_ms": dt_f * 1e3, "jacobian_ms": dt_j * 1e3, "jacobian_epochs_per_s": w.n_epochs / dt_j,
+            "sectors_per_epoch": float(ns.float().mean().item()), "precision": "f64"}
+
+
 def main(argv):
-    which = argv or ["adjoint", "triple", "train", "serve"]
-    fns = {"adjoint": adjoint, "triple": triple, "train": train, "serve": serving}
+    which = argv or ["adjoint", "triple", "train", "serve", "hybrid", "nll", "fig2"]
+    fns = {"adjoint": adjoint, "triple": triple, "train": train, "serve": serving, "hybrid": hybrid, "nll": nll,
+           "fig2": fig2}
     for k in which:
         print(json.dumps(fns[k]()), flush=True)
 

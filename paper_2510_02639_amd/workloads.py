@@ -234,3 +234,53 @@ def config3(n_events=256, n_epochs=2000, seed=3) -> Workload:
     t = np.tile(np.linspace(-30.0, 30.0, n_epochs), n_events)
     off = np.arange(0, n_events * n_epochs + 1, n_epochs, dtype=np.int64)
     return Workload("triple-batch", 3, params, off, t, 128, 128, 512, "fp32", "fp64")
+
+
+def fig2_triple(n_epochs=1000, rho=1e-2) -> Workload:
+    """The triple-lens gradient example of Sec. 3.5 / Fig. 2: (t0, tE, u0, q, s, alpha, q3,
+    r3, psi) = (0, 10 d, 0, 0.5, 1.1, 60 deg, 0.03, 1.24, 76 deg), uniform source, 500 x 500
+    grids.  The caption gives no rho and no time range: rho = 1e-2 and t in [-1.5 tE, 1.5 tE]
+    are taken."""
+    p = _row(1.1, 0.5, 0.0, np.deg2rad(60.0), 0.0, 10.0, rho, 0.0, 0.03, 1.24, np.deg2rad(76.0))[None, :]
+    t = np.linspace(-15.0, 15.0, n_epochs)
+    return Workload("triple-fig2", 3, p, np.array([0, n_epochs], np.int64), t, 128, 500, 500, "fp64", "fp64")
+
+
+def cadence_workload(n_events=512, seed=5, rho=1e-3, days=72.0, cadence_min=12.0) -> Workload:
+    """Light curves on a survey cadence (Sec. 5.1: 72 days at a 12-minute cadence, 8640 epochs
+    per event), planetary-regime binaries drawn as in the benchmark batch (rho fixed), each
+    event's window centred on t0 = 0 with tE = 20 d.  Most epochs lie far from the caustics:
+    the workload of the hybrid light curve (Sec. 3.4, item iii)."""
+    rng = np.random.default_rng(seed)
+    rows = []
+    for _ in range(n_events):
+        lq = rng.uniform(-5.0, -2.0)
+        s = float(np.exp(rng.uniform(np.log(0.5), np.log(2.0))))
+        u0 = rng.uniform(0.0, 0.3)
+        alpha = rng.uniform(0.0, 2.0 * np.pi)
+        u1 = rng.uniform(0.3, 0.7)
+        rows.append(_row(s, 10 ** lq, u0, alpha, 0.0, 20.0, rho, u1))
+    n_e = int(round(days * 24 * 60 / cadence_min))
+    t1 = np.arange(n_e) * (cadence_min / (24 * 60)) - days / 2
+    t = np.tile(t1, n_events)
+    off = np.arange(0, n_events * n_e + 1, n_e, dtype=np.int64)
+    return Workload("binary-cadence-72d-12min", 2, np.stack(rows), off, t, 128, 128, 512, "fp32", "fp32")
+
+
+def fig4_sources(rho, n_sources=24, seed=44, s=1.0, q=0.1, u1=0.0) -> Workload:
+    """The accuracy protocol of Sec. 4.1 / Fig. 4: source centres drawn uniformly inside a
+    circle of radius rho around a randomly chosen point of the caustic of the q = 0.1, s = 1
+    binary (one resonant caustic, so every source lies within rho of it); uniform source.
+    One event per source with a single epoch: t0 = 0, tE = 1, alpha = 0 put the centre at
+    w_c = t + i u0."""
+    rng = np.random.default_rng(seed)
+    caus = binary_caustics(s, q, n_phi=4096)[0].reshape(-1)
+    rows, ts = [], []
+    for _ in range(n_sources):
+        c = caus[rng.integers(caus.size)]
+        r = rho * np.sqrt(rng.uniform())
+        w = c + r * np.exp(1j * rng.uniform(0.0, 2.0 * np.pi))
+        rows.append(_row(s, q, w.imag, 0.0, 0.0, 1.0, rho, u1))
+        ts.append(w.real)
+    off = np.arange(n_sources + 1, dtype=np.int64)
+    return Workload(f"fig4-rho{rho:g}", 2, np.stack(rows), off, np.array(ts), 256, 1000, 1000, "fp64", "fp64")
