@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <limits>
 #include <cstdint>
 #include <cstring>
 #include <type_traits>
@@ -217,7 +218,8 @@ bool ea_roots(const Poly& P, std::vector<cplx>& z, int* iters_out, bool continue
       const double az = std::abs(z[k]);
       for (int j = n; j >= 0; --j) noise = noise * az + std::abs(P[j]);
       noise *= 8.0 * n * 1.1102230246251565e-16;
-      if (noise_stop && std::abs(p) <= noise) {
+      // P(z) exactly zero: z is a root, its correction (P/P') / (1 - (P/P') S) is zero
+      if (p == cplx(0.0, 0.0) || (noise_stop && std::abs(p) <= noise)) {
         done[k] = 1;
         continue;
       }
@@ -245,22 +247,28 @@ bool ea_roots(const Poly& P, std::vector<cplx>& z, int* iters_out, bool continue
 
 // ---------------------------------------------------------------------------------------
 // O6: validation, Sec. 2.1 ("each root ... must be validated by substituting it back").
-// Reading of the tolerance: every root is polished by at most 8 Newton steps on the lens
+// Reading of the tolerance: every root is polished by Newton steps on the lens
 // equation itself (with F = lens_map(z) - w and kappa as above, the step solving
 // dz + kappa conj(dz) = -F is dz = (kappa conj(F) - F) / (1 - |kappa|^2)), kept when
 // |F| <= 1e-10 afterwards, and dropped as a duplicate within 1e-9 max(1,|z|) of a kept one.
-// A root still within the residual bound after 8 steps whose steps have not converged (last
-// step above 1e-14 max(1,|z|)) takes up to 8 more while it stays within the bound: a
+// Steps stop once a step is below 1e-14 max(1,|z|).  After 8 steps a root goes on, to 24 at
+// most, while it is within the residual bound or its |F| at least halves per step: a
 // spurious root of the polynomial can wander into an image's basin and stop within the
-// residual bound yet outside the duplicate radius, which would count that image twice.
+// residual bound yet outside the duplicate radius, which would count that image twice; and a
+// root of a tight cluster next to a low-mass lens, accurate only to the cluster's
+// conditioning (~1e-5), needs more than 8 Newton steps to reach its image across the nearby
+// critical curve, and a fixed cap there drops a true image.
 // An image count outside {N+1, N+3, ..., 5(N-1)} triggers one extra pass seeded next to
 // each lens (z = a_k - eps_k / conj(w' - a_k), w' = w shifted by the other lenses'
 // deflection at a_k -- the leading-order image near a lens); a count still outside the
 // set raises ST_IMG_COUNT.
 cplx polish(const Lens& L, cplx w, cplx z) {
-  for (int s = 0; s < 16; ++s) {
+  double f_prev = std::numeric_limits<double>::infinity();
+  for (int s = 0; s < 24; ++s) {
     const cplx F = lens_map(L, z) - w;
-    if (s >= 8 && !(std::abs(F) <= 1e-10)) break;
+    const double f = std::abs(F);
+    if (s >= 8 && !(f <= 1e-10) && !(f <= 0.5 * f_prev)) break;
+    f_prev = f;
     const cplx k = kappa_of(L, z);
     const double den = 1.0 - std::norm(k);
     if (den == 0.0 || !std::isfinite(den)) break;
@@ -1296,6 +1304,9 @@ int orc_num_threads() {
   return n;
 }
 
+// Sets the thread count of the oracle's later parallel regions (n >= 1).
+void orc_set_num_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+
 void orc_frame(int n_lens, const double* params, double* eps, double* a) {
   const Lens L = make_lens(n_lens, params);
   for (int i = 0; i < n_lens; ++i) {
@@ -1347,6 +1358,33 @@ int orc_ea_roots(int deg, const double* coef, double* roots, int* iters) {
     roots[2 * k + 1] = z[k].imag();
   }
   return ok ? 1 : 0;
+}
+
+// Ehrlich-Aberth continued from the estimates in roots (in/out) with the step test only, at
+// most cap iterations (the validation's last resort); returns 1 when every root converged.
+int orc_ea_continue(int deg, const double* coef, double* roots, int cap) {
+  Poly P(deg + 1);
+  for (int j = 0; j <= deg; ++j) P[j] = cplx(coef[2 * j], coef[2 * j + 1]);
+  std::vector<cplx> z(deg);
+  for (int k = 0; k < deg; ++k) z[k] = cplx(roots[2 * k], roots[2 * k + 1]);
+  int it = 0;
+  const bool ok = ea_roots(P, z, &it, true, cap);
+  for (int k = 0; k < deg; ++k) {
+    roots[2 * k] = z[k].real();
+    roots[2 * k + 1] = z[k].imag();
+  }
+  return ok ? 1 : 0;
+}
+
+// Newton polish of one candidate z on the lens equation (the validation's step rule);
+// returns |F| at the result.
+double orc_polish(int n, const double* eps, const double* a, const double* w, double* z) {
+  const Lens L = lens_from(n, eps, a);
+  const cplx ww(w[0], w[1]);
+  const cplx r = polish(L, ww, cplx(z[0], z[1]));
+  z[0] = r.real();
+  z[1] = r.imag();
+  return std::abs(lens_map(L, r) - ww);
 }
 
 // Validated images of a point source at w; returns the count, status bits in *status.

@@ -46,6 +46,7 @@ def lib():
                                     ctypes.c_int32, ctypes.c_int64)
         P = ctypes.POINTER
         L.orc_num_threads.restype = i
+        L.orc_set_num_threads.argtypes = [i]
         L.orc_frame.argtypes = [i, P(d), P(d), P(d)]
         L.orc_source_center.argtypes = [P(d), d, P(d)]
         L.orc_lens_map.argtypes = [i, P(d), P(d), P(d), P(d)]
@@ -53,6 +54,10 @@ def lib():
         L.orc_lens_poly.restype = i
         L.orc_ea_roots.argtypes = [i, P(d), P(d), P(i)]
         L.orc_ea_roots.restype = i
+        L.orc_ea_continue.argtypes = [i, P(d), P(d), i]
+        L.orc_ea_continue.restype = i
+        L.orc_polish.argtypes = [i, P(d), P(d), P(d), P(d)]
+        L.orc_polish.restype = d
         L.orc_images.argtypes = [i, P(d), P(d), P(d), P(d), P(u32)]
         L.orc_images.restype = i
         L.orc_point_mag.argtypes = [i, P(d), P(d), P(d), P(i), P(d)]
@@ -85,6 +90,11 @@ def lib():
 
 def num_threads():
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n):
+    """Thread count of the oracle's later parallel regions."""
+    lib().orc_set_num_threads(int(n))
 
 
 def _p(a, ct=ctypes.c_double):
@@ -150,6 +160,28 @@ def ea_roots(coef):
     it = ctypes.c_int(0)
     ok = lib().orc_ea_roots(deg, _p(cb), _p(out), ctypes.byref(it))
     return out[0::2] + 1j * out[1::2], bool(ok), it.value
+
+
+def ea_continue(coef, z0, cap=100):
+    """Ehrlich-Aberth continued from the estimates z0 with the step test only (no
+    rounding-noise stop), at most cap iterations; returns (roots, converged)."""
+    coef = np.asarray(coef, dtype=np.complex128)
+    deg = coef.size - 1
+    cb = _dbl(np.stack([coef.real, coef.imag], -1).reshape(-1))
+    z0 = np.asarray(z0, dtype=np.complex128)
+    zz = _dbl(np.stack([z0.real, z0.imag], -1).reshape(-1))
+    ok = lib().orc_ea_continue(deg, _p(cb), _p(zz), int(cap))
+    return zz[0::2] + 1j * zz[1::2], bool(ok)
+
+
+def polish(eps, a, w, z):
+    """The validation's Newton polish of one candidate z; returns (z, |F|)."""
+    n = int(np.size(eps))
+    e, ab = _lens_arrays(eps, a)
+    ww = _dbl([complex(w).real, complex(w).imag])
+    zz = _dbl([complex(z).real, complex(z).imag])
+    f = lib().orc_polish(n, _p(e), _p(ab), _p(ww), _p(zz))
+    return complex(zz[0], zz[1]), float(f)
 
 
 def images(eps, a, w):

@@ -159,6 +159,31 @@ def test_images_inside_a_small_planetary_caustic(w):
     assert abs(np.sum(mu) - 1.0) < 1e-6 * A
 
 
+def test_polish_reaches_an_image_across_the_critical_curve():
+    """A root of the five-root cluster of the last point above, as accurately as the cluster's
+    conditioning lets a fused-multiply-add evaluation of the polynomial place it (3e-5 off):
+    Newton on the lens equation first jumps across the nearby critical curve and needs ten
+    steps to converge; the polish must get there (a fixed 8-step cap stopped at |F| ~ 1e-9
+    and dropped a true image)."""
+    s, q = _PLANETARY_CLUSTER_S_Q
+    eps, a = O.frame(2, O.params(s=s, q=q))
+    w = _PLANETARY_CLUSTER_POINTS[-1]
+    ref = R.newton_images(eps, a, w)
+    for z0 in (complex(0.769039891371, 0.003014730046), complex(0.769026248525, 0.002975107960)):
+        z, f = O.polish(eps, a, w, z0)
+        assert f <= 1e-10
+        assert np.min(np.abs(ref - z)) <= 1e-12 * max(1.0, abs(z)), (z, ref)
+
+
+def test_continued_iteration_stops_on_an_exact_root():
+    """The step-test-only continuation from estimates one of which is exactly a root (P = 0
+    there): the others still converge to the remaining roots and nothing turns into NaN."""
+    coef = np.poly1d([1.0, -2.0, -5.0, 6.0]).coeffs[::-1]          # (z - 1)(z + 2)(z - 3), low order first
+    z, ok = O.ea_continue(coef, [1.0 + 0.0j, 2.5 + 0.3j, -1.4 - 0.2j], cap=100)
+    assert ok and np.all(np.isfinite(z))
+    assert R.multiset_close(z, np.array([1.0, -2.0, 3.0], dtype=complex), 1e-12), z
+
+
 # --- O7: point-source magnification (eqs. amp_point, detJ) ------------------------------
 
 def test_single_lens_point_magnification_closed_form():
