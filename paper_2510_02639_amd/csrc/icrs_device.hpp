@@ -323,7 +323,9 @@ __device__ inline int ehrlich_aberth(const cx<T> (&b)[D + 1], cx<T> (&z)[D], int
 #pragma unroll
       for (int j = D - 1; j >= 0; --j) noise = noise * az + absb[j];
       noise *= T(8 * D) * EAConst<T>::unit;
-      if (noise_stop && norm2(p) <= noise * noise) {
+      // P(z) exactly zero: z is a root and its correction P/P' / (1 - (P/P') S) is zero
+      // (dividing by P would give NaN and spread it to every root through S)
+      if (is_zero(p) || (noise_stop && norm2(p) <= noise * noise)) {
         done |= 1u << k;
         continue;
       }
@@ -351,18 +353,27 @@ __device__ inline int ehrlich_aberth(const cx<T> (&b)[D + 1], cx<T> (&z)[D], int
 
 // ---------------------------------------------------------------------------------------
 // Validation (Sec. 2.1: roots are checked by substitution into eq. lens_eq).  Each candidate
-// gets at most 8 Newton steps on the lens equation itself -- the step solving
+// is polished by Newton steps on the lens equation itself -- the step solving
 // dz + kappa conj(dz) = -F is (kappa conj(F) - F)/(1 - |kappa|^2) -- and is kept when
-// |F| <= 1e-10, unless it lies within 1e-9 max(1,|z|) of an image already kept.  A candidate
-// still within the residual bound after 8 steps that has not converged gets up to 8 more, for
-// as long as it stays within the bound: a spurious root of the polynomial can drift into an
-// image's basin and stop inside the residual bound but outside the duplicate radius, where it
-// would count as a second copy of that image.
+// |F| <= 1e-10, unless it lies within 1e-9 max(1,|z|) of an image already kept.  Steps stop
+// when a step falls below 1e-14 max(1,|z|); after the first 8, a candidate goes on only while
+// it is within the residual bound or its |F| at least halves per step, 24 steps at most.  The
+// first rule: a spurious root of the polynomial can drift into an image's basin and stop
+// inside the residual bound but outside the duplicate radius, where it would count as a
+// second copy of that image.  The second: a root of a tight cluster is only as accurate as
+// the cluster's conditioning allows (~1e-5 next to a planet), and Newton from there first
+// crosses the critical curve between the two images; a fixed 8-step cap rejected such an
+// image while its residual was still falling quadratically, which can leave a valid but
+// wrong image count.
+constexpr int kPolishMaxSteps = 24;
 template <int N>
 __device__ inline c64 polish(const Lens<N>& L, c64 w, c64 z) {
-  for (int s = 0; s < 16; ++s) {
+  double f_prev = __builtin_inf();
+  for (int s = 0; s < kPolishMaxSteps; ++s) {
     const c64 F = lens_map(L, z) - w;
-    if (s >= 8 && !(norm2(F) <= 1e-20)) break;
+    const double f = norm2(F);
+    if (s >= 8 && !(f <= 1e-20) && !(f <= 0.25 * f_prev)) break;
+    f_prev = f;
     const c64 k = lens_kappa(L, z);
     const double den = 1.0 - norm2(k);
     if (den == 0.0 || !isfinite(den)) break;

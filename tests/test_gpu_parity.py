@@ -155,6 +155,47 @@ def test_spurious_roots_are_not_kept_as_second_images(roots):
             assert np.min(np.abs(got - z)) < 1e-9
 
 
+# a planetary binary (s = 0.768, q = 1.4e-5) and source points just inside its planetary
+# caustic, limb points of benchmark-workload epochs (the same points as the oracle's pins):
+# five images, three or four of them within a few 1e-3 of each other next to the planet.  At
+# the last point two images 2e-5 apart straddle the critical curve: a cold solve's cluster
+# roots land 3e-5 off, both polished onto one image under a fixed 8-step Newton cap, and the
+# step-test-only continuation then divided by an exactly zero P(z) and returned NaN roots.
+_PLANETARY_CLUSTER_S_Q = (0.7680762680197694, 1.3738029330516958e-05)
+_PLANETARY_CLUSTER_POINTS = [complex(-0.5342693897421594, -0.00689307926796158),
+                             complex(-0.5339617226949848, -0.0073322717253918885),
+                             complex(-0.5337469782160287, -0.007306817365788684),
+                             complex(-0.5351270736998957, -0.0062434861140690575),
+                             complex(-0.5336263835786164, -0.007107361116016892),
+                             complex(-0.5325874217950066, -0.00622251111559628)]
+
+
+@pytest.mark.parametrize("roots", ["fp32", "fp64"])
+def test_images_of_a_root_cluster_next_to_a_planet(roots):
+    """Device images at those points (each taken as the source centre of a cold solve) equal
+    the oracle's five, each within 1e-9, with no status bit."""
+    s, q = _PLANETARY_CLUSTER_S_Q
+    pts = _PLANETARY_CLUSTER_POINTS
+    params = np.stack([O.params(s=s, q=q, u0=w.imag, alpha=0.0, t0=0.0, tE=1.0, rho=1e-3, u1=0.5) for w in pts])
+    t = np.array([w.real for w in pts])
+    h = icrs.Handle(n_lens=2, n_limb=128, n_r=128, n_theta=512, ray_precision="fp32", root_precision=roots)
+    img, nimg, aps = h.point_images(params, np.arange(len(pts) + 1, dtype=np.int64), torch.tensor(t, device="cuda"))
+    torch.cuda.synchronize()
+    img, nimg, aps = img.cpu().numpy(), nimg.cpu().numpy(), aps.cpu().numpy()
+    for e, w in enumerate(pts):
+        eps, a = O.frame(2, params[e])
+        assert abs(O.source_center(params[e], t[e]) - w) < 1e-15
+        ref, st = O.images(eps, a, w)
+        assert st == 0 and ref.size == 5
+        got = img[e, :nimg[e], 0] + 1j * img[e, :nimg[e], 1]
+        print(f"point {e}: device {nimg[e]} images, oracle {ref.size}", flush=True)
+        assert nimg[e] == 5 and np.all(np.isfinite(got)), got
+        for z in ref:
+            assert np.min(np.abs(got - z)) < 1e-9
+        A, _ = O.point_mag(eps, a, w)
+        assert abs(aps[e] / A - 1) < 1e-9
+
+
 def test_ragged_binary_batch_fp64():
     """Uneven events (one empty), planetary mass ratios, FP64 roots and rays at 64 x 256."""
     big = W.binary_batch(2, 8)
@@ -369,6 +410,8 @@ def test_fp32_rays_on_poorly_resolved_near_caustic_images():
 # the planetary caustic while the source centre does not: warm-started from the centre's
 # roots, two Ehrlich-Aberth iterates settled in the root cluster next to the planet on one
 # root, one of the five images went missing and the epoch carried a false image-count flag
+# (the last one: a cold solve's pair of cluster roots 3e-5 off, rejected by a fixed 8-step
+# polish, then NaN roots from the continuation dividing by an exactly zero P(z))
 _LOST_ROOT_EPOCHS = np.array([5083418, 5083483, 5083637, 5083769, 5083922, 5084692, 5085325])
 
 
