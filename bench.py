@@ -31,6 +31,7 @@ from __future__ import annotations
 
 import argparse
 import json
+from concurrent.futures import ThreadPoolExecutor
 import os
 import sys
 import time
@@ -61,26 +62,46 @@ TRAFFIC = {("fp32", 2048, "plain"): 2.666e11,   # FETCH 70694665 KiB x 2.0 + WRI
 
 
 def cpu_baseline(w, mags, budget_s, seed=0):
-    """The FP64 oracle on a bounded sample of the same epochs (all host threads); on the
-    same sample, each GPU path against the oracle and against the oracle's source-disk
+    """The FP64 oracle on a bounded sample of the same epochs, on all host threads (median of
+    three timings) and on one (median of three); on the same sample, each GPU path against the oracle and against the oracle's source-disk
     quadrature (epochs where no caustic crosses the disk and two resolutions agree)."""
     from oracle import oracle as O
     rng = np.random.default_rng(seed)
     ev_of = np.repeat(np.arange(w.n_events), np.diff(w.offsets))
 
-    def run(idx):
+    threads = O.num_threads()
+
+    def run(idx, workers):
+        """Oracle magnifications of the sampled epochs, one event per job on `workers` host
+        threads (each job's OpenMP region held to one thread); returns (idx, mag, seconds)."""
         idx = np.sort(idx)
-        t0 = time.perf_counter()
         out = np.empty(idx.size)
-        for i in np.unique(ev_of[idx]):
+        ev = np.unique(ev_of[idx])
+
+        def one(i):
+            O.set_num_threads(1)
             sel = idx[ev_of[idx] == i]
-            r = O.magnification(w.n_lens, w.params[i], w.t[sel], n_limb=w.n_limb, n_r=w.n_r, n_theta=w.n_theta)
-            out[np.searchsorted(idx, sel)] = r["mag"]
+            out[np.searchsorted(idx, sel)] = O.magnification(w.n_lens, w.params[i], w.t[sel], n_limb=w.n_limb,
+                                                             n_r=w.n_r, n_theta=w.n_theta)["mag"]
+
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(max_workers=workers) as ex:
+            list(ex.map(one, ev))
         return idx, out, time.perf_counter() - t0
 
-    idx, mag, dt = run(rng.choice(w.n_epochs, size=64, replace=False))
-    n = int(np.clip(budget_s / max(dt / 64, 1e-6), 64, 20000))
-    idx, mag, dt = run(rng.choice(w.n_epochs, size=n, replace=False))
+    _, _, dt = run(rng.choice(w.n_epochs, size=4 * threads, replace=False), threads)
+    n = int(np.clip(budget_s / max(dt / (4 * threads), 1e-6), 96, 30000)) // 3 * 3
+    idx = np.sort(rng.choice(w.n_epochs, size=n, replace=False))
+    # all threads: three disjoint thirds of the sample, the rate the median of the three
+    parts = [run(idx[k::3], threads) for k in range(3)]
+    rates = sorted(p[0].size / p[2] for p in parts)
+    mag = np.empty(idx.size)
+    for p_idx, p_mag, _ in parts:
+        mag[np.searchsorted(idx, p_idx)] = p_mag
+    dt = sum(p[2] for p in parts)
+    # one thread: three small samples, median
+    n1 = 24
+    one = sorted(n1 / run(rng.choice(w.n_epochs, size=n1, replace=False), 1)[2] for _ in range(3))
     ref = np.full(idx.size, np.nan)
     for i in np.unique(ev_of[idx]):
         sel = np.nonzero(ev_of[idx] == i)[0]
@@ -97,9 +118,12 @@ def cpu_baseline(w, mags, budget_s, seed=0):
                      "vs_disk_median": float(np.median(err)), "vs_disk_p99": float(np.quantile(err, 0.99)),
                      "vs_disk_max": float(err.max()), "vs_disk_frac_le_1e-4": float(np.mean(err <= 1e-4))}
     return {
-        "value": idx.size / dt, "unit": "epochs/s", "cores": O.num_threads(), "kind": "oracle",
-        "sample": f"{idx.size} epochs drawn uniformly (seed {seed}) from the same workload, FP64 oracle "
-                  f"(plain path), {w.n_r}x{w.n_theta} grids, {dt:.1f} s",
+        "value": rates[1], "unit": "epochs/s", "cores": threads, "kind": "oracle",
+        "single_core": {"value": one[1], "unit": "epochs/s", "cores": 1, "runs": one, "epochs_per_run": n1},
+        "runs": rates,
+        "sample": f"{idx.size} epochs drawn uniformly (seed {seed}) from the same workload, timed as three "
+                  f"disjoint thirds (median rate), FP64 oracle (plain path), {w.n_r}x{w.n_theta} grids, "
+                  f"{dt:.1f} s on {threads} threads; single core: median of three runs of {n1} epochs",
     }, acc, (idx[good], ref[good])
 
 

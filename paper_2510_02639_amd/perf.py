@@ -93,16 +93,19 @@ def train():
             "inference_tflops": pred_rows * flops_row / dt_inf / 1e12, "mfma_peak_bf16_tflops": 2500.0}
 
 
-def serving(seconds=6.0):
-    reqs = serve.make_requests(seconds)
+def serving(seconds=60.0, rate=200.0):
+    """The serving loop for `seconds` of Poisson arrivals (200 events/s: ~12,000 events at
+    60 s), each path with the grids and gate the autotuner picked on a calibration batch."""
+    reqs = serve.make_requests(seconds, rate)
     out = {}
     for use in (True, False):
-        srv = serve.Server(4 << 30, use_learned=use)
+        srv = serve.tuned_server(4 << 30, use_learned=use)
         srv.run_batch(reqs[:4])
         srv.reset_stats()
-        r = srv.serve([serve.Request(q.params, q.t, q.arrival) for q in reqs])
+        r = srv.serve([serve.Request(q.params, q.t, q.arrival) for q in reqs], verbose=True)
         out["learned" if use else "plain"] = r
-    return {"measure": "serve", "rate_events_per_s": 200.0, "seconds": seconds, **out}
+        print(json.dumps({"serve": r}), flush=True)
+    return {"measure": "serve", "rate_events_per_s": rate, "seconds": seconds, **out}
 
 
 def hybrid(n_events=512):

@@ -9,7 +9,12 @@ oldest first, while the batch's workspace fits the budget, runs one call, and st
 request's completion.  Latency = completion - arrival.  The workspace is allocated once,
 at the budget, and reused by every batch.
 
-    python -m paper_2510_02639_amd.serve --seconds 20 [--plain] [--budget-gib 16]
+Grids and drift gate: by default the autotuner picks them, untimed, on a calibration batch of
+the same event distribution (its own seed): the plain grid (the fallback's) as the smallest
+whose median error is within 3e-5 of the converged path, the learned grid and gate as the
+fastest no worse than plain at that grid (median and 99th percentile).
+
+    python -m paper_2510_02639_amd.serve --seconds 60 [--plain] [--budget-gib 16] [--no-tune]
 """
 from __future__ import annotations
 
@@ -21,7 +26,7 @@ import time
 import numpy as np
 import torch
 
-from . import icrs, learned, workloads
+from . import autotune, icrs, learned, workloads
 
 
 @dataclasses.dataclass
@@ -48,12 +53,13 @@ def make_requests(seconds=60.0, rate=200.0, seed=51, max_events=None):
 
 class Server:
     def __init__(self, budget_bytes=16 << 30, use_learned=True, model=None, n_limb=128, n_r=128, n_theta=512,
-                 learned_grid=None):
+                 learned_grid=None, gate_rel=1e-3, gate_slack=0.0):
         self.h = icrs.Handle(n_lens=2, n_limb=n_limb, n_r=n_r, n_theta=n_theta, ray_precision="fp32",
                              root_precision="fp32")
         self.use_learned = use_learned
         self.model = model if (model is not None or not use_learned) else learned.BoundsModel.load()
         self.learned_grid = learned_grid or (n_r, n_theta)
+        self.gate = (float(gate_rel), float(gate_slack))
         self.budget = int(budget_bytes)
         self.ws = torch.empty(self.budget, dtype=torch.uint8, device="cuda")
         self.reset_stats()
@@ -76,7 +82,8 @@ class Server:
         n = t.numel()
         if self.use_learned:
             mag, status, st = self.h.magnification_learned(params, off, t, self.model, workspace=self.ws,
-                                                           n_r=self.learned_grid[0], n_theta=self.learned_grid[1])
+                                                           n_r=self.learned_grid[0], n_theta=self.learned_grid[1],
+                                                           gate_rel=self.gate[0], gate_slack=self.gate[1])
             self.stats["fallback"] += st["n_fallback"]
             self.stats["learned"] += st["n_learned"]
         else:
@@ -126,7 +133,22 @@ class Server:
                 "p99_ms": float(np.percentile(lat, 99) * 1e3), "max_ms": float(lat.max() * 1e3),
                 "batches": len(batch_sizes), "mean_batch_events": float(np.mean(batch_sizes)),
                 "fallback_epochs": self.stats["fallback"], "learned_epochs": self.stats["learned"],
-                "path": "learned" if self.use_learned else "plain"}
+                "path": "learned" if self.use_learned else "plain", "plain_grid": [self.h.cfg.n_r, self.h.cfg.n_theta],
+                "learned_grid": list(self.learned_grid) if self.use_learned else None,
+                "gate": list(self.gate) if self.use_learned else None}
+
+
+def tuned_server(budget_bytes, use_learned=True, n_calibration_events=256, seed=61, verbose=False):
+    """A server whose grids and gate the autotuner picked on a calibration batch drawn like
+    the requests (planetary events, rho = 1e-3) with its own seed."""
+    cal = workloads.binary_batch(seed, n_calibration_events, rho_fixed=1e-3, name="serving-calibration")
+    g = autotune.tune(cal, tol=3e-5, every=20, stat="median", verbose=verbose)
+    kw = dict(n_r=g.n_r, n_theta=g.n_theta)
+    if use_learned:
+        model = learned.BoundsModel.load()
+        lt = autotune.tune_learned(cal, model, plain_grid=(g.n_r, g.n_theta), every=20, verbose=verbose)
+        kw.update(model=model, learned_grid=(lt.n_r, lt.n_theta), gate_rel=lt.gate_rel, gate_slack=lt.gate_slack)
+    return Server(budget_bytes, use_learned=use_learned, **kw)
 
 
 def main():
@@ -135,9 +157,12 @@ def main():
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--budget-gib", type=float, default=16.0)
     ap.add_argument("--plain", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="fixed 128 x 512 grids and a 1e-3 gate")
     args = ap.parse_args()
     reqs = make_requests(args.seconds, args.rate)
-    srv = Server(int(args.budget_gib * (1 << 30)), use_learned=not args.plain)
+    budget = int(args.budget_gib * (1 << 30))
+    srv = (Server(budget, use_learned=not args.plain) if args.no_tune
+           else tuned_server(budget, use_learned=not args.plain))
     srv.run_batch(reqs[:4])            # warm-up (kernel loading), not part of the run
     srv.reset_stats()
     print(json.dumps(srv.serve(reqs)), flush=True)

@@ -54,3 +54,21 @@ def test_serving_budget_splits_batches():
     assert out["events"] == len(reqs)
     total = srv2._bytes(len(reqs), sum(r.t.size for r in reqs))
     assert out["batches"] >= total // budget and out["batches"] > 1
+
+
+def test_served_plain_results_match_the_oracle():
+    """Magnifications a plain server returns, on sampled epochs of sampled requests, against
+    the oracle at the server's grid (FP32 rays: 3e-5)."""
+    from oracle import oracle as O
+    reqs = serve.make_requests(seconds=0.5, rate=200.0, seed=54)
+    srv = serve.Server(budget_bytes=1 << 30, use_learned=False)
+    out = srv.serve(reqs)
+    assert out["events"] == len(reqs)
+    rng = np.random.default_rng(54)
+    worst = 0.0
+    for r in (reqs[i] for i in rng.choice(len(reqs), size=min(6, len(reqs)), replace=False)):
+        sel = np.sort(rng.choice(r.t.size, size=min(8, r.t.size), replace=False))
+        ref = O.magnification(2, r.params, r.t[sel], n_limb=128, n_r=128, n_theta=512)["mag"]
+        worst = max(worst, float(np.max(np.abs(r.mag[sel] / ref - 1.0))))
+    print("served vs oracle max rel err", worst, flush=True)
+    assert worst <= 3e-5
