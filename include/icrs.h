@@ -114,6 +114,23 @@ icrs_status icrs_magnification(icrs_handle* h, int64_t n_events, const double* p
                                double* mag, uint32_t* status, void* workspace,
                                size_t workspace_bytes);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): icrs_magnification without a caller
+ * workspace.  The device scratch is a library-owned array of ICRS_NOALLOC_SCRATCH_BYTES
+ * (64 MiB) per GPU, resolved on the first call on each device and held until the process
+ * ends; the call allocates nothing (no hipMalloc/hipFree, no allocating library routine).
+ * Inputs and outputs as for icrs_magnification, on the current device (the handle's stream
+ * must belong to it).  A batch whose workspace (icrs_workspace_bytes) exceeds the scratch --
+ * about 90 000 epochs -- returns ICRS_ENOMEM before anything is enqueued.  Every call on a
+ * GPU uses that GPU's one scratch array: calls that overlap on one GPU (two streams, two
+ * threads) race and must be serialised by the caller.  Each call initialises every part of
+ * the scratch it reads, so the contents left by an earlier call do not matter; final
+ * sectors are not exported (icrs_get_sectors needs a caller workspace). */
+#define ICRS_NOALLOC_SCRATCH_BYTES (64u << 20)
+icrs_status icrs_magnification_noalloc(icrs_handle* h, int64_t n_events, const double* params,
+                                       const int64_t* epoch_offsets, int64_t n_epochs, const double* t,
+                                       double* mag, uint32_t* status);
+
 /* The plain path split for stream capture (hipGraph) and repeated runs over one batch:
  * icrs_prepare() checks and uploads the events (host arrays as for icrs_magnification)
  * into the workspace and records the batch in the handle; icrs_run() then enqueues the whole

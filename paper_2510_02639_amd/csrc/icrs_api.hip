@@ -3,6 +3,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 
 #include "../../include/icrs.h"
@@ -434,6 +435,34 @@ icrs_status run_learned(icrs_handle* h, const Views& v, const icrs_learned_confi
 }
 
 
+// Device scratch of icrs_magnification_noalloc: one copy per GPU, held until the process
+// ends.  In host code `scratch` names a host-side stand-in, not device memory: its device
+// address is taken once per device with hipGetSymbolAddress (with that device current) and
+// only that address is ever passed to kernels or copies.
+static __device__ __align__(256) unsigned char scratch[ICRS_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's copy of `scratch` (resolved on the first call on that device).
+hipError_t scratch_for_current_device(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr || ((uintptr_t)ptr & (kAlign - 1)) != 0) return hipErrorInvalidValue;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -504,6 +533,27 @@ icrs_status icrs_magnification(icrs_handle* h, int64_t n_events, const double* p
   const icrs_status ps = prepare(h, n_events, params, epoch_offsets, n_epochs, t, workspace, workspace_bytes, &v);
   if (ps != ICRS_OK || n_epochs == 0) return ps;
   return run_plain(h, v, mag, status);
+}
+
+icrs_status icrs_magnification_noalloc(icrs_handle* h, int64_t n_events, const double* params,
+                                       const int64_t* epoch_offsets, int64_t n_epochs, const double* t, double* mag,
+                                       uint32_t* status) {
+  if (!h || !events_ok(h->cfg, n_events, params, epoch_offsets, n_epochs)) return ICRS_EINVAL;
+  if (n_epochs > 0 && (!t || !mag || !status)) return ICRS_EINVAL;
+  const size_t need = layout_for(n_events, n_epochs).total;
+  if (need > (size_t)ICRS_NOALLOC_SCRATCH_BYTES) return ICRS_ENOMEM;
+  if (n_epochs == 0) return ICRS_OK;
+  void* ws = nullptr;
+  ICRS_TRY(scratch_for_current_device(&ws));
+  Views v;
+  const icrs_status ps = prepare(h, n_events, params, epoch_offsets, n_epochs, t, ws, need, &v);
+  if (ps != ICRS_OK) return ps;
+  // no host waits and no event timers here
+  const int prof = h->profiling;
+  h->profiling = 0;
+  const icrs_status st = run_plain(h, v, mag, status);
+  h->profiling = prof;
+  return st;
 }
 
 icrs_status icrs_prepare(icrs_handle* h, int64_t n_events, const double* params, const int64_t* epoch_offsets,

@@ -99,6 +99,8 @@ def lib():
     L.icrs_point_images.restype = ctypes.c_int
     L.icrs_magnification_vjp.argtypes = [vp, i64, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz]
     L.icrs_magnification_vjp.restype = ctypes.c_int
+    L.icrs_magnification_noalloc.argtypes = [vp, i64, vp, vp, i64, vp, vp, vp]
+    L.icrs_magnification_noalloc.restype = ctypes.c_int
     L.icrs_prepare.argtypes = [vp, i64, vp, vp, i64, vp, sz]
     L.icrs_prepare.restype = ctypes.c_int
     L.icrs_run.argtypes = [vp, vp, vp, vp, vp, sz]
@@ -150,7 +152,7 @@ def lib():
 
 
 EXPORTED = ["icrs_default_config", "icrs_create", "icrs_destroy", "icrs_workspace_bytes", "icrs_magnification",
-
+            "icrs_magnification_noalloc",
             "icrs_magnification_given", "icrs_magnification_vjp", "icrs_get_sectors", "icrs_point_images",
             "icrs_prepare", "icrs_run", "icrs_set_profiling",
             "icrs_get_profile", "icrs_mlp_pack", "icrs_mlp_forward", "icrs_mlp_workspace_bytes",
@@ -161,6 +163,7 @@ EXPORTED = ["icrs_default_config", "icrs_create", "icrs_destroy", "icrs_workspac
             "icrs_status_string"]
 ST_LEARNED, ST_FALLBACK, ST_IMG_RECHECK, ST_BAD_SECTORS, ST_POINT = 128, 256, 512, 1024, 2048
 ICRS_MAX_EPOCHS = 1 << 27
+NOALLOC_SCRATCH_BYTES = 64 << 20
 MLP_PARAM_FLOATS, MLP_PACKED_HALFS, MLP_NORM_FLOATS = 39312, 75776, 32
 
 
@@ -248,6 +251,18 @@ class Handle:
         code = lib().icrs_magnification(self._h, p.shape[0], _ptr(p), _ptr(o), n, _ptr(t), _ptr(mag), _ptr(status),
                                         _ptr(ws), ws.numel())
         _check(code, "icrs_magnification")
+        return mag, status
+
+    def magnification_noalloc(self, params, offsets, t, mag=None, status=None):
+        """icrs_magnification_noalloc: the plain path on the library's own per-GPU scratch (no
+        workspace; the outputs are the caller's)."""
+        p, o = _host_events(params, offsets)
+        t = _dev(t, torch.float64)
+        n = t.numel()
+        mag = torch.empty(n, dtype=torch.float64, device=t.device) if mag is None else mag
+        status = torch.empty(n, dtype=torch.int32, device=t.device) if status is None else status
+        _check(lib().icrs_magnification_noalloc(self._h, p.shape[0], _ptr(p), _ptr(o), n, _ptr(t), _ptr(mag),
+                                                _ptr(status)), "icrs_magnification_noalloc")
         return mag, status
 
     def prepare(self, params, offsets, n_epochs, workspace=None):
