@@ -45,9 +45,9 @@ METRIC = "magnified epochs/sec at rho=1e-3 LD (rel err<=1e-4), plain vs batched+
 FLOPS_PER_RAY = {2: 35.0, 3: 48.0}          # algorithmic flop-equivalents per ray
 PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}  # MI355X vector peaks
 def kernel_name(rays, n_theta):
-    """The ray kernel instantiation a grid of n_theta columns runs on (4, 8 or 16 columns per lane)."""
+    """The ray kernel instantiation a grid of n_theta columns runs on (4, 8, 12 or 16 columns per lane)."""
     j = (n_theta + 63) // 64
-    jmax = 4 if j <= 4 else 8 if j <= 8 else 16
+    jmax = 4 if j <= 4 else 8 if j <= 8 else 12 if j <= 12 else 16
     exact = n_theta % 64 == 0 and j == jmax
     m = "MapF32" if rays == "fp32" else "MapF64"
     return f"rays_kernel<2, {jmax}, {'true' if exact else 'false'}, {m}<2, {jmax}>>"
@@ -127,8 +127,8 @@ def cpu_baseline(w, mags, budget_s, seed=0):
     }, acc, (idx[good], ref[good])
 
 
-PLAIN_LADDER = [(128, 512), (256, 512), (256, 1024), (512, 1024)]
-LEARNED_LADDER = [(64, 256), (128, 512), (256, 512), (256, 1024)]
+PLAIN_LADDER = [(128, 512), (256, 512), (128, 1024), (256, 1024), (512, 1024)]
+LEARNED_LADDER = [(64, 256), (128, 512), (256, 512), (128, 1024), (256, 1024)]
 
 
 def accuracy_sweep(w, model, gate_rel, idx, ref, every=10, gate_slack=0.0):
@@ -266,6 +266,9 @@ def main():
     ap.add_argument("--no-sweep", action="store_true", help="skip the accuracy/throughput sweep over grids")
     ap.add_argument("--plain-only", action="store_true", help="time the plain path only (profiling runs)")
     ap.add_argument("--learned-only", action="store_true", help="time the batched+learned path only (profiling runs)")
+    ap.add_argument("--grid", default=None, help="plain grid NRxNT instead of the autotuner's (profiling runs)")
+    ap.add_argument("--learned", default=None,
+                    help="learned grid and gate NRxNT:GATE:SLACK instead of the autotuner's (profiling runs)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (counter calibration) and exit")
     args = ap.parse_args()
@@ -297,9 +300,13 @@ def main():
     # plain grid: the autotuner's smallest grid whose median error on a 1% calibration subset
     # is within 3e-5 of the same path converged (FP64, 512 x 1024, Richardson-trusted epochs)
     t_tune = time.perf_counter()
-    ptune = autotune.tune(w, tol=3e-5, every=100, stat="median", roots=args.roots)
+    if args.grid:
+        ptune = None
+        grid = tuple(int(x) for x in args.grid.split("x"))
+    else:
+        ptune = autotune.tune(w, tol=3e-5, every=100, stat="median", roots=args.roots)
+        grid = (ptune.n_r, ptune.n_theta)
     t_tune = time.perf_counter() - t_tune
-    grid = (ptune.n_r, ptune.n_theta)
     print(f"[bench] plain grid {grid[0]} x {grid[1]} (tuned in {t_tune:.1f} s)", file=sys.stderr, flush=True)
     hs = torch.cuda.Stream()   # the library's stream: eager calls and graph capture
     h = icrs.Handle(n_lens=2, n_limb=w.n_limb, n_r=grid[0], n_theta=grid[1], ray_precision=args.rays,
@@ -335,9 +342,10 @@ def main():
                  "status_counts": {name: int(np.sum((st & bit) != 0)) for name, bit in
                                    [("root_nonconv", 1), ("img_count", 2), ("cap_overflow", 4), ("clip", 8),
                                     ("nan", 16)]},
-                 "autotune": {"target": "median rel err <= 3e-5 vs FP64 512x1024 (converged, Richardson-trusted)",
-                              "calibration_epochs": ptune.n_calibration, "trusted": ptune.n_trusted,
-                              "tried": ptune.errors, "seconds": t_tune}}
+                 "autotune": None if ptune is None else {
+                     "target": "median rel err <= 3e-5 vs FP64 512x1024 (converged, Richardson-trusted)",
+                     "calibration_epochs": ptune.n_calibration, "trusted": ptune.n_trusted,
+                     "tried": ptune.errors, "seconds": t_tune}}
         line["batched+plain"] = {"value": w.n_epochs * args.steps / dt_bp, "ms_per_step": dt_bp * 1e3 / args.steps,
                                  "graph": True, "bitwise_equal_to_eager": bp_equal}
         line["plain_per_event"] = {"value": pe_rate, "events_timed": pe_events,
@@ -349,7 +357,12 @@ def main():
         # learned grid and gate: the autotuner's fastest pair whose error on the calibration
         # subset is no worse than the plain path's at the plain grid (median and p99)
         t_lt = time.perf_counter()
-        tune = autotune.tune_learned(w, model, plain_grid=grid, every=100)
+        if args.learned:
+            g, gate, slack = args.learned.split(":")
+            nr, nt = (int(x) for x in g.split("x"))
+            tune = autotune.LearnedTuneResult(nr, nt, float(gate), float(slack), tuple(grid), (None, None), [], 0, {})
+        else:
+            tune = autotune.tune_learned(w, model, plain_grid=grid, every=100)
         t_lt = time.perf_counter() - t_lt
         print(f"[bench] learned grid {tune.n_r} x {tune.n_theta}, gate {tune.gate_rel:g}/{tune.gate_slack:g} "
               f"(tuned in {t_lt:.1f} s)",

@@ -90,8 +90,11 @@ def tune(w: Workload, tol=3e-5, every=100, n_r_ref=512, n_theta_ref=1024, candid
 
 
 LEARNED_CANDIDATES = [(32, 128), (32, 192), (48, 192), (32, 256), (48, 256), (64, 192), (64, 256), (64, 320),
-                      (80, 320), (64, 384), (96, 320), (96, 384), (112, 448), (128, 384), (96, 512), (128, 448),
-                      (128, 512)]
+                      (80, 320), (64, 384), (96, 320), (96, 384), (64, 512), (112, 448), (128, 384), (96, 512),
+                      (128, 448), (128, 512), (64, 768), (96, 640), (96, 768), (128, 640), (64, 1024), (128, 768),
+                      (96, 1024), (160, 768), (128, 1024), (192, 768), (160, 1024), (192, 1024), (256, 768),
+                      (256, 1024)]
+LEARNED_GATES = ((1e-3, 0.0), (3e-3, 0.0), (1e-2, 0.0), (3e-3, 0.25), (3e-4, 0.0))
 
 
 @dataclasses.dataclass
@@ -108,7 +111,7 @@ class LearnedTuneResult:
 
 
 def tune_learned(w: Workload, model, plain_grid=(128, 512), every=100, n_r_ref=512, n_theta_ref=1024,
-                 candidates=LEARNED_CANDIDATES, gates=((1e-3, 0.0), (3e-3, 0.0), (1e-2, 0.0), (3e-3, 0.25)),
+                 candidates=LEARNED_CANDIDATES, gates=LEARNED_GATES,
                  verbose=False) -> LearnedTuneResult:
     """Fastest learned-path grid whose error on the calibration subset is no worse than the
     plain path's at plain_grid, in median and in the 99th percentile.  Both are measured

@@ -37,11 +37,15 @@ struct MapF64 {
   static constexpr bool kRefine = false;
   // up to 512 columns: three waves per SIMD (168 VGPRs, a few spills) beat two and four
   static constexpr int kMinWaves = JMAX <= 8 ? 3 : 1;
+  static constexpr bool kPhaseTable = false;
+  static constexpr int kPhaseEntries = 1;
   double cs[JMAX], sn[JMAX];
   Lens<N> L;
   c64 wc;
   double r;
-  __device__ void init_sector(const Lens<N>& lens, c64 w_c, const double* sp, int n_r, int n_theta, int lane) {
+  __device__ void init_sector(const Lens<N>& lens, c64 w_c, const double* sp, int n_r, int n_theta, int lane,
+                              const float2* phases) {
+    (void)phases;
     L = lens;
     wc = w_c;
     (void)n_r;
@@ -83,13 +87,32 @@ struct MapF32 {
   // spills per lane) runs ~10% faster than at three and ~40% faster than at two; five or six
   // waves spill more than they gain; the triple lens is best at three
   static constexpr int kMinWaves = N == 2 ? 4 : 3;
-  float gx[JMAX], gy[JMAX];  // e^{i theta_s} (e^{i dtheta_l} - 1) per owned column
+  // the column phases g_l = e^{i theta_s} (e^{i dtheta_l} - 1) live in a per-workgroup LDS
+  // table (JMAX x 64 entries): in registers they took 2 JMAX of the 128 VGPRs and were
+  // spilled to scratch and reloaded in the row loop
+  static constexpr bool kPhaseTable = true;
+  static constexpr int kPhaseEntries = JMAX * 64;
+  const float2* ph;          // this lane's column phases, stride 64
   float ux0, uy0;            // e^{i theta_s}
   float bx, by;              // w(z_s) - w_c
   float ax[N], ay[N], hx[N], hy[N];
   float r, ex, ey;           // row: r_i, (r_i - r_s) e^{i theta_s}
-  __device__ void init_sector(const Lens<N>& L, c64 wc, const double* sp, int n_r, int n_theta, int lane) {
+  // g_l for l = 0 .. 64 JMAX - 1, filled by the whole workgroup (threads t, t + 256, ...)
+  __device__ static void fill_phases(float2* tab, const double* sp, int n_theta) {
+    const double th_s = 0.5 * (sp[2] + sp[3]);
+    const double dth = (sp[3] - sp[2]) / n_theta;
+    double sa, ca;
+    sincos(th_s, &sa, &ca);
+    for (int l = (int)threadIdx.x; l < kPhaseEntries; l += (int)blockDim.x) {
+      // e^{i dt_l} - 1 with dt_l = (l + 1/2 - N_theta/2) dtheta
+      const c64 e = expm1_i((l + 0.5 - 0.5 * n_theta) * dth);
+      tab[l] = make_float2((float)(ca * e.x - sa * e.y), (float)(ca * e.y + sa * e.x));
+    }
+  }
+  __device__ void init_sector(const Lens<N>& L, c64 wc, const double* sp, int n_r, int n_theta, int lane,
+                              const float2* phases) {
     (void)n_r;
+    ph = phases + lane;
     const double r_s = 0.5 * (sp[0] + sp[1]);
     const double th_s = 0.5 * (sp[2] + sp[3]);
     const double dth = (sp[3] - sp[2]) / n_theta;
@@ -112,15 +135,7 @@ struct MapF32 {
     by = (float)wy;
     ux0 = (float)ca;
     uy0 = (float)sa;
-    // E_j = e^{i dt_j} - 1 with dt_j = (l + 1/2 - N_theta/2) dtheta, l = lane + 64 j
-    const c64 f = expm1_i(64.0 * dth);
-    c64 e = expm1_i((lane + 0.5 - 0.5 * n_theta) * dth);
-#pragma unroll
-    for (int j = 0; j < JMAX; ++j) {
-      gx[j] = (float)(ca * e.x - sa * e.y);
-      gy[j] = (float)(ca * e.y + sa * e.x);
-      e = e + f + e * f;
-    }
+    (void)n_theta;
   }
   __device__ void init_row(double r_i, double dr_i) {
     r = (float)r_i;
@@ -129,7 +144,8 @@ struct MapF32 {
   }
   // w - w_c = B + dz + conj(dz G), G = sum_k h_k / u_k (dz factored out of the lens sum)
   __device__ __forceinline__ float d2(int j) const {
-    const float dzx = fmaf(r, gx[j], ex), dzy = fmaf(r, gy[j], ey);
+    const float2 g = ph[64 * j];
+    const float dzx = fmaf(r, g.x, ex), dzy = fmaf(r, g.y, ey);
     float Gx = 0.0f, Gy = 0.0f;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
@@ -272,10 +288,10 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 // sum over the n queued items of r_i I (f(delta) - 1), lane k taking items k, k + 64, ...;
-// square roots and brightness are taken here, where every lane has an item.  One out-of-line
-// copy serves every call site.
+// square roots and brightness are taken here, where every lane has an item.  Inlined: as an
+// out-of-line call its register saves and restores cost 4-5% of the kernel.
 template <typename T>
-__device__ __attribute__((noinline)) double flush_crossings(const CrossQueue<T>* q, int n, T rho, T u1, T delta_c,
+__device__ __forceinline__ double flush_crossings(const CrossQueue<T>* q, int n, T rho, T u1, T delta_c,
                                                             T f_edge, T inv_rho2, T i_lin, T i_sqrt) {
   const int lane = threadIdx.x & 63;
   double s = 0.0;
@@ -306,7 +322,8 @@ template <int N, int JMAX, bool EXACT, typename MAP>
 __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L, c64 wc, double rho_d, double u1_d,
                                     double delta_c_d, int n_r, int n_theta, typename MAP::T* rowbuf_all,
                                     uint64_t* bwords, CrossQueue<typename MAP::T>* queues, double* wsum,
-                                    int* wclip, double ebound, double* flux_out, int* clip_out_bits) {
+                                    int* wclip, double ebound, float2* phase_sh, double* flux_out,
+                                    int* clip_out_bits) {
   using T = typename MAP::T;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -323,8 +340,12 @@ __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L
   const int last = n_theta - 1;
   const int jl = last >> 6, bl = last & 63;
 
+  if constexpr (MAP::kPhaseTable) {
+    MAP::fill_phases(phase_sh, sp, n_theta);
+    __syncthreads();
+  }
   MAP map;
-  map.init_sector(L, wc, sp, n_r, n_theta, lane);
+  map.init_sector(L, wc, sp, n_r, n_theta, lane, phase_sh);
 
   double acc = 0.0;
   int clip = 0;
@@ -425,78 +446,113 @@ __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L
       if (in_last) clip |= 8;
     }
     // boundary words (wave-uniform): inside nodes whose left (side 0) or right (side 1)
-    // neighbour is outside or beyond a non-periodic edge; their popcounts stay scalar and
-    // the words go to LDS, so a lane's rank search compares counts only and reads one word
-    int n_left = 0, n_all = 0;
-    int pc0[JMAX], pc1[JMAX];
+    // neighbour is outside or beyond a non-periodic edge.  Counted here with the chunk that
+    // holds each side's last item, so a row with one item per side -- an image crossed once,
+    // most rows -- finds both with scalar bit scans and queues them from lanes 0 and 1.
+    int n_left = 0, n_all = 0, jw0 = 0, jw1 = 0;
+    uint64_t ww0 = 0, ww1 = 0;
 #pragma unroll
     for (int j = 0; j < JMAX; ++j) {
-      pc0[j] = pc1[j] = 0;
       if ((EXACT || j < J) && m[j]) {  // an empty chunk has no boundary nodes
         const uint64_t w0 = boundary_word<JMAX>(m, j, J, 0, per, in_last, jl, bl);
         const uint64_t w1 = boundary_word<JMAX>(m, j, J, 1, per, in_last, jl, bl);
-        pc0[j] = __popcll(w0);
-        pc1[j] = __popcll(w1);
-        n_left += pc0[j];
-        n_all += pc1[j];
-        if (lane == 0) {
-          bwl[j] = w0;
-          bwl[JMAX + j] = w1;
+        n_left += __popcll(w0);
+        n_all += __popcll(w1);
+        if (w0) {
+          jw0 = j;
+          ww0 = w0;
+        }
+        if (w1) {
+          jw1 = j;
+          ww1 = w1;
         }
       }
     }
     n_all += n_left;
+    // the row buffer's stencil values are read across lanes below
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // queue the row's crossings, 64 per step, flushing when the queue would overflow
-    for (int base = 0; base < n_all; base += 64) {
-      if (qn + 64 > kQueue) {
+    // one item: its stencil (squared distances from the row buffer), row radius and flags
+    auto enqueue = [&](int side, int l, int slot) {
+      int fl = side;
+      if ((side == 0 && l == 0 && !per) || (side == 1 && l == last && !per)) {
+        fl |= 4;
+        cq->d[1][slot] = buf[l];
+      } else {
+        // side 0: crossing in (theta_{l-1}, theta_l), bracket p = l-1; side 1: in (theta_l, theta_{l+1}), p = l
+        const int pp = side ? l : (l == 0 ? last : l - 1);
+        const bool cubic = per || (pp - 1 >= 0 && pp + 2 <= last);
+        // neighbours of pp in [0, n_theta): wrap by one subtraction (periodic) or clamp
+        const int im1 = per ? (pp == 0 ? last : pp - 1) : max(pp - 1, 0);
+        const int ip1 = pp == last ? 0 : pp + 1;
+        const int ip2 = per ? (pp + 2 > last ? pp + 2 - n_theta : pp + 2) : min(pp + 2, last);
+        cq->d[0][slot] = buf[im1];
+        cq->d[1][slot] = buf[pp];
+        cq->d[2][slot] = buf[ip1];
+        cq->d[3][slot] = buf[ip2];
+        if (cubic) fl |= 2;
+      }
+      cq->r[slot] = r;
+      cq->f[slot] = fl;
+    };
+    if (n_left == 1 && n_all == 2) {
+      if (qn + 2 > kQueue) {
         wave_lds_sync();
         acc += flush_crossings<T>(cq, qn, rho, u1, delta_c, f_edge, inv_rho2, i_lin, i_sqrt);
         wave_lds_sync();
         qn = 0;
       }
-      const int k = base + lane;
-      if (k < n_all) {
-        const int side = k >= n_left ? 1 : 0;
-        int rem = side ? k - n_left : k;
-        int jw = 0;
+      const int l0 = 64 * jw0 + __builtin_ctzll(ww0), l1 = 64 * jw1 + __builtin_ctzll(ww1);
+      if (lane < 2) enqueue(lane, lane ? l1 : l0, qn + lane);
+      qn += 2;
+    } else if (n_all > 0) {
+      // general rows: the words go to LDS and each lane finds its item by comparing
+      // scalar popcounts, then reads one word
+      int pc0[JMAX], pc1[JMAX];
 #pragma unroll
-        for (int j = 0; j < JMAX; ++j) {
-          if (EXACT || j < J) {
-            const int pc = side ? pc1[j] : pc0[j];
-            if (rem >= 0 && rem < pc) jw = j;
-            if (rem >= 0) rem -= (rem < pc) ? (1 << 30) : pc;
+      for (int j = 0; j < JMAX; ++j) {
+        pc0[j] = pc1[j] = 0;
+        if ((EXACT || j < J) && m[j]) {
+          const uint64_t w0 = boundary_word<JMAX>(m, j, J, 0, per, in_last, jl, bl);
+          const uint64_t w1 = boundary_word<JMAX>(m, j, J, 1, per, in_last, jl, bl);
+          pc0[j] = __popcll(w0);
+          pc1[j] = __popcll(w1);
+          if (lane == 0) {
+            bwl[j] = w0;
+            bwl[JMAX + j] = w1;
           }
         }
-        uint64_t word = bwl[side * JMAX + jw];
-        rem += 1 << 30;  // rank of the node inside its word (< 64 whenever k < n_all)
-        for (int q = 0; q < rem && q < 64; ++q) word &= word - 1ull;
-        const int l = 64 * jw + __ffsll((unsigned long long)word) - 1;
-        const int slot = qn + lane;
-        int fl = side;
-        if ((side == 0 && l == 0 && !per) || (side == 1 && l == last && !per)) {
-          fl |= 4;
-          cq->d[1][slot] = buf[l];
-        } else {
-          // side 0: crossing in (theta_{l-1}, theta_l), bracket p = l-1; side 1: in (theta_l, theta_{l+1}), p = l
-          const int pp = side ? l : (l == 0 ? last : l - 1);
-          const bool cubic = per || (pp - 1 >= 0 && pp + 2 <= last);
-          // neighbours of pp in [0, n_theta): wrap by one subtraction (periodic) or clamp
-          const int im1 = per ? (pp == 0 ? last : pp - 1) : max(pp - 1, 0);
-          const int ip1 = pp == last ? 0 : pp + 1;
-          const int ip2 = per ? (pp + 2 > last ? pp + 2 - n_theta : pp + 2) : min(pp + 2, last);
-          cq->d[0][slot] = buf[im1];
-          cq->d[1][slot] = buf[pp];
-          cq->d[2][slot] = buf[ip1];
-          cq->d[3][slot] = buf[ip2];
-          if (cubic) fl |= 2;
-        }
-        cq->r[slot] = r;
-        cq->f[slot] = fl;
       }
-      qn += min(64, n_all - base);
+      wave_lds_sync();
+      // 64 items per step, flushing when the queue would overflow
+      for (int base = 0; base < n_all; base += 64) {
+        if (qn + 64 > kQueue) {
+          wave_lds_sync();
+          acc += flush_crossings<T>(cq, qn, rho, u1, delta_c, f_edge, inv_rho2, i_lin, i_sqrt);
+          wave_lds_sync();
+          qn = 0;
+        }
+        const int k = base + lane;
+        if (k < n_all) {
+          const int side = k >= n_left ? 1 : 0;
+          int rem = side ? k - n_left : k;
+          int jw = 0;
+#pragma unroll
+          for (int j = 0; j < JMAX; ++j) {
+            if (EXACT || j < J) {
+              const int pc = side ? pc1[j] : pc0[j];
+              if (rem >= 0 && rem < pc) jw = j;
+              if (rem >= 0) rem -= (rem < pc) ? (1 << 30) : pc;
+            }
+          }
+          uint64_t word = bwl[side * JMAX + jw];
+          rem += 1 << 30;  // rank of the node inside its word (< 64 whenever k < n_all)
+          for (int q = 0; q < rem && q < 64; ++q) word &= word - 1ull;
+          enqueue(side, 64 * jw + __ffsll((unsigned long long)word) - 1, qn + lane);
+        }
+        qn += min(64, n_all - base);
+      }
     }
     acc += r * (double)row;
     __builtin_amdgcn_wave_barrier();
@@ -544,6 +600,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MAP::kMinWa
   __shared__ int wclip[kWaves];
   __shared__ unsigned long long next_sh;
   __shared__ double ebound_sh[kMaxSectors];
+  __shared__ float2 phase_sh[MAP::kPhaseEntries];
 
   const unsigned long long total = w.items   ? (unsigned long long)(*w.n_items)
                                    : w.n_dev ? (unsigned long long)(*w.n_dev)
@@ -596,7 +653,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MAP::kMinWa
       double flux = 0.0;
       int c = 0;
       shoot_sector<N, JMAX, EXACT, MAP>(sp, per, L, wc, p[6], p[7], delta_c, n_r, n_theta, rowbuf, bwords, queues, wsum,
-                                        wclip, ebound, &flux, &c);
+                                        wclip, ebound, phase_sh, &flux, &c);
       if (threadIdx.x == 0) {
         partial[e * kMaxSectors + slot] = flux;
         clip_out[e * kMaxSectors + slot] = (uint8_t)c;
@@ -696,6 +753,7 @@ hipError_t launch_rays_n(const Batch& b, const SectorBuf& sec, const RayWork& w,
   }
   ICRS_RAYS_J(4)
   ICRS_RAYS_J(8)
+  ICRS_RAYS_J(12)
   ICRS_RAYS_J(16)
 #undef ICRS_RAYS_J
   return hipErrorInvalidValue;

@@ -12,9 +12,11 @@
   nll       the fit objective of App. B (marginalised NLL and its gradient through the
             reverse mode) on the cadence batch with the hybrid curve;
   fig2      the triple-lens gradient example of Fig. 2 (1000 epochs, 500 x 500, FP64):
-            forward and Jacobian time.
+            forward and Jacobian time;
+  kernels   one eager plain step and one eager learned step of the metric workload at
+            given grids (plain=NRxNT learned=NRxNT:GATE:SLACK), for counter and trace runs.
 
-    python -m paper_2510_02639_amd.perf [adjoint triple train serve hybrid nll fig2]
+    python -m paper_2510_02639_amd.perf [adjoint triple train serve hybrid nll fig2 kernels] [plain=..] [learned=..]
 
 Inputs are resident in HBM before each timed region; times are wall-clock around
 synchronised device work.
@@ -29,6 +31,18 @@ import numpy as np
 import torch
 
 from . import icrs, learned, serve, workloads
+
+# algorithmic flop-equivalents per node (FMA = 2, a reciprocal or square root = 1) and the
+# MI355X vector peaks they are held against
+FLOPS_RAY_FP32 = {2: 35.0, 3: 48.0}     # FP32 map, squared distance, brightness
+FLOPS_NODE_ADJOINT = {2: 85.0, 3: 122.0}  # FP64 map, d(d^2)/d(eps, a, w_c) and its accumulation
+PEAK = {"fp32": 157.3, "fp64": 78.6, "bf16": 2500.0}
+
+
+def _roofline(units, flops_per_unit, seconds, peak_key):
+    achieved = units * flops_per_unit / seconds / 1e12
+    return {"bound": "alu" if peak_key != "bf16" else "mfma", "achieved": achieved, "peak": PEAK[peak_key],
+            "unit": "TFLOP/s", "frac": achieved / PEAK[peak_key], "flops_per_unit": flops_per_unit}
 
 
 def _timed(fn, reps=3):
@@ -55,6 +69,7 @@ def adjoint():
     return {"measure": "adjoint", "workload": "binary-fit-rho1e-3", "n_events": w.n_events, "n_epochs": w.n_epochs,
             "grid": [128, 512], "forward_epochs_per_s": w.n_epochs / dt_f, "vjp_epochs_per_s": w.n_epochs / dt_b,
             "vjp_ms": dt_b * 1e3, "vjp_rays_per_s": rays / dt_b, "vjp_precision": "f64",
+            "vjp_roofline": _roofline(rays, FLOPS_NODE_ADJOINT[2], dt_b, "fp64"),
             "grad_finite": bool(torch.isfinite(grad).all().item())}
 
 
@@ -69,8 +84,11 @@ def triple():
     prof = h.get_profile()
     h.set_profiling(False)
     per_call = {k: prof[k] / 4 for k in ("ms_centre", "ms_limb_sectors", "ms_rays", "ms_finalize")}
+    main = _roofline(prof["n_main_rays"], FLOPS_RAY_FP32[3], prof["ms_rays_main"] * 1e-3, "fp32")
+    main["kernel"] = "rays_kernel<3, 8, true, MapF32<3, 8>> (main pass)"
     return {"measure": "triple", "workload": "triple-rho1e-3", "n_events": w.n_events, "n_epochs": w.n_epochs,
             "grid": [128, 512], "epochs_per_s": w.n_epochs / dt, "ms_per_call": dt * 1e3, "breakdown_ms": per_call,
+            "rays_roofline": main, "limb_points_per_s": w.n_epochs * 128 / (per_call["ms_limb_sectors"] * 1e-3),
             "sectors_per_epoch": prof["n_sector_passes"] / max(prof["n_epochs"], 1)}
 
 
@@ -90,7 +108,8 @@ def train():
     return {"measure": "train", "rows": int(x.shape[0]), "steps": 1000, "batch": 16384,
             "train_rows_per_s": 1000 * 16384 / dt, "final_loss": losses[-1][1],
             "inference_rows_per_s": pred_rows / dt_inf,
-            "inference_tflops": pred_rows * flops_row / dt_inf / 1e12, "mfma_peak_bf16_tflops": 2500.0}
+            "inference_tflops": pred_rows * flops_row / dt_inf / 1e12, "mfma_peak_bf16_tflops": 2500.0,
+            "inference_roofline": _roofline(pred_rows, flops_row, dt_inf, "bf16")}
 
 
 def serving(seconds=60.0, rate=200.0):
@@ -159,10 +178,40 @@ def fig2():
             "sectors_per_epoch": float(ns.float().mean().item()), "precision": "f64"}
 
 
+def kernels(plain="256x1024", learned_cfg="192x768:0.01:0"):
+    """One eager plain step and one eager learned step on the 2048-event metric workload at
+    the given grids (for counter and trace runs: no autotuning, no graph, nothing else)."""
+    w = workloads.metric_workload(2048)
+    pr, pt = (int(x) for x in plain.split("x"))
+    g, gate, slack = learned_cfg.split(":")
+    lr, lt = (int(x) for x in g.split("x"))
+    h = icrs.Handle(n_lens=2, n_limb=w.n_limb, n_r=pr, n_theta=pt, ray_precision="fp32", root_precision="fp32")
+    t = torch.tensor(w.t, device="cuda")
+    ws = h.learned_workspace(w.n_events, w.n_epochs)
+    mag = torch.empty(w.n_epochs, dtype=torch.float64, device="cuda")
+    st = torch.empty(w.n_epochs, dtype=torch.int32, device="cuda")
+    model = learned.BoundsModel.load()
+    h.set_profiling(True)
+    h.get_profile(reset=True)
+    h.magnification(w.params, w.offsets, t, mag, st, ws)
+    torch.cuda.synchronize()
+    pp = h.get_profile(reset=True)
+    h.magnification_learned(w.params, w.offsets, t, model, mag, st, ws, n_r=lr, n_theta=lt, gate_rel=float(gate),
+                            gate_slack=float(slack), stats=False)
+    torch.cuda.synchronize()
+    lp = h.get_profile()
+    h.set_profiling(False)
+    return {"measure": "kernels", "workload": w.name, "plain_grid": [pr, pt], "learned": [lr, lt, float(gate),
+            float(slack)], "plain_main_ms": pp["ms_rays_main"], "plain_main_rays": pp["n_main_rays"],
+            "learned_main_ms": lp["ms_rays_learned"], "learned_main_rays": lp["n_learned_rays"]}
+
+
 def main(argv):
-    which = argv or ["adjoint", "triple", "train", "serve", "hybrid", "nll", "fig2"]
+    which = [a for a in argv if "=" not in a] or ["adjoint", "triple", "train", "serve", "hybrid", "nll", "fig2"]
+    opts = dict(a.split("=", 1) for a in argv if "=" in a)
     fns = {"adjoint": adjoint, "triple": triple, "train": train, "serve": serving, "hybrid": hybrid, "nll": nll,
-           "fig2": fig2}
+           "fig2": fig2,
+           "kernels": lambda: kernels(opts.get("plain", "256x1024"), opts.get("learned", "192x768:0.01:0"))}
     for k in which:
         print(json.dumps(fns[k]()), flush=True)
 

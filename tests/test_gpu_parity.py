@@ -89,17 +89,20 @@ def test_config1_sectors_match_oracle():
         assert np.allclose(sec[e, :k], ref["sectors"][e, :k], rtol=1e-12, atol=1e-12), e
 
 
-def test_given_grid_fp64_matches_oracle_quadrature():
-    """Given-grid mode isolates the ray kernel: the oracle's own sectors in, same rule out."""
+@pytest.mark.parametrize("n_r,n_theta", [(64, 256), (48, 768)])
+def test_given_grid_fp64_matches_oracle_quadrature(n_r, n_theta):
+    """Given-grid mode isolates the ray kernel: the oracle's own sectors in, same rule out
+    (FP64 map; 4 and 12 column chunks per lane)."""
     w = W.config1()
     ref = _oracle(w)
-    h = icrs.Handle(n_lens=2, n_limb=64, n_r=64, n_theta=256)
+    h = icrs.Handle(n_lens=2, n_limb=64, n_r=n_r, n_theta=n_theta)
     t = torch.tensor(w.t, device="cuda")
     mag, st = h.magnification_given(w.params, w.offsets, t, torch.tensor(ref["sectors"], device="cuda"),
                                     torch.tensor(ref["periodic"], device="cuda"),
                                     torch.tensor(ref["nsec"], device="cuda"))
     torch.cuda.synchronize()
-    omag, ost = O.magnification_given(2, w.params[0], w.t, ref["sectors"], ref["periodic"], ref["nsec"], 64, 256)
+    omag, ost = O.magnification_given(2, w.params[0], w.t, ref["sectors"], ref["periodic"], ref["nsec"], n_r,
+                                      n_theta)
     rel = np.abs(mag.cpu().numpy() / omag - 1)
     _report("given fp64", rel)
     assert np.all(rel <= FP64_TOL)
@@ -315,11 +318,11 @@ def _planetary_subset(n_events=6, per_event=6, rho=None, seed=2):
                       128, 128, 512, "fp32", "fp32")
 
 
-@pytest.mark.parametrize("n_r,n_theta", [(128, 512), (64, 256), (48, 320), (32, 1024)])
+@pytest.mark.parametrize("n_r,n_theta", [(128, 512), (64, 256), (48, 320), (48, 768), (40, 704), (32, 1024)])
 def test_fp32_rays_given_grid_planetary(n_r, n_theta):
     """FP32 ray loop (anchor-relative) on the oracle's own sectors: 3e-5 of the FP64 oracle.
-    The grids cover every kernel shape: 4, 8 (with a partial chunk at 320) and 16 column
-    chunks per lane."""
+    The grids cover every kernel shape: 4, 8 (with a partial chunk at 320), 12 (with a
+    partial chunk at 704) and 16 column chunks per lane."""
     w = _planetary_subset(rho=1e-3)
     ref = _oracle(w)
     h = icrs.Handle(n_lens=2, n_limb=128, n_r=n_r, n_theta=n_theta, ray_precision="fp32", root_precision="fp32")
