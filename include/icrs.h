@@ -378,6 +378,23 @@ icrs_status icrs_point_jacobian(icrs_handle* h, int64_t n_events, const double* 
                                 const int64_t* epoch_offsets, int64_t n_epochs, const double* t,
                                 double* a_ps, double* jac, uint32_t* status, void* workspace,
                                 size_t workspace_bytes);
+/* Grid-free reference magnification (Sec. 2.2: the finite-source magnification is the
+ * brightness-weighted mean of the point-source magnification, eq. amp_point, over the source
+ * disk), for checking and tuning the ray quadrature's accuracy.  n_x Gauss-Legendre nodes in
+ * x on [0, pi/2] with r = sin x (1 <= n_x <= 64) times n_phi midpoint angles (1 <= n_phi <=
+ * 4096) per epoch, each a point-source solve in FP64 started from the centre's roots, linear
+ * limb darkening.  The mean is a valid quadrature only while no caustic crosses the disk:
+ * count_changes[e] counts the nodes whose image count differs from the centre's or whose solve
+ * set a status bit (plus one when the centre's solve did); use mag[e] only where it is 0.  Events and epochs as for
+ * icrs_magnification (params/epoch_offsets host, t device); mag [n_epochs] float64 and
+ * count_changes [n_epochs] int32 are device arrays written on the handle's stream; workspace
+ * as for icrs_magnification (icrs_workspace_bytes).  Cost: n_x n_phi point-source solves per
+ * epoch.  Errors: EINVAL (bad sizes or pointers), ENOMEM (workspace too small). */
+icrs_status icrs_disk_magnification(icrs_handle* h, int64_t n_events, const double* params,
+                                    const int64_t* epoch_offsets, int64_t n_epochs, const double* t, int n_x,
+                                    int n_phi, double* mag, int32_t* count_changes, void* workspace,
+                                    size_t workspace_bytes);
+
 /* Reverse mode of the hybrid curve: status (DEVICE [n_epochs]) from the forward call selects
  * the rule per epoch -- ICRS_ST_POINT epochs are differentiated through their images, the
  * others on their frozen sectors (as icrs_magnification_vjp; point epochs must have

@@ -834,6 +834,24 @@ icrs_status icrs_point_jacobian(icrs_handle* h, int64_t n_events, const double* 
                                                 status, nullptr, 0u, h->stream));
 }
 
+icrs_status icrs_disk_magnification(icrs_handle* h, int64_t n_events, const double* params,
+                                    const int64_t* epoch_offsets, int64_t n_epochs, const double* t, int n_x,
+                                    int n_phi, double* mag, int32_t* count_changes, void* workspace,
+                                    size_t workspace_bytes) {
+  if (!h || !events_ok(h->cfg, n_events, params, epoch_offsets, n_epochs)) return ICRS_EINVAL;
+  if (n_x < 1 || n_x > 64 || n_phi < 1 || n_phi > 4096) return ICRS_EINVAL;
+  if (n_epochs > 0 && (!t || !mag || !count_changes)) return ICRS_EINVAL;
+  Views v;
+  const icrs_status ps = prepare(h, n_events, params, epoch_offsets, n_epochs, t, workspace, workspace_bytes, &v);
+  if (ps != ICRS_OK || n_epochs == 0) return ps;
+  // centre images in FP64 (their roots warm-start every disk node); the partial-flux area
+  // of the workspace holds the centre's status words
+  ICRS_TRY(icrs::launch_centre_images(h->cfg.n_lens, 0, v.b, nullptr, count_changes, nullptr, (uint32_t*)v.partial,
+                                      h->stream, v.roots));
+  return hip_status(icrs::launch_disk_mag(h->cfg.n_lens, n_x, n_phi, v.b, count_changes, (const uint32_t*)v.partial,
+                                          v.roots, mag, h->stream));
+}
+
 icrs_status icrs_hybrid_vjp(icrs_handle* h, int64_t n_events, const double* params, const int64_t* epoch_offsets,
                             int64_t n_epochs, const double* t, const uint32_t* status, const double* sectors,
                             const uint8_t* periodic, const int32_t* n_sectors, const double* cotangent, double* grad,

@@ -99,6 +99,11 @@ hipError_t launch_hybrid_select(int n_lens, int root_fp32, int n_check, double g
                                 hipStream_t s);
 // A_ps and dA_ps/dparams [n_epochs][11] of every epoch (with only_status, only epochs whose
 // status_in has that bit); status_out (or null) gets the image-finding bits.
+// Grid-free disk reference: cn_changes holds each epoch's centre image count on entry and
+// the number of disk nodes whose image count or status differs (plus one for a flagged
+// centre) on return.
+hipError_t launch_disk_mag(int n_lens, int n_x, int n_phi, const Batch& b, int32_t* cn_changes,
+                           const uint32_t* centre_status, const double* roots, double* mag, hipStream_t s);
 hipError_t launch_point_jacobian(int n_lens, int root_fp32, const Batch& b, double* a_ps, double* jac,
                                  uint32_t* status_out, const uint32_t* status_in, uint32_t only_status,
                                  hipStream_t s);

@@ -139,6 +139,8 @@ def lib():
     L.icrs_magnification_hybrid.restype = ctypes.c_int
     L.icrs_point_jacobian.argtypes = [vp, i64, vp, vp, i64, vp, vp, vp, vp, vp, sz]
     L.icrs_point_jacobian.restype = ctypes.c_int
+    L.icrs_disk_magnification.argtypes = [vp, i64, vp, vp, i64, vp, ctypes.c_int, ctypes.c_int, vp, vp, vp, sz]
+    L.icrs_disk_magnification.restype = ctypes.c_int
     L.icrs_hybrid_vjp.argtypes = [vp, i64, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz]
     L.icrs_hybrid_vjp.restype = ctypes.c_int
     L.icrs_marginal_nll_workspace_bytes.argtypes = [i64]
@@ -160,7 +162,7 @@ EXPORTED = ["icrs_default_config", "icrs_create", "icrs_destroy", "icrs_workspac
             "icrs_learned_workspace_bytes", "icrs_magnification_learned", "icrs_run_learned",
             "icrs_default_hybrid_config", "icrs_hybrid_workspace_bytes", "icrs_magnification_hybrid",
             "icrs_point_jacobian", "icrs_hybrid_vjp", "icrs_marginal_nll_workspace_bytes", "icrs_marginal_nll",
-            "icrs_status_string"]
+            "icrs_disk_magnification", "icrs_status_string"]
 ST_LEARNED, ST_FALLBACK, ST_IMG_RECHECK, ST_BAD_SECTORS, ST_POINT = 128, 256, 512, 1024, 2048
 ICRS_MAX_EPOCHS = 1 << 27
 NOALLOC_SCRATCH_BYTES = 64 << 20
@@ -355,6 +357,20 @@ class Handle:
         _check(lib().icrs_point_jacobian(self._h, p.shape[0], _ptr(p), _ptr(o), n, _ptr(t), _ptr(a), _ptr(J),
                                          _ptr(st), _ptr(ws), ws.numel()), "icrs_point_jacobian")
         return a, J, st
+
+    def disk_magnification(self, params, offsets, t, n_x=16, n_phi=96, workspace=None):
+        """Grid-free reference (mag [E], count_changes [E] int32), CUDA: the brightness-weighted
+        mean of the point-source magnification over the source disk; valid where
+        count_changes == 0 (no caustic crosses the disk)."""
+        p, o = _host_events(params, offsets)
+        t = _dev(t, torch.float64)
+        n = t.numel()
+        mag = torch.empty(n, dtype=torch.float64, device=t.device)
+        ch = torch.empty(n, dtype=torch.int32, device=t.device)
+        ws = workspace if workspace is not None else self.workspace(p.shape[0], n)
+        _check(lib().icrs_disk_magnification(self._h, p.shape[0], _ptr(p), _ptr(o), n, _ptr(t), int(n_x), int(n_phi),
+                                             _ptr(mag), _ptr(ch), _ptr(ws), ws.numel()), "icrs_disk_magnification")
+        return mag, ch
 
     def hybrid_vjp(self, params, offsets, t, status, sectors, periodic, nsec, cotangent=None, jac=False,
                    workspace=None):

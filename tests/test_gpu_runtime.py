@@ -10,7 +10,7 @@ pytestmark = pytest.mark.gpu
 
 def test_autotuner_picks_the_cheapest_grid_meeting_its_tolerance():
     w = W.metric_workload(8)
-    res = autotune.tune(w, tol=3e-4, every=40, n_r_ref=256, n_theta_ref=1024,
+    res = autotune.tune(w, tol=3e-4, every=40, n_r_ref=256, n_theta_ref=1024, stat="max", reference="grid",
                         candidates=[(32, 128), (64, 256), (128, 512), (256, 1024)])
     print(res, flush=True)
     assert res.n_trusted > 0
@@ -22,6 +22,23 @@ def test_autotuner_picks_the_cheapest_grid_meeting_its_tolerance():
         assert chosen == tried[-1]
         assert all(e[2] > res.tol for e in res.errors[:-1])
     assert res.ray_precision in ("fp32", "fp64") and all(v > 0 for v in res.timings.values())
+
+
+def test_autotuner_against_the_disk_reference_stops_at_the_first_grid_within_tol():
+    """Default mode: errors against the grid-free disk quadrature on the calibration epochs
+    where no caustic crosses the disk; the chosen grid is the first (cheapest) whose median
+    error is within tol, every cheaper one above it."""
+    w = W.metric_workload(8)
+    cands = [(32, 128), (64, 256), (128, 512), (256, 1024)]
+    res = autotune.tune(w, tol=3e-4, every=20, candidates=cands)
+    print(res.n_trusted, res.errors, flush=True)
+    assert res.n_trusted >= 20
+    med = [e[4] for e in res.errors]
+    if med[-1] <= res.tol:
+        assert (res.n_r, res.n_theta) == tuple(res.errors[-1][:2])
+        assert all(m > res.tol for m in med[:-1])
+    else:
+        assert (res.n_r, res.n_theta) == (256, 1024) and len(med) == len(cands)
 
 
 def test_serving_loop_serves_every_request_and_matches_direct_calls():
