@@ -87,12 +87,15 @@ struct MapF32 {
   // spills per lane) runs ~10% faster than at three and ~40% faster than at two; five or six
   // waves spill more than they gain; the triple lens is best at three
   static constexpr int kMinWaves = N == 2 ? 4 : 3;
-  // the column phases g_l = e^{i theta_s} (e^{i dtheta_l} - 1) live in a per-workgroup LDS
-  // table (JMAX x 64 entries): in registers they took 2 JMAX of the 128 VGPRs and were
-  // spilled to scratch and reloaded in the row loop
-  static constexpr bool kPhaseTable = true;
-  static constexpr int kPhaseEntries = JMAX * 64;
-  const float2* ph;          // this lane's column phases, stride 64
+  // the column phases g_l = e^{i theta_s} (e^{i dtheta_l} - 1): from 12 chunks per lane up
+  // they live in a per-workgroup LDS table (JMAX x 64 entries) -- in registers they took
+  // 2 JMAX of the 128 VGPRs and were spilled and reloaded in every row; below, registers
+  // are faster (the table's read latency cost 4% at 8 chunks)
+  static constexpr bool kPhaseTable = JMAX >= 12;
+  static constexpr int kPhaseEntries = kPhaseTable ? JMAX * 64 : 1;
+  static constexpr int kPhaseRegs = kPhaseTable ? 1 : JMAX;
+  const float2* ph;          // this lane's column phases in the table, stride 64
+  float gx[kPhaseRegs], gy[kPhaseRegs];  // or in registers
   float ux0, uy0;            // e^{i theta_s}
   float bx, by;              // w(z_s) - w_c
   float ax[N], ay[N], hx[N], hy[N];
@@ -135,7 +138,20 @@ struct MapF32 {
     by = (float)wy;
     ux0 = (float)ca;
     uy0 = (float)sa;
-    (void)n_theta;
+    if constexpr (!kPhaseTable) {
+      // E_j = e^{i dt_j} - 1 with dt_j = (l + 1/2 - N_theta/2) dtheta, l = lane + 64 j, by
+      // the recurrence E_{j+1} = E_j + F + E_j F, F = e^{i 64 dtheta} - 1 (FP64)
+      const c64 f = expm1_i(64.0 * dth);
+      c64 e = expm1_i((lane + 0.5 - 0.5 * n_theta) * dth);
+#pragma unroll
+      for (int j = 0; j < kPhaseRegs; ++j) {
+        gx[j] = (float)(ca * e.x - sa * e.y);
+        gy[j] = (float)(ca * e.y + sa * e.x);
+        e = e + f + e * f;
+      }
+    } else {
+      (void)dth;
+    }
   }
   __device__ void init_row(double r_i, double dr_i) {
     r = (float)r_i;
@@ -144,7 +160,12 @@ struct MapF32 {
   }
   // w - w_c = B + dz + conj(dz G), G = sum_k h_k / u_k (dz factored out of the lens sum)
   __device__ __forceinline__ float d2(int j) const {
-    const float2 g = ph[64 * j];
+    float2 g;
+    if constexpr (kPhaseTable) {
+      g = ph[64 * j];
+    } else {
+      g = make_float2(gx[j], gy[j]);
+    }
     const float dzx = fmaf(r, g.x, ex), dzy = fmaf(r, g.y, ey);
     float Gx = 0.0f, Gy = 0.0f;
 #pragma unroll
@@ -337,7 +358,7 @@ __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L
   const double dr = (r_hi - r_lo) / n_r;
   const double dth = (sp[3] - sp[2]) / n_theta;
   const T f_edge = edge_factor<T>(T(0.5), u1, delta_c) - T(1);  // neighbour beyond a sector edge
-  const int last = n_theta - 1;
+  const int last = (EXACT ? 64 * JMAX : n_theta) - 1;  // a compile-time constant for exact grids
   const int jl = last >> 6, bl = last & 63;
 
   if constexpr (MAP::kPhaseTable) {
@@ -486,7 +507,7 @@ __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L
         // neighbours of pp in [0, n_theta): wrap by one subtraction (periodic) or clamp
         const int im1 = per ? (pp == 0 ? last : pp - 1) : max(pp - 1, 0);
         const int ip1 = pp == last ? 0 : pp + 1;
-        const int ip2 = per ? (pp + 2 > last ? pp + 2 - n_theta : pp + 2) : min(pp + 2, last);
+        const int ip2 = per ? (pp + 2 > last ? pp + 1 - last : pp + 2) : min(pp + 2, last);
         cq->d[0][slot] = buf[im1];
         cq->d[1][slot] = buf[pp];
         cq->d[2][slot] = buf[ip1];

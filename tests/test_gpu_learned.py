@@ -163,6 +163,37 @@ def test_network_gain_over_check_points_alone(small_model):
     assert st_n["n_fallback"] + passes_n < st_c["n_fallback"] + passes_c
 
 
+def test_network_gain_over_the_plain_method():
+    """What the shipped network gains over the method without it, against the truth (the
+    device's grid-free disk quadrature, on the epochs where no caustic crosses the disk): the
+    learned path at 64 x 256 with a 3e-3 gate is at least as accurate by its median as the
+    plain path at the configured 128 x 512, and its main ray passes (learned boxes plus the
+    plain pass over the epochs it hands back) map at most half as many nodes."""
+    from paper_2510_02639_amd import autotune
+    w = W.metric_workload(64).sample_epochs(10)
+    ref, trusted = autotune.disk_reference(w)
+    assert trusted.sum() >= 0.8 * w.n_epochs
+    t = torch.tensor(w.t, device="cuda")
+    h = icrs.Handle(n_lens=2, n_limb=128, n_r=128, n_theta=512, ray_precision="fp32", root_precision="fp32")
+    model = learned.BoundsModel.load()
+    h.set_profiling(True)
+    h.get_profile(reset=True)
+    mp, _ = h.magnification(w.params, w.offsets, t)
+    pp = h.get_profile(reset=True)
+    ml, _, st = h.magnification_learned(w.params, w.offsets, t, model, n_r=64, n_theta=256, gate_rel=3e-3)
+    lp = h.get_profile(reset=True)
+    h.set_profiling(False)
+    e_plain = np.abs(mp.cpu().numpy()[trusted] / ref[trusted] - 1.0)
+    e_learn = np.abs(ml.cpu().numpy()[trusted] / ref[trusted] - 1.0)
+    nodes_plain = pp["n_main_rays"]
+    nodes_learn = lp["n_learned_rays"] + lp["n_main_rays"]
+    print(f"plain 128x512: median {np.median(e_plain):.2e} p99 {np.quantile(e_plain, 0.99):.2e}, "
+          f"{nodes_plain:.3e} nodes; learned 64x256: median {np.median(e_learn):.2e} "
+          f"p99 {np.quantile(e_learn, 0.99):.2e}, {nodes_learn:.3e} nodes, {st}", flush=True)
+    assert np.median(e_learn) <= np.median(e_plain)
+    assert nodes_learn <= 0.5 * nodes_plain
+
+
 def test_learned_results_do_not_depend_on_workspace_contents():
     """The learned path with the shipped network on a sample of the 2048-event workload: a
     workspace prefilled with different byte patterns gives bitwise identical magnifications,
