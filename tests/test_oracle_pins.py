@@ -473,6 +473,39 @@ def test_dual_jacobian_matches_frozen_central_differences(u1, hs, tol):
         assert np.max(np.abs(jac[:, k] - fd)) <= tol * scale, (k, np.max(np.abs(jac[:, k] - fd)) / scale)
 
 
+def test_dual_jacobian_matches_frozen_central_differences_planetary_rho1e3():
+    """The same pin in the differentiable-fit regime: a planetary event of the fit workload
+    (rho = 1e-3, q = 1e-4) at epochs within 3 rho tE of its caustic crossings, 128 x 512
+    grids: central differences of the frozen-structure primal meet the dual Jacobian.
+    Parameters 0-6 on a uniform source (with limb darkening, nodes just inside the limb carry
+    sqrt(1 - x^2) brightness, whose curvature there defeats any step that survives
+    rounding); the limb-darkening coefficient, on which the primal is linear, with u = 0.5.
+    The step is 1e-8: a node next to the planet moves so fast with s, q, alpha, t0 and tE
+    that at 1e-6 the frozen crossings leave their brackets, and at 1e-8 the primal's FP64
+    rounding (~1e-15 of A ~ 5) against derivatives of ~1e-3 limits those five columns to a
+    few 1e-3; u0, rho and u meet 1e-5."""
+    from paper_2510_02639_amd import workloads as W
+    w = W.binary_batch(40, 4, rho_fixed=1e-3, n_epochs_fixed=3000)
+    seg = w.t[w.offsets[1]:w.offsets[2]]
+    t = seg[np.linspace(0, seg.size - 1, 3).astype(int)]
+    for u1, ks, hs in ((0.0, range(7), 1e-8), (0.5, [7], 1e-6)):
+        p = w.params[1].copy()
+        p[7] = u1
+        r = O.magnification(2, p, t, n_limb=128, n_r=128, n_theta=512)
+        mag, jac = O.jacobian_given(2, p, t, r["sectors"], r["periodic"], r["nsec"], n_r=128, n_theta=512)
+        assert np.allclose(mag, r["mag"], rtol=1e-13, atol=0)
+        for k in ks:
+            h = hs * (abs(p[k]) if k in (0, 1, 6) else max(abs(p[k]), 1.0))
+            pp, pm = p.copy(), p.copy()
+            pp[k] += h
+            pm[k] -= h
+            args = (t, r["sectors"], r["periodic"], r["nsec"], 128, 512)
+            fd = (O.magnification_frozen(2, pp, p, *args) - O.magnification_frozen(2, pm, p, *args)) / (2 * h)
+            scale = np.abs(jac[:, k]).max()
+            tol = 1e-2 if k in (0, 1, 3, 4, 5) else 1e-5
+            assert np.max(np.abs(jac[:, k] - fd)) <= tol * scale, (k, np.max(np.abs(jac[:, k] - fd)) / scale)
+
+
 def test_triple_jacobian_matches_frozen_central_differences():
     p = O.params(s=1.1, q=0.5, u0=0.02, alpha=np.radians(60), t0=0, tE=10, rho=0.02, u1=0.0, q3=0.03, r3=1.24,
                  psi=np.radians(76))
