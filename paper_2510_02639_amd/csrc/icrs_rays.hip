@@ -466,30 +466,24 @@ __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L
       if (m[0] & 1ull) clip |= 4;
       if (in_last) clip |= 8;
     }
-    // boundary words (wave-uniform): inside nodes whose left (side 0) or right (side 1)
-    // neighbour is outside or beyond a non-periodic edge.  Counted here with the chunk that
-    // holds each side's last item, so a row with one item per side -- an image crossed once,
-    // most rows -- finds both with scalar bit scans and queues them from lanes 0 and 1.
-    int n_left = 0, n_all = 0, jw0 = 0, jw1 = 0;
-    uint64_t ww0 = 0, ww1 = 0;
+    // Boundary items: inside nodes whose left (side 0) or right (side 1) neighbour is outside
+    // or beyond a non-periodic edge.  A row whose inside nodes form one run -- an image
+    // crossed once, most rows -- has exactly one per side, its first and last inside column,
+    // found from the masks' population count and two bit scans (all scalar) and queued from
+    // lanes 0 and 1.  A run that touches both ends of a periodic ring may wrap around and
+    // takes the general path with the other rows.
+    int n_in = 0, first = 0, lastc = 0;
+#pragma unroll
+    for (int j = JMAX - 1; j >= 0; --j)
+      if ((EXACT || j < J) && m[j]) first = 64 * j + (int)__builtin_ctzll(m[j]);
 #pragma unroll
     for (int j = 0; j < JMAX; ++j) {
-      if ((EXACT || j < J) && m[j]) {  // an empty chunk has no boundary nodes
-        const uint64_t w0 = boundary_word<JMAX>(m, j, J, 0, per, in_last, jl, bl);
-        const uint64_t w1 = boundary_word<JMAX>(m, j, J, 1, per, in_last, jl, bl);
-        n_left += __popcll(w0);
-        n_all += __popcll(w1);
-        if (w0) {
-          jw0 = j;
-          ww0 = w0;
-        }
-        if (w1) {
-          jw1 = j;
-          ww1 = w1;
-        }
+      if ((EXACT || j < J) && m[j]) {
+        n_in += __popcll(m[j]);
+        lastc = 64 * j + 63 - (int)__builtin_clzll(m[j]);
       }
     }
-    n_all += n_left;
+    const bool one_run = n_in == lastc - first + 1 && !(per && (first == 0 || lastc == last));
     // the row buffer's stencil values are read across lanes below
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -517,34 +511,37 @@ __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L
       cq->r[slot] = r;
       cq->f[slot] = fl;
     };
-    if (n_left == 1 && n_all == 2) {
+    if (one_run) {
       if (qn + 2 > kQueue) {
         wave_lds_sync();
         acc += flush_crossings<T>(cq, qn, rho, u1, delta_c, f_edge, inv_rho2, i_lin, i_sqrt);
         wave_lds_sync();
         qn = 0;
       }
-      const int l0 = 64 * jw0 + __builtin_ctzll(ww0), l1 = 64 * jw1 + __builtin_ctzll(ww1);
-      if (lane < 2) enqueue(lane, lane ? l1 : l0, qn + lane);
+      if (lane < 2) enqueue(lane, lane ? lastc : first, qn + lane);
       qn += 2;
-    } else if (n_all > 0) {
-      // general rows: the words go to LDS and each lane finds its item by comparing
-      // scalar popcounts, then reads one word
+    } else {
+      // general rows: boundary words per chunk (their popcounts scalar, the words in LDS);
+      // lane k finds the k-th item by comparing counts and reading one word
+      int n_left = 0, n_all = 0;
       int pc0[JMAX], pc1[JMAX];
 #pragma unroll
       for (int j = 0; j < JMAX; ++j) {
         pc0[j] = pc1[j] = 0;
-        if ((EXACT || j < J) && m[j]) {
+        if ((EXACT || j < J) && m[j]) {  // an empty chunk has no boundary nodes
           const uint64_t w0 = boundary_word<JMAX>(m, j, J, 0, per, in_last, jl, bl);
           const uint64_t w1 = boundary_word<JMAX>(m, j, J, 1, per, in_last, jl, bl);
           pc0[j] = __popcll(w0);
           pc1[j] = __popcll(w1);
+          n_left += pc0[j];
+          n_all += pc1[j];
           if (lane == 0) {
             bwl[j] = w0;
             bwl[JMAX + j] = w1;
           }
         }
       }
+      n_all += n_left;
       wave_lds_sync();
       // 64 items per step, flushing when the queue would overflow
       for (int base = 0; base < n_all; base += 64) {
