@@ -403,6 +403,8 @@ __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L
     map.init_row(r, (i + 0.5 - 0.5 * n_r) * dr);
     uint64_t m[JMAX];
     uint64_t any = 0;
+    // the row's inside nodes: count, first and last column (for the one-run test below)
+    int n_in = 0, first = 0, lastc = 0;
     T row = T(0);
     T mind = T(__builtin_inf());  // closest |d^2 - rho^2| among the lane's nodes of the row
 #pragma unroll
@@ -421,6 +423,9 @@ __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L
           // compiler computes the brightness for every chunk and selects
           __asm__ volatile("");
           row += in ? brightness<T>(d2, inv_rho2, i_lin, i_sqrt) : T(0);
+          if (n_in == 0) first = 64 * j + (int)__builtin_ctzll(m[j]);
+          n_in += __popcll(m[j]);
+          lastc = 64 * j + 63 - (int)__builtin_clzll(m[j]);
         }
       }
     }
@@ -446,11 +451,17 @@ __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L
                  (old < rho2 ? brightness<T>(old, inv_rho2, i_lin, i_sqrt) : T(0));
         }
         any = 0;
+        n_in = 0;
 #pragma unroll
         for (int j = 0; j < JMAX; ++j) {
           if ((EXACT || j < J) && !((rowskip >> j) & 1u))
             m[j] = __ballot((EXACT || lane + 64 * j < n_theta) && buf[lane + 64 * j] < rho2);
           any |= m[j];
+          if (m[j]) {
+            if (n_in == 0) first = 64 * j + (int)__builtin_ctzll(m[j]);
+            n_in += __popcll(m[j]);
+            lastc = 64 * j + 63 - (int)__builtin_clzll(m[j]);
+          }
         }
       }
     }
@@ -469,20 +480,9 @@ __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L
     // Boundary items: inside nodes whose left (side 0) or right (side 1) neighbour is outside
     // or beyond a non-periodic edge.  A row whose inside nodes form one run -- an image
     // crossed once, most rows -- has exactly one per side, its first and last inside column,
-    // found from the masks' population count and two bit scans (all scalar) and queued from
-    // lanes 0 and 1.  A run that touches both ends of a periodic ring may wrap around and
+    // known from the masks' population count and bit scans taken while the row was mapped
+    // (all scalar), and queued from lanes 0 and 1.  A run that touches both ends of a periodic ring may wrap around and
     // takes the general path with the other rows.
-    int n_in = 0, first = 0, lastc = 0;
-#pragma unroll
-    for (int j = JMAX - 1; j >= 0; --j)
-      if ((EXACT || j < J) && m[j]) first = 64 * j + (int)__builtin_ctzll(m[j]);
-#pragma unroll
-    for (int j = 0; j < JMAX; ++j) {
-      if ((EXACT || j < J) && m[j]) {
-        n_in += __popcll(m[j]);
-        lastc = 64 * j + 63 - (int)__builtin_clzll(m[j]);
-      }
-    }
     const bool one_run = n_in == lastc - first + 1 && !(per && (first == 0 || lastc == last));
     // the row buffer's stencil values are read across lanes below
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
