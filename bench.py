@@ -46,9 +46,9 @@ METRIC = "magnified epochs/sec at rho=1e-3 LD (rel err<=1e-4), plain vs batched+
 FLOPS_PER_RAY = {2: 35.0, 3: 48.0}          # algorithmic flop-equivalents per ray
 PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}  # MI355X vector peaks
 def kernel_name(rays, n_theta):
-    """The ray kernel instantiation a grid of n_theta columns runs on (4, 8, 12 or 16 columns per lane)."""
+    """The ray kernel instantiation a grid of n_theta columns runs on (2, 4, 8, 12 or 16 columns per lane)."""
     j = (n_theta + 63) // 64
-    jmax = 4 if j <= 4 else 8 if j <= 8 else 12 if j <= 12 else 16
+    jmax = 2 if j <= 2 else 4 if j <= 4 else 8 if j <= 8 else 12 if j <= 12 else 16
     exact = n_theta % 64 == 0 and j == jmax
     m = "MapF32" if rays == "fp32" else "MapF64"
     return f"rays_kernel<2, {jmax}, {'true' if exact else 'false'}, {m}<2, {jmax}>>"

@@ -121,7 +121,7 @@ icrs_status icrs_magnification(icrs_handle* h, int64_t n_events, const double* p
  * ends; the call allocates nothing (no hipMalloc/hipFree, no allocating library routine).
  * Inputs and outputs as for icrs_magnification, on the current device (the handle's stream
  * must belong to it).  A batch whose workspace (icrs_workspace_bytes) exceeds the scratch --
- * about 90 000 epochs -- returns ICRS_ENOMEM before anything is enqueued.  Every call on a
+ * about 63 000 epochs -- returns ICRS_ENOMEM before anything is enqueued.  Every call on a
  * GPU uses that GPU's one scratch array: calls that overlap on one GPU (two streams, two
  * threads) race and must be serialised by the caller.  Each call initialises every part of
  * the scratch it reads, so the contents left by an earlier call do not matter; final

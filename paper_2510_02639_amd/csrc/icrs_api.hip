@@ -29,9 +29,14 @@ constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
-  size_t params, offsets, epoch_event, sectors, periodic, nsec, partial, clip, list_a, list_b, fallback, jac, roots,
-      counters, total;
+  size_t params, offsets, epoch_event, sectors, periodic, nsec, partial, clip, list_a, list_b, fallback, retake,
+      retake_fx, jac, roots, counters, total;
 };
+
+// Room for FP32 crossings retaken in FP64 (next to the edge rule's jump at delta_c): the
+// benchmark workload lists 6 per epoch at 192 x 512 and 16 at 256 x 1024; a sector whose
+// crossings do not fit is redone by the FP64 pass.
+constexpr int64_t kRetakePerEpoch = 32;
 
 Layout layout_for(int64_t n_events, int64_t n_epochs) {
   Layout L;
@@ -52,6 +57,8 @@ Layout layout_for(int64_t n_events, int64_t n_epochs) {
   L.list_a = take(E * sizeof(int32_t));
   L.list_b = take(E * sizeof(int32_t));
   L.fallback = take(E * ICRS_MAX_SECTORS * sizeof(int32_t));
+  L.retake = take(E * kRetakePerEpoch * 2 * sizeof(int32_t));
+  L.retake_fx = take(E * ICRS_MAX_SECTORS * sizeof(unsigned long long));
   L.jac = take(E * ICRS_N_PARAMS * sizeof(double));
   L.roots = take(E * 10 * 2 * sizeof(double));  // the source centre's polynomial roots
   L.counters = take(64);
@@ -179,10 +186,13 @@ struct Views {
   int32_t* list_a;
   int32_t* list_b;
   int32_t* fallback;
+  int32_t* retake;
+  unsigned long long* retake_fx;
+  int64_t retake_cap;
   double* jac;
   double* roots;       // [n_epochs][10] complex: roots of the centre's lens polynomial
   int32_t* counters;   // [0], [1] retry list counts, [2] cold-redo list count, [4] FP64 fallback
-                       // count, [8..9] int64 sector passes, [12..13] int64 work queue
+                       // count, [5] retake count, [8..9] int64 sector passes, [12..13] int64 work queue
 };
 
 icrs_status prepare(icrs_handle* h, int64_t n_events, const double* params, const int64_t* off, int64_t n_epochs,
@@ -205,6 +215,9 @@ icrs_status prepare(icrs_handle* h, int64_t n_events, const double* params, cons
   v->list_a = (int32_t*)(base + L.list_a);
   v->list_b = (int32_t*)(base + L.list_b);
   v->fallback = (int32_t*)(base + L.fallback);
+  v->retake = (int32_t*)(base + L.retake);
+  v->retake_fx = (unsigned long long*)(base + L.retake_fx);
+  v->retake_cap = n_epochs * kRetakePerEpoch;
   v->jac = (double*)(base + L.jac);
   v->roots = (double*)(base + L.roots);
   v->counters = (int32_t*)(base + L.counters);
@@ -236,6 +249,9 @@ Views prepared_views(const icrs_handle* h, const double* t, void* workspace) {
   v.list_a = (int32_t*)(base + L.list_a);
   v.list_b = (int32_t*)(base + L.list_b);
   v.fallback = (int32_t*)(base + L.fallback);
+  v.retake = (int32_t*)(base + L.retake);
+  v.retake_fx = (unsigned long long*)(base + L.retake_fx);
+  v.retake_cap = h->prep_epochs * kRetakePerEpoch;
   v.jac = (double*)(base + L.jac);
   v.roots = (double*)(base + L.roots);
   v.counters = (int32_t*)(base + L.counters);
@@ -269,6 +285,11 @@ icrs_status run_rays(icrs_handle* h, const Views& v, int max_retries, double* ma
   int32_t* lists[2] = {v.list_a, v.list_b};
   int32_t* counts[2] = {v.counters + 0, v.counters + 1};
   unsigned long long* passes = (unsigned long long*)(v.counters + 8);
+  icrs::RetakeBuf rb;
+  rb.items = v.retake;
+  rb.n = v.counters + 5;
+  rb.cap = v.retake_cap;
+  rb.fx = v.retake_fx;
   const bool learned = (extra_status & ICRS_ST_LEARNED) != 0;
   if (h->profiling) ICRS_TRY(icrs::launch_fill_i32(v.counters + 8, 2, 0, h->stream));
   Timer tm(h);
@@ -279,7 +300,7 @@ icrs_status run_rays(icrs_handle* h, const Views& v, int max_retries, double* ma
       ICRS_TRY(tm.begin());
       ICRS_TRY(icrs::launch_rays(c.n_lens, c.ray_precision, stage, v.b, v.sec, w, c.n_r, c.n_theta, c.delta_c,
                                  v.partial, v.clip, (unsigned long long*)(v.counters + 12), v.fallback,
-                                 v.counters + 4, h->stream));
+                                 v.counters + 4, rb, h->stream));
       double* also = nullptr;
       if (attempt == 0 && stage == 0) also = learned ? &h->prof.ms_rays_learned : &h->prof.ms_rays_main;
       ICRS_TRY(tm.end(&h->prof.ms_rays, also));

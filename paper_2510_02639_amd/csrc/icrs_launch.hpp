@@ -49,16 +49,31 @@ struct RayWork {
   const int32_t* n_items = nullptr;
   int32_t* fallback = nullptr;      // FP32 pass: sectors sent to the FP64 pass
   int32_t* n_fallback = nullptr;
+  int32_t* retake = nullptr;        // FP32 pass: crossings retaken in FP64, pairs (16 e + slot, queue flags)
+  int32_t* n_retake = nullptr;      // their count (may pass retake_cap; pairs beyond it are not stored)
+  int64_t retake_cap = 0;
+  unsigned long long* retake_fx = nullptr;  // per sector slot: the retaken terms' sum, two's complement, 2^-40 units
+};
+
+// Buffers of the FP64 retake of FP32 crossings next to the edge rule's jump at delta_c.
+struct RetakeBuf {
+  int32_t* items = nullptr;  // [cap][2]
+  int32_t* n = nullptr;
+  int64_t cap = 0;
+  unsigned long long* fx = nullptr;  // [n_epochs * 10]
 };
 
 // persistent ray kernel; queue: 16 bytes of device scratch (zeroed here) for the work
 // counter; fallback/n_fallback: [n_epochs * 10] list + counter for FP32 -> FP64 sectors.
 // stage 0 is the main pass over w (FP32 or FP64); stage 1 is the FP64 pass over the sectors
 // the FP32 main pass listed (nothing to do when ray_fp32 == 0).  Both stages are always
-// launched, in order, before the finalize kernel.
+// launched, in order, before the finalize kernel.  rb: the FP32 pass lists its crossings
+// whose edge-rule branch rounding could flip, and stage 0 retakes them in FP64 and adds
+// them to partial before it returns (sectors whose crossings do not fit go to the FP64 pass).
 hipError_t launch_rays(int n_lens, int ray_fp32, int stage, const Batch& b, const SectorBuf& sec, const RayWork& w,
                        int n_r, int n_theta, double delta_c, double* partial, uint8_t* clip,
-                       unsigned long long* queue, int32_t* fallback, int32_t* n_fallback, hipStream_t s);
+                       unsigned long long* queue, int32_t* fallback, int32_t* n_fallback, const RetakeBuf& rb,
+                       hipStream_t s);
 
 // sums sector fluxes into magnifications; epochs with edge touches and retries left get
 // widened sectors and are appended to next_list (count in *next_count).  add_mag (or null):

@@ -43,13 +43,17 @@ __device__ __forceinline__ T edge_factor(T delta, T u1, T delta_c) {
 // (2,d3) with rho on the bracket [0,1] (d1, d2 on opposite sides of rho); linear between
 // d1 and d2 when cubic is false.  Safeguarded Newton from the linear estimate: the bracket
 // shrinks on every step and a step leaving it is replaced by bisection.  Quotients use the
-// hardware reciprocal (refined once in FP64): they only steer the iteration.
+// hardware reciprocal (refined once in FP64): they only steer the iteration.  slope (if
+// given) receives the interpolant's slope L'(t) at the last iterate before t.
 template <typename T>
-__device__ inline T crossing_t(T d0, T d1, T d2, T d3, bool cubic, T rho) {
+__device__ inline T crossing_t(T d0, T d1, T d2, T d3, bool cubic, T rho, T* slope = nullptr) {
   const T den = d2 - d1;
   T t = (den == T(0)) ? T(0.5) : (rho - d1) * rcp_fast(den);
   t = fmin(fmax(t, T(0)), T(1));
-  if (!cubic) return t;
+  if (!cubic) {
+    if (slope) *slope = den;
+    return t;
+  }
   const T c0 = d1 - rho;
   const T c1 = -d0 * T(1.0 / 3.0) - T(0.5) * d1 + d2 - d3 * T(1.0 / 6.0);
   const T c2 = T(0.5) * d0 - d1 + T(0.5) * d2;
@@ -58,24 +62,28 @@ __device__ inline T crossing_t(T d0, T d1, T d2, T d3, bool cubic, T rho) {
   // whose iterate leaves the bracket or is still moving takes the safeguarded loop
   T tq = t;
   T last_step = T(0);
+  T dg = c1;
 #pragma unroll
   for (int it = 0; it < Num<T>::fast_steps; ++it) {
     const T g = ((c3 * tq + c2) * tq + c1) * tq + c0;
-    const T dg = (T(3) * c3 * tq + T(2) * c2) * tq + c1;
+    dg = (T(3) * c3 * tq + T(2) * c2) * tq + c1;
     last_step = g * rcp_fast(dg);
     tq -= last_step;
   }
-  if (tq >= T(0) && tq <= T(1) && fabs(last_step) <= Num<T>::newton_tol) return tq;
+  if (tq >= T(0) && tq <= T(1) && fabs(last_step) <= Num<T>::newton_tol) {
+    if (slope) *slope = dg;
+    return tq;
+  }
   const bool in0 = c0 < T(0);
   T a = T(0), b = T(1);
   for (int it = 0; it < Num<T>::newton_iter; ++it) {
     const T g = ((c3 * t + c2) * t + c1) * t + c0;
+    dg = (T(3) * c3 * t + T(2) * c2) * t + c1;
     if (g == T(0)) break;
     if ((g < T(0)) == in0)
       a = t;
     else
       b = t;
-    const T dg = (T(3) * c3 * t + T(2) * c2) * t + c1;
     const T step = g * rcp_fast(dg);  // Newton step; its rounding does not move the root
     T tn = t - step;
     // converged: accept before the safeguard (t sits on a bracket end by now, and a
@@ -87,6 +95,7 @@ __device__ inline T crossing_t(T d0, T d1, T d2, T d3, bool cubic, T rho) {
     if (!(tn >= a && tn <= b)) tn = T(0.5) * (a + b);
     t = tn;
   }
+  if (slope) *slope = dg;
   return t;
 }
 

@@ -235,6 +235,29 @@ __device__ __attribute__((noinline)) double node_d2_f64(const Lens<N> L, c64 wc,
   return fma(wx, wx, wy * wy);
 }
 
+// The limb-darkened edge rule jumps at delta = delta_c (by 0.41 of the node's brightness at
+// delta_c = 0.1), so which side of delta_c a crossing falls on is a decision, like chi.  An
+// FP32 crossing whose delta lies within rounding of delta_c is retaken here: FP64 distances
+// of the stencil nodes p-1 .. p+2 of column p (eq. lens_eq), the same interpolant and edge
+// rule (App. A); returns the item's I (f(delta) - 1), the brightness at the boundary node (p
+// for a right-side item, p + 1 for a left-side one) in FP64 too.
+template <int N>
+__device__ __attribute__((noinline)) double crossing_term_f64(const Lens<N> L, c64 wc, double r, double th0,
+                                                              double dth, int p, int flags, double rho, double u1,
+                                                              double delta_c, double i_lin, double i_sqrt) {
+  const bool cubic = (flags & 2) != 0;
+  double d2[4] = {0.0, 0.0, 0.0, 0.0}, d[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = 0; k < 4; ++k) {
+    if (cubic || k == 1 || k == 2) {
+      d2[k] = node_d2_f64<N>(L, wc, r, th0 + (p + k - 0.5) * dth);
+      d[k] = sqrt(d2[k]);
+    }
+  }
+  const double t = crossing_t<double>(d[0], d[1], d[2], d[3], cubic, rho);
+  const double b = brightness<double>((flags & 1) ? d2[1] : d2[2], 1.0 / (rho * rho), i_lin, i_sqrt);
+  return b * (edge_factor<double>((flags & 1) ? t : 1.0 - t, u1, delta_c) - 1.0);
+}
+
 // Lower bound of d = |w(z) - w_c| over the arc z = z0 e^{i phi}, |phi| <= Phi, z0 = r e^{i theta_c}.
 // w(z) = z + f(conj z) with f holomorphic, so for Delta = z - z0:
 //   w(z) = w0 + Delta + K conj(Delta) + R2,  K = f'(conj z0) = sum_k eps_k / conj(z0 - a_k)^2,
@@ -299,7 +322,8 @@ template <typename T>
 struct CrossQueue {
   T d[4][kQueue];    // squared stencil distances d_{p-1}^2 .. d_{p+2}^2 (an edge item keeps its node's in d[1])
   double r[kQueue];  // its row radius
-  int f[kQueue];     // bit 0: side (1 = right), bit 1: cubic stencil, bit 2: neighbour beyond an edge
+  int f[kQueue];     // bit 0: side (1 = right), bit 1: cubic stencil, bit 2: neighbour beyond an edge,
+                     // bits 3-12: the bracket's left column p, bits 13+: the row
 };
 
 __device__ __forceinline__ void wave_lds_sync() {
@@ -308,18 +332,41 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// clip bit of a sector whose retake list was full (the FP64 pass redoes it)
+constexpr int kClipRetakeOverflow = 256;
+
+// Per-wave staging of the crossings to retake (their queue flags): the row loop writes LDS
+// only, and the wave copies the list to the global one once per sector, so no global
+// pointer is live in the loop.  A wave with more than kRetake in one sector overflows.
+// Kept small: at 64 columns per lane the kernel's LDS stays under the 40 KB that leaves room
+// for four workgroups per CU.
+constexpr int kRetake = 16;
+
+struct RetakeList {
+  int f[kRetake];
+};
+
 // sum over the n queued items of r_i I (f(delta) - 1), lane k taking items k, k + 64, ...;
 // square roots and brightness are taken here, where every lane has an item.  Inlined: as an
 // out-of-line call its register saves and restores cost 4-5% of the kernel.
+//
+// FP32 only, for the edge rule's jump at delta_c (crossing_term_f64): t_err is 2.5 times
+// the bound (e_s + 2^-21) rho on a stencil distance's error; the cubic's Lebesgue constant
+// on [0, 1] is 1.25, so the FP32 crossing lies within t_err / 2 / abs(L'(t)) of the exact
+// one, plus the solver's 1e-6 step tolerance.  An item with delta that close to delta_c
+// adds nothing here and is staged in rl, rl_n counting all of them (wave-uniform).
 template <typename T>
 __device__ __forceinline__ double flush_crossings(const CrossQueue<T>* q, int n, T rho, T u1, T delta_c,
-                                                            T f_edge, T inv_rho2, T i_lin, T i_sqrt) {
+                                                  T f_edge, T inv_rho2, T i_lin, T i_sqrt, T t_err,
+                                                  RetakeList* rl, int& rl_n) {
   const int lane = threadIdx.x & 63;
   double s = 0.0;
   for (int base = 0; base < n; base += 64) {
     const int k = base + lane;
+    bool take = false;
+    int f = 0;
     if (k < n) {
-      const int f = q->f[k];
+      f = q->f[k];
       // the boundary node is p (right side, or an edge item) or p + 1 (left side)
       const T b = brightness<T>((f & 5) ? q->d[1][k] : q->d[2][k], inv_rho2, i_lin, i_sqrt);
       T corr;
@@ -327,24 +374,41 @@ __device__ __forceinline__ double flush_crossings(const CrossQueue<T>* q, int n,
         corr = f_edge;
       } else {
         // side 0: crossing in (theta_{l-1}, theta_l), delta = 1 - t; side 1: in (theta_l, theta_{l+1}), delta = t
+        const bool cubic = (f & 2) != 0;
+        T slope;
         const T t = crossing_t<T>(sqrt_fast(q->d[0][k]), sqrt_fast(q->d[1][k]), sqrt_fast(q->d[2][k]),
-                                  sqrt_fast(q->d[3][k]), (f & 2) != 0, rho);
-        corr = edge_factor<T>((f & 1) ? t : T(1) - t, u1, delta_c) - T(1);
+                                  sqrt_fast(q->d[3][k]), cubic, rho, &slope);
+        const T delta = (f & 1) ? t : T(1) - t;
+        corr = edge_factor<T>(delta, u1, delta_c) - T(1);
+        if constexpr (sizeof(T) == 4) {
+          slope = fabs(slope);
+          take = u1 != T(0) && fabs(delta - delta_c) * slope <= t_err + T(4e-6) * slope;
+        }
       }
-      s += q->r[k] * (double)(b * corr);
+      if (!take) s += q->r[k] * (double)(b * corr);
+    }
+    if constexpr (sizeof(T) == 4) {
+      const uint64_t tm = __ballot(take);
+      if (tm) {
+        const int pos = rl_n + (int)__popcll(tm & ((1ull << lane) - 1ull));
+        if (take && pos < kRetake) rl->f[pos] = f;
+        rl_n += (int)__popcll(tm);
+      }
     }
   }
   return s;
 }
 
 // One (epoch, sector) grid shot by the whole workgroup; the flux and clip bits end up in
-// thread 0.  EXACT: n_theta == 64 * JMAX (no partial column chunk).
+// thread 0, with kClipRetakeOverflow set when an FP32 wave listed more crossings near delta_c
+// than it can retake (the flux is then incomplete).  EXACT: n_theta == 64 * JMAX (no partial
+// column chunk).
 template <int N, int JMAX, bool EXACT, typename MAP>
 __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L, c64 wc, double rho_d, double u1_d,
                                     double delta_c_d, int n_r, int n_theta, typename MAP::T* rowbuf_all,
                                     uint64_t* bwords, CrossQueue<typename MAP::T>* queues, double* wsum,
-                                    int* wclip, double ebound, float2* phase_sh, double* flux_out,
-                                    int* clip_out_bits) {
+                                    int* wclip, double ebound, float2* phase_sh, RetakeList* retakes,
+                                    const RayWork& w, int code, double* flux_out, int* clip_out_bits) {
   using T = typename MAP::T;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -358,6 +422,7 @@ __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L
   const double dr = (r_hi - r_lo) / n_r;
   const double dth = (sp[3] - sp[2]) / n_theta;
   const T f_edge = edge_factor<T>(T(0.5), u1, delta_c) - T(1);  // neighbour beyond a sector edge
+  const T t_err = (T)(2.5 * (ebound + 0x1p-21) * rho_d);
   const int last = (EXACT ? 64 * JMAX : n_theta) - 1;  // a compile-time constant for exact grids
   const int jl = last >> 6, bl = last & 63;
 
@@ -374,6 +439,8 @@ __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L
   uint64_t* bwl = bwords + wave * (2 * JMAX);
   CrossQueue<T>* cq = queues + wave;
   int qn = 0;
+  RetakeList* rl = retakes + (sizeof(T) == 4 ? wave : 0);  // FP64 maps have one unused list
+  int rl_n = 0;
 
   // Chunk culling: a 64-column chunk of a row is skipped when the arc through it, widened
   // by two columns on each side, provably maps farther than rho (1 + 1e-3) from the source
@@ -507,6 +574,7 @@ __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L
         cq->d[2][slot] = buf[ip1];
         cq->d[3][slot] = buf[ip2];
         if (cubic) fl |= 2;
+        fl |= (pp << 3) | (i << 13);
       }
       cq->r[slot] = r;
       cq->f[slot] = fl;
@@ -514,7 +582,7 @@ __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L
     if (one_run) {
       if (qn + 2 > kQueue) {
         wave_lds_sync();
-        acc += flush_crossings<T>(cq, qn, rho, u1, delta_c, f_edge, inv_rho2, i_lin, i_sqrt);
+        acc += flush_crossings<T>(cq, qn, rho, u1, delta_c, f_edge, inv_rho2, i_lin, i_sqrt, t_err, rl, rl_n);
         wave_lds_sync();
         qn = 0;
       }
@@ -547,7 +615,7 @@ __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L
       for (int base = 0; base < n_all; base += 64) {
         if (qn + 64 > kQueue) {
           wave_lds_sync();
-          acc += flush_crossings<T>(cq, qn, rho, u1, delta_c, f_edge, inv_rho2, i_lin, i_sqrt);
+          acc += flush_crossings<T>(cq, qn, rho, u1, delta_c, f_edge, inv_rho2, i_lin, i_sqrt, t_err, rl, rl_n);
           wave_lds_sync();
           qn = 0;
         }
@@ -578,7 +646,24 @@ __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L
 
   if (qn > 0) {
     wave_lds_sync();
-    acc += flush_crossings<T>(cq, qn, rho, u1, delta_c, f_edge, inv_rho2, i_lin, i_sqrt);
+    acc += flush_crossings<T>(cq, qn, rho, u1, delta_c, f_edge, inv_rho2, i_lin, i_sqrt, t_err, rl, rl_n);
+  }
+  if constexpr (sizeof(T) == 4) {
+    // the staged crossings to the global list, one reservation per wave.  Every reserved slot
+    // below the capacity is written (the retake kernel reads all of them); an overflowed
+    // sector's retakes are harmless, as the FP64 pass overwrites its flux.
+    if (rl_n > 0) {
+      const int nw = min(rl_n, kRetake);
+      int at = 0;
+      if (lane == 0) at = atomicAdd(w.n_retake, nw);
+      at = __shfl(at, 0);
+      if (rl_n > kRetake || (int64_t)at + nw > w.retake_cap) clip |= kClipRetakeOverflow;
+      wave_lds_sync();
+      if (lane < nw && (int64_t)at + lane < w.retake_cap) {
+        w.retake[2 * ((int64_t)at + lane)] = code;
+        w.retake[2 * ((int64_t)at + lane) + 1] = rl->f[lane];
+      }
+    }
   }
   // deterministic reductions: butterfly inside the wave, then waves in order
 #pragma unroll
@@ -604,8 +689,9 @@ __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L
 // Persistent ray kernel.  Tasks come from a device counter: with w.items set, task k is the
 // single sector w.items[k] = 16 e + slot (k < *w.n_items); otherwise task k is every sector
 // of epoch w.list[k] (or k).  An FP32 pass sends sectors whose rounding bound exceeds the
-// budget to w.fallback for the FP64 pass.  Every workgroup leaves once the counter has
-// passed the end.
+// budget, and those with more crossings near delta_c than the waves retake, to w.fallback
+// for the FP64 pass (an FP32 pass always has the list).  Every workgroup leaves once the
+// counter has passed the end.
 template <int N, int JMAX, bool EXACT, typename MAP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MAP::kMinWaves))) void rays_kernel(
     Batch b, SectorBuf sec, RayWork w, int n_r, int n_theta, double delta_c, double* __restrict__ partial,
@@ -619,6 +705,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MAP::kMinWa
   __shared__ unsigned long long next_sh;
   __shared__ double ebound_sh[kMaxSectors];
   __shared__ float2 phase_sh[MAP::kPhaseEntries];
+  __shared__ RetakeList retakes[sizeof(T) == 4 ? kWaves : 1];
 
   const unsigned long long total = w.items   ? (unsigned long long)(*w.n_items)
                                    : w.n_dev ? (unsigned long long)(*w.n_dev)
@@ -671,16 +758,65 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MAP::kMinWa
       double flux = 0.0;
       int c = 0;
       shoot_sector<N, JMAX, EXACT, MAP>(sp, per, L, wc, p[6], p[7], delta_c, n_r, n_theta, rowbuf, bwords, queues, wsum,
-                                        wclip, ebound, phase_sh, &flux, &c);
+                                        wclip, ebound, phase_sh, retakes, w, (int)(e * 16 + slot), &flux, &c);
       if (threadIdx.x == 0) {
         partial[e * kMaxSectors + slot] = flux;
         clip_out[e * kMaxSectors + slot] = (uint8_t)c;
+        if constexpr (sizeof(T) == 4) {
+          // the retake kernel adds into the sector's sum from zero; the FP64 pass overwrites
+          // partial and clip of an overflowed sector
+          w.retake_fx[e * kMaxSectors + slot] = 0ull;
+          if (c & kClipRetakeOverflow) w.fallback[atomicAdd(w.n_fallback, 1)] = (int32_t)(e * 16 + slot);
+        }
       }
     }
     if (threadIdx.x == 0) next_sh = ticket;
     __syncthreads();
     idx = next_sh;
     __syncthreads();
+  }
+}
+
+// FP64 retake of the crossings an FP32 pass listed (one per thread): its term r I (f(delta) - 1)
+// goes into the sector's sum as an integer multiple of 2^-40, so the sum is the same whatever
+// order the atomic additions take (a term's magnitude is below r_max I0 < 2^22).
+template <int N>
+__global__ __launch_bounds__(256) void retake_kernel(Batch b, SectorBuf sec, RayWork w, int n_r, int n_theta,
+                                                     double delta_c) {
+  const int64_t n = min((int64_t)(*w.n_retake), w.retake_cap);
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+    const int code = w.retake[2 * k], f = w.retake[2 * k + 1];
+    const int64_t e = code >> 4;
+    const int slot = code & 15;
+    const double* p = b.params + (int64_t)b.epoch_event[e] * kParams;
+    const Lens<N> L = make_lens<N>(p);
+    const c64 wc = source_center(p, b.t[e]);
+    const double* sp = sec.sectors + (e * kMaxSectors + slot) * 4;
+    // the same row radius and column width as the ray kernel
+    const double dr = (sp[1] - sp[0]) / n_r, dth = (sp[3] - sp[2]) / n_theta;
+    const double r = sp[0] + ((f >> 13) + 0.5) * dr;
+    const double rho = p[6], u1 = p[7];
+    const double I0 = 3.0 / (kPi * (3.0 - u1));
+    const double term =
+        r * crossing_term_f64<N>(L, wc, r, sp[2], dth, (f >> 3) & 1023, f, rho, u1, delta_c, I0 * (1.0 - u1), I0 * u1);
+    atomicAdd(&w.retake_fx[e * kMaxSectors + slot], (unsigned long long)llrint(ldexp(term, 40)));
+  }
+}
+
+// Adds each listed sector's retake sum to its flux once: the first thread to exchange the sum
+// for zero holds all of it.
+__global__ __launch_bounds__(256) void retake_fold_kernel(SectorBuf sec, RayWork w, int n_r, int n_theta,
+                                                          double* __restrict__ partial) {
+  const int64_t n = min((int64_t)(*w.n_retake), w.retake_cap);
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+    const int code = w.retake[2 * k];
+    const int64_t at = (code >> 4) * kMaxSectors + (code & 15);
+    const unsigned long long v = atomicExch(&w.retake_fx[at], 0ull);
+    if (v != 0ull) {
+      const double* sp = sec.sectors + at * 4;
+      const double dr = (sp[1] - sp[0]) / n_r, dth = (sp[3] - sp[2]) / n_theta;
+      partial[at] += ldexp((double)(long long)v, -40) * dr * dth;
+    }
   }
 }
 
@@ -769,6 +905,7 @@ hipError_t launch_rays_n(const Batch& b, const SectorBuf& sec, const RayWork& w,
       return launch_rays_j<N, JJ, true, MAP>(b, sec, w, n_r, n_theta, delta_c, partial, clip, queue, s);  \
     return launch_rays_j<N, JJ, false, MAP>(b, sec, w, n_r, n_theta, delta_c, partial, clip, queue, s);   \
   }
+  ICRS_RAYS_J(2)
   ICRS_RAYS_J(4)
   ICRS_RAYS_J(8)
   ICRS_RAYS_J(12)
@@ -780,18 +917,32 @@ hipError_t launch_rays_n(const Batch& b, const SectorBuf& sec, const RayWork& w,
 template <int N>
 hipError_t launch_rays_lens(int ray_fp32, int stage, const Batch& b, const SectorBuf& sec, const RayWork& w,
                             int n_r, int n_theta, double delta_c, double* partial, uint8_t* clip,
-                            unsigned long long* queue, int32_t* fallback, int32_t* n_fallback, hipStream_t s) {
+                            unsigned long long* queue, int32_t* fallback, int32_t* n_fallback, const RetakeBuf& rb,
+                            hipStream_t s) {
   if (!ray_fp32)
     return stage == 0 ? launch_rays_n<N, MapF64>(b, sec, w, n_r, n_theta, delta_c, partial, clip, queue, s)
                       : hipSuccess;
   if (stage == 0) {
-    // FP32 pass; sectors over the rounding budget are listed for the FP64 pass
+    // FP32 pass; sectors over the rounding budget are listed for the FP64 pass, crossings
+    // next to delta_c for the retake, which follows at once
+    if (!rb.items || !rb.n || !rb.fx || rb.cap < 0 || rb.cap > ((int64_t)1 << 31) - 1) return hipErrorInvalidValue;
     hipError_t e = launch_fill_i32(n_fallback, 1, 0, s);
+    if (e == hipSuccess) e = launch_fill_i32(rb.n, 1, 0, s);
     if (e != hipSuccess) return e;
     RayWork w32 = w;
     w32.fallback = fallback;
     w32.n_fallback = n_fallback;
-    return launch_rays_n<N, MapF32>(b, sec, w32, n_r, n_theta, delta_c, partial, clip, queue, s);
+    w32.retake = rb.items;
+    w32.n_retake = rb.n;
+    w32.retake_cap = rb.cap;
+    w32.retake_fx = rb.fx;
+    e = launch_rays_n<N, MapF32>(b, sec, w32, n_r, n_theta, delta_c, partial, clip, queue, s);
+    if (e != hipSuccess) return e;
+    // grid-stride over the device-side count: 1024 x 256 threads cover a typical list in a
+    // few strides
+    hipLaunchKernelGGL(retake_kernel<N>, dim3(1024), dim3(256), 0, s, b, sec, w32, n_r, n_theta, delta_c);
+    hipLaunchKernelGGL(retake_fold_kernel, dim3(1024), dim3(256), 0, s, sec, w32, n_r, n_theta, partial);
+    return hipGetLastError();
   }
   RayWork w64{};
   w64.items = fallback;
@@ -804,13 +955,14 @@ hipError_t launch_rays_lens(int ray_fp32, int stage, const Batch& b, const Secto
 
 hipError_t launch_rays(int n_lens, int ray_fp32, int stage, const Batch& b, const SectorBuf& sec, const RayWork& w,
                        int n_r, int n_theta, double delta_c, double* partial, uint8_t* clip,
-                       unsigned long long* queue, int32_t* fallback, int32_t* n_fallback, hipStream_t s) {
+                       unsigned long long* queue, int32_t* fallback, int32_t* n_fallback, const RetakeBuf& rb,
+                       hipStream_t s) {
   if (w.n == 0) return hipSuccess;
   if (n_lens == 2)
     return launch_rays_lens<2>(ray_fp32, stage, b, sec, w, n_r, n_theta, delta_c, partial, clip, queue, fallback,
-                               n_fallback, s);
+                               n_fallback, rb, s);
   return launch_rays_lens<3>(ray_fp32, stage, b, sec, w, n_r, n_theta, delta_c, partial, clip, queue, fallback,
-                             n_fallback, s);
+                             n_fallback, rb, s);
 }
 
 hipError_t launch_finalize(const Batch& b, const SectorBuf& sec, const RayWork& w, const double* partial,

@@ -318,11 +318,12 @@ def _planetary_subset(n_events=6, per_event=6, rho=None, seed=2):
                       128, 128, 512, "fp32", "fp32")
 
 
-@pytest.mark.parametrize("n_r,n_theta", [(128, 512), (64, 256), (48, 320), (48, 768), (40, 704), (32, 1024)])
+@pytest.mark.parametrize("n_r,n_theta", [(32, 128), (24, 96), (128, 512), (64, 256), (48, 320), (48, 768),
+                                         (40, 704), (32, 1024)])
 def test_fp32_rays_given_grid_planetary(n_r, n_theta):
     """FP32 ray loop (anchor-relative) on the oracle's own sectors: 3e-5 of the FP64 oracle.
-    The grids cover every kernel shape: 4, 8 (with a partial chunk at 320), 12 (with a
-    partial chunk at 704) and 16 column chunks per lane."""
+    The grids cover every kernel shape: 2 (with a partial chunk at 96), 4, 8 (with a partial
+    chunk at 320), 12 (with a partial chunk at 704) and 16 column chunks per lane."""
     w = _planetary_subset(rho=1e-3)
     ref = _oracle(w)
     h = icrs.Handle(n_lens=2, n_limb=128, n_r=n_r, n_theta=n_theta, ray_precision="fp32", root_precision="fp32")
