@@ -192,7 +192,8 @@ struct Views {
   double* jac;
   double* roots;       // [n_epochs][10] complex: roots of the centre's lens polynomial
   int32_t* counters;   // [0], [1] retry list counts, [2] cold-redo list count, [4] FP64 fallback
-                       // count, [5] retake count, [8..9] int64 sector passes, [12..13] int64 work queue
+                       // count, [6..7] int64 retake count, [8..9] int64 sector passes, [12..13] int64
+                       // work queue
 };
 
 icrs_status prepare(icrs_handle* h, int64_t n_events, const double* params, const int64_t* off, int64_t n_epochs,
@@ -287,7 +288,7 @@ icrs_status run_rays(icrs_handle* h, const Views& v, int max_retries, double* ma
   unsigned long long* passes = (unsigned long long*)(v.counters + 8);
   icrs::RetakeBuf rb;
   rb.items = v.retake;
-  rb.n = v.counters + 5;
+  rb.n = (unsigned long long*)(v.counters + 6);
   rb.cap = v.retake_cap;
   rb.fx = v.retake_fx;
   const bool learned = (extra_status & ICRS_ST_LEARNED) != 0;

@@ -50,7 +50,7 @@ struct RayWork {
   int32_t* fallback = nullptr;      // FP32 pass: sectors sent to the FP64 pass
   int32_t* n_fallback = nullptr;
   int32_t* retake = nullptr;        // FP32 pass: crossings retaken in FP64, pairs (16 e + slot, queue flags)
-  int32_t* n_retake = nullptr;      // their count (may pass retake_cap; pairs beyond it are not stored)
+  unsigned long long* n_retake = nullptr;  // their count (may pass retake_cap; pairs beyond it are not stored)
   int64_t retake_cap = 0;
   unsigned long long* retake_fx = nullptr;  // per sector slot: the retaken terms' sum, two's complement, 2^-40 units
 };
@@ -58,7 +58,7 @@ struct RayWork {
 // Buffers of the FP64 retake of FP32 crossings next to the edge rule's jump at delta_c.
 struct RetakeBuf {
   int32_t* items = nullptr;  // [cap][2]
-  int32_t* n = nullptr;
+  unsigned long long* n = nullptr;  // 8-byte aligned
   int64_t cap = 0;
   unsigned long long* fx = nullptr;  // [n_epochs * 10]
 };

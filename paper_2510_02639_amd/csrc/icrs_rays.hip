@@ -654,14 +654,14 @@ __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L
     // sector's retakes are harmless, as the FP64 pass overwrites its flux.
     if (rl_n > 0) {
       const int nw = min(rl_n, kRetake);
-      int at = 0;
-      if (lane == 0) at = atomicAdd(w.n_retake, nw);
+      unsigned long long at = 0;
+      if (lane == 0) at = atomicAdd(w.n_retake, (unsigned long long)nw);
       at = __shfl(at, 0);
-      if (rl_n > kRetake || (int64_t)at + nw > w.retake_cap) clip |= kClipRetakeOverflow;
+      if (rl_n > kRetake || at + nw > (unsigned long long)w.retake_cap) clip |= kClipRetakeOverflow;
       wave_lds_sync();
-      if (lane < nw && (int64_t)at + lane < w.retake_cap) {
-        w.retake[2 * ((int64_t)at + lane)] = code;
-        w.retake[2 * ((int64_t)at + lane) + 1] = rl->f[lane];
+      if (lane < nw && at + lane < (unsigned long long)w.retake_cap) {
+        w.retake[2 * (at + lane)] = code;
+        w.retake[2 * (at + lane) + 1] = rl->f[lane];
       }
     }
   }
@@ -783,7 +783,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MAP::kMinWa
 template <int N>
 __global__ __launch_bounds__(256) void retake_kernel(Batch b, SectorBuf sec, RayWork w, int n_r, int n_theta,
                                                      double delta_c) {
-  const int64_t n = min((int64_t)(*w.n_retake), w.retake_cap);
+  const int64_t n = (int64_t)min(*w.n_retake, (unsigned long long)w.retake_cap);
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
     const int code = w.retake[2 * k], f = w.retake[2 * k + 1];
     const int64_t e = code >> 4;
@@ -807,7 +807,7 @@ __global__ __launch_bounds__(256) void retake_kernel(Batch b, SectorBuf sec, Ray
 // for zero holds all of it.
 __global__ __launch_bounds__(256) void retake_fold_kernel(SectorBuf sec, RayWork w, int n_r, int n_theta,
                                                           double* __restrict__ partial) {
-  const int64_t n = min((int64_t)(*w.n_retake), w.retake_cap);
+  const int64_t n = (int64_t)min(*w.n_retake, (unsigned long long)w.retake_cap);
   for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
     const int code = w.retake[2 * k];
     const int64_t at = (code >> 4) * kMaxSectors + (code & 15);
@@ -925,9 +925,9 @@ hipError_t launch_rays_lens(int ray_fp32, int stage, const Batch& b, const Secto
   if (stage == 0) {
     // FP32 pass; sectors over the rounding budget are listed for the FP64 pass, crossings
     // next to delta_c for the retake, which follows at once
-    if (!rb.items || !rb.n || !rb.fx || rb.cap < 0 || rb.cap > ((int64_t)1 << 31) - 1) return hipErrorInvalidValue;
+    if (!rb.items || !rb.n || !rb.fx || rb.cap < 0) return hipErrorInvalidValue;
     hipError_t e = launch_fill_i32(n_fallback, 1, 0, s);
-    if (e == hipSuccess) e = launch_fill_i32(rb.n, 1, 0, s);
+    if (e == hipSuccess) e = launch_fill_i32((int32_t*)rb.n, 2, 0, s);
     if (e != hipSuccess) return e;
     RayWork w32 = w;
     w32.fallback = fallback;

@@ -1,5 +1,10 @@
 """Throughput of the path's other rows on one GPU, one JSON line per measurement:
 
+  config1   the plain FP64 path on the single binary event (s = 0.9, q = 0.1, rho = 1e-2,
+            200 epochs across the central caustic, 64 x 256): epochs/s and the ray pass's
+            FP64 roofline;
+  config2   the planetary batch (2048 events, rho ~ logU[10^-3.5, 10^-2], 128 x 512, FP32
+            rays) in one call: epochs/s, rays/s and the main pass's FP32 roofline;
   adjoint   forward + reverse-mode gradient on the differentiable-fit workload (512 binary
             events x 3000 epochs, rho = 1e-3; cotangent N(0,1), seed 40): epochs/s of the
             forward and of the VJP, and the VJP's ray rate;
@@ -16,7 +21,8 @@
   kernels   one eager plain step and one eager learned step of the metric workload at
             given grids (plain=NRxNT learned=NRxNT:GATE:SLACK), for counter and trace runs.
 
-    python -m paper_2510_02639_amd.perf [adjoint triple train serve hybrid nll fig2 kernels] [plain=..] [learned=..]
+    python -m paper_2510_02639_amd.perf [config1 config2 adjoint triple train serve hybrid nll fig2 kernels]
+        [plain=..] [learned=..]
 
 Inputs are resident in HBM before each timed region; times are wall-clock around
 synchronised device work.
@@ -53,6 +59,38 @@ def _timed(fn, reps=3):
         out = fn()
     torch.cuda.synchronize()
     return out, (time.perf_counter() - t0) / reps
+
+
+def _plain(w, n_limb, n_r, n_theta, rays, roots, reps):
+    h = icrs.Handle(n_lens=w.n_lens, n_limb=n_limb, n_r=n_r, n_theta=n_theta, ray_precision=rays,
+                    root_precision=roots)
+    t = torch.tensor(w.t, device="cuda")
+    ws = h.workspace(w.n_events, w.n_epochs)
+    h.magnification(w.params, w.offsets, t, workspace=ws)
+    h.set_profiling(True)
+    h.get_profile(reset=True)
+    _, dt = _timed(lambda: h.magnification(w.params, w.offsets, t, workspace=ws), reps=reps)
+    prof = h.get_profile()
+    h.set_profiling(False)
+    calls = reps + 1  # _timed's warm-up call is profiled too
+    main = _roofline(prof["n_main_rays"] / calls, FLOPS_RAY_FP32[w.n_lens], prof["ms_rays_main"] / calls * 1e-3,
+                     "fp32" if rays == "fp32" else "fp64")
+    return {"n_events": w.n_events, "n_epochs": w.n_epochs, "grid": [n_r, n_theta], "rays": rays, "roots": roots,
+            "epochs_per_s": w.n_epochs / dt, "ms_per_call": dt * 1e3,
+            "rays_per_s": prof["n_main_rays"] / (prof["ms_rays_main"] * 1e-3),
+            "breakdown_ms": {k: prof[k] / calls for k in ("ms_centre", "ms_limb_sectors", "ms_rays", "ms_rays_main",
+                                                          "ms_finalize")},
+            "sectors_per_epoch": prof["n_sector_passes"] / max(prof["n_epochs"], 1), "rays_roofline": main}
+
+
+def config1():
+    w = workloads.config1()
+    return {"measure": "config1", "workload": w.name, **_plain(w, 64, 64, 256, "fp64", "fp64", reps=20)}
+
+
+def config2():
+    w = workloads.config2()
+    return {"measure": "config2", "workload": w.name, **_plain(w, 128, 128, 512, "fp32", "fp32", reps=3)}
 
 
 def adjoint():
@@ -207,9 +245,10 @@ def kernels(plain="256x1024", learned_cfg="192x768:0.01:0"):
 
 
 def main(argv):
-    which = [a for a in argv if "=" not in a] or ["adjoint", "triple", "train", "serve", "hybrid", "nll", "fig2"]
+    which = [a for a in argv if "=" not in a] or ["config1", "config2", "adjoint", "triple", "train", "serve",
+                                                  "hybrid", "nll", "fig2"]
     opts = dict(a.split("=", 1) for a in argv if "=" in a)
-    fns = {"adjoint": adjoint, "triple": triple, "train": train, "serve": serving, "hybrid": hybrid, "nll": nll,
+    fns = {"config1": config1, "config2": config2, "adjoint": adjoint, "triple": triple, "train": train, "serve": serving, "hybrid": hybrid, "nll": nll,
            "fig2": fig2,
            "kernels": lambda: kernels(opts.get("plain", "256x1024"), opts.get("learned", "192x768:0.01:0"))}
     for k in which:
