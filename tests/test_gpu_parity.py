@@ -343,6 +343,34 @@ def test_fp32_rays_given_grid_planetary(n_r, n_theta):
     assert np.all(rel <= FP32_TOL)
 
 
+@pytest.mark.parametrize("delta_c", [0.05, 0.3, 0.6])
+@pytest.mark.parametrize("n_r,n_theta", [(32, 128), (64, 256)])
+def test_fp32_edge_rule_branch_at_other_delta_c(n_r, n_theta, delta_c):
+    """The limb-darkened edge rule jumps at delta_c (App. A.2), and the FP32 path takes the
+    branch of a crossing within its rounding of delta_c from FP64 stencil distances.  With the
+    jump moved to 0.05, 0.3 or 0.6 every epoch still matches the oracle's quadrature on the
+    same sectors and delta_c to the FP32 bar (a branch flip costs ~0.2 of a node's weight,
+    up to 4e-4 of a poorly resolved image at these grids)."""
+    w = _planetary_subset(n_events=8, per_event=8, rho=1e-3)
+    ref = _oracle(w)
+    t = torch.tensor(w.t, device="cuda")
+    args = [torch.tensor(ref[k], device="cuda") for k in ("sectors", "periodic", "nsec")]
+    om = []
+    for i in range(w.n_events):
+        sl = slice(w.offsets[i], w.offsets[i + 1])
+        om.append(O.magnification_given(2, w.params[i], w.t[sl], ref["sectors"][sl], ref["periodic"][sl],
+                                        ref["nsec"][sl], n_r, n_theta, delta_c=delta_c)[0])
+    om = np.concatenate(om)
+    for rays, tol in (("fp64", FP64_TOL), ("fp32", FP32_TOL)):
+        h = icrs.Handle(n_lens=2, n_limb=128, n_r=n_r, n_theta=n_theta, ray_precision=rays, root_precision="fp32",
+                        delta_c=delta_c)
+        mag, st = h.magnification_given(w.params, w.offsets, t, *args)
+        torch.cuda.synchronize()
+        rel = np.abs(mag.cpu().numpy() / om - 1)
+        _report(f"given {rays} planetary {n_r}x{n_theta} delta_c={delta_c}", rel)
+        assert np.all(rel <= tol)
+
+
 def test_fp32_end_to_end_planetary():
     """Config-2 shape: FP32 EA + FP64 polish, FP32 rays, 128 limb points, 128 x 512."""
     w = _planetary_subset()
