@@ -62,10 +62,16 @@ __device__ inline uint16_t f2bf(float f) {
 }
 __device__ inline float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-// GELU, tanh form: x/2 (1 + tanh(c (x + a x^3))), c = sqrt(2/pi), a = 0.044715
-constexpr float kGc = 0.7978845608028654f, kGa = 0.044715f;
-__device__ inline float tanh_f(float u) { return 1.0f - 2.0f / (1.0f + __expf(2.0f * u)); }
-__device__ inline float gelu(float x) { return 0.5f * x * (1.0f + tanh_f(kGc * (x + kGa * x * x * x))); }
+// GELU, tanh form: x/2 (1 + tanh(c (x + a x^3))), c = sqrt(2/pi), a = 0.044715, evaluated
+// as x sigmoid(2 c x (1 + a x^2)) with the hardware base-2 exponential and reciprocal (their
+// rounding, a few FP32 units, is far below the bfloat16 the activations are stored in);
+// e^{-z} overflowing to infinity gives the limit 0.
+constexpr float kGc = 0.7978845608028654f, kGa = 0.044715f, kLog2e = 1.4426950408889634f;
+__device__ inline float exp_hw(float u) { return __builtin_amdgcn_exp2f(u * kLog2e); }
+__device__ inline float tanh_f(float u) { return 1.0f - 2.0f * __builtin_amdgcn_rcpf(1.0f + exp_hw(2.0f * u)); }
+__device__ inline float gelu(float x) {
+  return x * __builtin_amdgcn_rcpf(1.0f + exp_hw(-2.0f * kGc * x * fmaf(kGa * x, x, 1.0f)));
+}
 __device__ inline float gelu_grad(float x) {
   const float t = tanh_f(kGc * (x + kGa * x * x * x));
   return 0.5f * (1.0f + t) + 0.5f * x * (1.0f - t * t) * kGc * (1.0f + 3.0f * kGa * x * x);
@@ -142,28 +148,83 @@ __device__ inline f32x4 output_layer(const Net& net, const uint16_t* H3) {
   return acc;
 }
 
+// Inference: a workgroup of four waves owns 128 rows, 32 per wave as two 16-row tiles, so each
+// 16-byte weight operand feeds two MFMAs (half the weight traffic per row of the 16-row
+// tiling, which the vector L1 could not keep up with).  One activation buffer: a layer loads
+// its wave's A operands into registers before it writes any output, and each wave reads and
+// writes only its own rows, so layers update it in place (45 KB of LDS per workgroup).
+constexpr int kFwdTile = 128, kFwdRowsPerWave = 32;
+
+template <int KCH>
+__device__ inline void fwd_layer(const uint16_t* Hin, int pitch_in, const uint16_t* __restrict__ W, int ldw,
+                                 const float* __restrict__ bias, uint16_t* Hout) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, lr = l & 15, lq = l >> 4;
+  const int rw = kFwdRowsPerWave * w;
+  // the previous layer's outputs (other lanes of this wave) are visible
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  u16x8 a0[KCH], a1[KCH];
+#pragma unroll
+  for (int kc = 0; kc < KCH; ++kc) {
+    a0[kc] = ld8(Hin + (rw + lr) * pitch_in + kc * 32 + 8 * lq);
+    a1[kc] = ld8(Hin + (rw + 16 + lr) * pitch_in + kc * 32 + 8 * lq);
+  }
+  // the wave's operands are in registers before any of its rows is overwritten
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll 2
+  for (int nt = 0; nt < kHid / 16; ++nt) {
+    f32x4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kc = 0; kc < KCH; ++kc) {
+      const u16x8 b = ld8(W + (nt * 16 + lr) * ldw + kc * 32 + 8 * lq);
+      c0 = mfma(a0[kc], b, c0);
+      c1 = mfma(a1[kc], b, c1);
+    }
+    const int col = nt * 16 + lr;
+    const float bb = bias[col];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = rw + 4 * lq + i;
+      Hout[row * kPitchH + col] = f2bf(gelu(c0[i] + bb));
+      Hout[(row + 16) * kPitchH + col] = f2bf(gelu(c1[i] + bb));
+    }
+  }
+}
+
 __global__ __launch_bounds__(kThreads) void mlp_forward_kernel(Net net, const float* __restrict__ x, int64_t m_rows,
                                                                float* __restrict__ y) {
-  __shared__ __align__(16) uint16_t XS[kTile * kPitchX];
-  __shared__ __align__(16) uint16_t HA[kTile * kPitchH];
-  __shared__ __align__(16) uint16_t HB[kTile * kPitchH];
-  const int64_t row0 = (int64_t)blockIdx.x * kTile;
+  __shared__ __align__(16) uint16_t XS[kFwdTile * kPitchX];
+  __shared__ __align__(16) uint16_t H[kFwdTile * kPitchH];
+  const int64_t row0 = (int64_t)blockIdx.x * kFwdTile;
   load_inputs(net, x, m_rows, row0, XS);
+  load_inputs(net, x, m_rows, row0 + kTile, XS + kTile * kPitchX);
   __syncthreads();
-  hidden_layer<1, false>(XS, kPitchX, net.wb + pW1, kInPad, net.prm + oB1, HA, nullptr);
-  __syncthreads();
-  hidden_layer<4, false>(HA, kPitchH, net.wb + pW2, kHid, net.prm + oB2, HB, nullptr);
-  __syncthreads();
-  hidden_layer<4, false>(HB, kPitchH, net.wb + pW3, kHid, net.prm + oB3, HA, nullptr);
-  __syncthreads();
-  const f32x4 o = output_layer(net, HA);
+  fwd_layer<1>(XS, kPitchX, net.wb + pW1, kInPad, net.prm + oB1, H);
+  fwd_layer<4>(H, kPitchH, net.wb + pW2, kHid, net.prm + oB2, H);
+  fwd_layer<4>(H, kPitchH, net.wb + pW3, kHid, net.prm + oB3, H);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63, lr = l & 15, lq = l >> 4;
+  const int rw = kFwdRowsPerWave * w;
+  f32x4 o0 = {0.f, 0.f, 0.f, 0.f}, o1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int kc = 0; kc < 4; ++kc) {
+    const u16x8 b = ld8(net.wb + pW4 + lr * kHid + kc * 32 + 8 * lq);
+    o0 = mfma(ld8(H + (rw + lr) * kPitchH + kc * 32 + 8 * lq), b, o0);
+    o1 = mfma(ld8(H + (rw + 16 + lr) * kPitchH + kc * 32 + 8 * lq), b, o1);
+  }
   if (lr < kOut) {
+    const float bb = net.prm[oB4 + lr];
     const float om = net.norm[2 * kIn + lr], os = net.norm[2 * kIn + kOut + lr];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int64_t gm = row0 + 16 * w + 4 * lq + i;
-      if (gm < m_rows) y[gm * kOut + lr] = o[i] * os + om;
+      const int64_t g0 = row0 + rw + 4 * lq + i, g1 = g0 + 16;
+      if (g0 < m_rows) y[g0 * kOut + lr] = (o0[i] + bb) * os + om;
+      if (g1 < m_rows) y[g1 * kOut + lr] = (o1[i] + bb) * os + om;
     }
   }
 }
@@ -374,7 +435,7 @@ hipError_t launch_pack(const float* prm, uint16_t* wb, hipStream_t s) {
 hipError_t launch_forward(const uint16_t* wb, const float* prm, const float* norm, int64_t m_rows, const float* x,
                           float* y, hipStream_t s) {
   if (m_rows == 0) return hipSuccess;
-  const int64_t tiles = (m_rows + kTile - 1) / kTile;
+  const int64_t tiles = (m_rows + kFwdTile - 1) / kFwdTile;
   hipLaunchKernelGGL(mlp_forward_kernel, dim3((unsigned)tiles), dim3(kThreads), 0, s, Net{wb, prm, norm}, x, m_rows,
                      y);
   return hipGetLastError();
