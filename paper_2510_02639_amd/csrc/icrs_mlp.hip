@@ -53,13 +53,8 @@ __device__ inline f32x4 mfma(u16x8 a, u16x8 b, f32x4 c) {
                                                  0, 0);
 }
 
-// round to nearest bfloat16, ties to even (NaN stays NaN)
-__device__ inline uint16_t f2bf(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
+// round to nearest bfloat16, ties to even, NaN stays NaN (gfx950's v_cvt_pk_bf16_f32)
+__device__ inline uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ inline float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 // GELU, tanh form: x/2 (1 + tanh(c (x + a x^3))), c = sqrt(2/pi), a = 0.044715, evaluated
