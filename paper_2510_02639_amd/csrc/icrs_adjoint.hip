@@ -124,12 +124,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void a
       for (int a = 0; a < NA; ++a) acc[a] = 0.0;
       for (int i = wave; i < n_r; i += kAW) {
         const double r = r_lo + (i + 0.5) * dr;
+        // chunk culling as in the forward kernel: lane j tests chunk j's arc, widened by two
+        // columns on each side; one that provably maps farther than rho (1 + 1e-3) from the
+        // source centre has no inside node and no stencil node of a crossing (changes no bit)
+        bool sk = false;
+        if (lane < J) {
+          double cs, sn;
+          sincos(th_lo + (64.0 * lane + 32.0) * dth, &sn, &cs);
+          sk = arc_distance_lower_bound<N>(L, wc, r, cs, sn, 34.0 * dth) > rho * 1.001;
+        }
+        const uint64_t rowskip = __ballot(sk);
+        if (rowskip == (1ull << J) - 1ull) continue;  // the whole row misses the image
         uint64_t m[JMAX];
         uint64_t any = 0;
 #pragma unroll
         for (int j = 0; j < JMAX; ++j) {
           m[j] = 0;
-          if (j >= J) continue;
+          if (j >= J || ((rowskip >> j) & 1ull)) continue;
           const int l = lane + 64 * j;
           const bool valid = l < n_theta;
           const int lc = valid ? l : last;

@@ -135,6 +135,46 @@ __device__ inline T crossing_basis(T d0, T d1, T d2, T d3, bool cubic, T t, T (&
   return (T(3) * c3 * t + T(2) * c2) * t + c1;
 }
 
+// Lower bound of d = |w(z) - w_c| over the arc z = z0 e^{i phi}, |phi| <= Phi, z0 = r e^{i theta_c}.
+// w(z) = z + f(conj z) with f holomorphic, so for Delta = z - z0:
+//   w(z) = w0 + Delta + K conj(Delta) + R2,  K = f'(conj z0) = sum_k eps_k / conj(z0 - a_k)^2,
+//   |R2| <= sum_k eps_k / dmin_k^3 |Delta|^2   (dmin_k: lens k's distance to the arc's disc),
+// and Delta = i z0 phi + e with |e| <= r phi^2 / 2, |Delta| <= r Phi.  The linear part traces
+// the segment c + v phi (c = w0 - w_c, v = i z0 + K conj(i z0)); its distance to the origin
+// less the two remainder bounds is the bound.  Returns 0 when a lens is within r Phi of z0.
+// Quotients and roots use the refined hardware reciprocal and square root: their relative
+// error (~1e-15) is far inside the 1e-3 margin the caller asks for.
+template <int N>
+__device__ inline double arc_distance_lower_bound(const Lens<N>& L, c64 wc, double r, double cth, double sth,
+                                                  double Phi) {
+  const double zx = r * cth, zy = r * sth;
+  const double R = r * Phi;
+  double wx = zx, wy = zy, kx = 0.0, ky = 0.0, M = 0.0;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const double ux = zx - L.a[k].x, uy = zy - L.a[k].y;
+    const double u2 = fma(ux, ux, uy * uy);
+    const double dmin = sqrt_fast(u2) - R;
+    if (!(dmin > 0.0)) return 0.0;
+    const double inv = rcp_fast(u2);
+    const double gx = L.eps[k] * ux * inv, gy = L.eps[k] * uy * inv;  // eps / conj(u)
+    wx -= gx;
+    wy -= gy;
+    kx += (gx * ux - gy * uy) * inv;  // eps / conj(u)^2 = (eps / conj(u)) (u / |u|^2)
+    ky += (gx * uy + gy * ux) * inv;
+    M += L.eps[k] * rcp_fast(dmin * dmin * dmin);
+  }
+  const double tx = -zy, ty = zx;  // i z0
+  const double vx = tx + (kx * tx + ky * ty), vy = ty + (ky * tx - kx * ty);
+  const double cx = wx - wc.x, cy = wy - wc.y;
+  const double vv = fma(vx, vx, vy * vy);
+  double phi = vv > 0.0 ? -(cx * vx + cy * vy) * rcp_fast(vv) : 0.0;
+  phi = fmin(fmax(phi, -Phi), Phi);
+  const double ex = fma(vx, phi, cx), ey = fma(vy, phi, cy);
+  const double E = (1.0 + sqrt_fast(fma(kx, kx, ky * ky))) * 0.5 * r * Phi * Phi + M * R * R;
+  return sqrt_fast(fma(ex, ex, ey * ey)) - E;
+}
+
 // d f / d delta on the branch that f(delta) takes
 template <typename T>
 __device__ __forceinline__ T edge_factor_slope(T delta, T u1, T delta_c) {
