@@ -56,17 +56,26 @@ __device__ inline double node_d2_grad(const Lens<N>& L, c64 wc, double x, double
 struct Bright {
   double I, dI_dd2, dI_drho, dI_du1;
 };
-__device__ inline Bright bright_grad(double d2, double rho, double u1) {
-  const double I0 = 3.0 / (kPi * (3.0 - u1));
-  const double inv_rho2 = 1.0 / (rho * rho);
-  const double c = fmax(1.0 - d2 * inv_rho2, 0.0);
+// The epoch's constants of I: I0 = 3 / (pi (3 - u1)), 1/rho^2, 2/rho^3 and dI0/du1 = I0 / (3 - u1),
+// so that no node divides.
+struct BrightConst {
+  double u1, I0, inv_rho2, two_inv_rho3, dI0_du1;
+  __device__ inline BrightConst(double rho, double u1_) : u1(u1_) {
+    I0 = 3.0 / (kPi * (3.0 - u1));
+    inv_rho2 = 1.0 / (rho * rho);
+    two_inv_rho3 = 2.0 * inv_rho2 / rho;
+    dI0_du1 = I0 / (3.0 - u1);
+  }
+};
+__device__ inline Bright bright_grad(double d2, const BrightConst& k) {
+  const double c = fmax(1.0 - d2 * k.inv_rho2, 0.0);
   const double s = sqrt_fast(c);
   Bright b;
-  b.I = I0 * (1.0 - u1 + u1 * s);
-  const double ds_dc = (s > 0.0) ? 0.5 / s : 0.0;
-  b.dI_dd2 = I0 * u1 * ds_dc * (-inv_rho2);
-  b.dI_drho = I0 * u1 * ds_dc * (2.0 * d2 * inv_rho2 / rho);
-  b.dI_du1 = I0 / (3.0 - u1) * (1.0 - u1 + u1 * s) + I0 * (s - 1.0);
+  b.I = k.I0 * (1.0 - k.u1 + k.u1 * s);
+  const double ds_dc = (s > 0.0) ? 0.5 * rcp_fast(s) : 0.0;  // refined reciprocal, ~1e-15 relative
+  b.dI_dd2 = k.I0 * k.u1 * ds_dc * (-k.inv_rho2);
+  b.dI_drho = k.I0 * k.u1 * ds_dc * (d2 * k.two_inv_rho3);
+  b.dI_du1 = k.dI0_du1 * (1.0 - k.u1 + k.u1 * s) + k.I0 * (s - 1.0);
   return b;
 }
 
@@ -102,6 +111,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void a
     const double rho = p[6], u1 = p[7];
     const double rho2 = rho * rho;
     const double f_edge = edge_factor<double>(0.5, u1, delta_c) - 1.0;
+    const BrightConst bk(rho, u1);
     double tot[NA];
 #pragma unroll
     for (int a = 0; a < NA; ++a) tot[a] = 0.0;
@@ -151,7 +161,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void a
           any |= m[j];
           if (valid) buf[l] = d2;
           if (in) {
-            const Bright br = bright_grad(d2, rho, u1);
+            const Bright br = bright_grad(d2, bk);
 #pragma unroll
             for (int g = 0; g < NG; ++g) acc[g] = fma(r * br.dI_dd2, gg[g], acc[g]);
             acc[NG] = fma(r, br.I, acc[NG]);
@@ -203,7 +213,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void a
           }
           double gl[NG];
           const double d2l = node_d2_grad<N>(L, wc, r * colc[l], r * cols[l], gl);
-          const Bright br = bright_grad(d2l, rho, u1);
+          const Bright br = bright_grad(d2l, bk);
           double corr;
           const bool edge = (side == 0 && l == 0 && !per) || (side == 1 && l == last && !per);
           if (edge) {
