@@ -93,7 +93,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void a
   __shared__ unsigned long long next_sh;
 
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform (as in the ray kernel)
   const int J = (n_theta + 63) >> 6;
   const int last = n_theta - 1;
   double* buf = rowbuf[wave];
