@@ -58,9 +58,9 @@ def kernel_name(rays, n_theta):
 # scaled by the same counters' reading on a plain copy kernel of known size (FETCH reads 2.0x
 # low, WRITE 1.0x on this machine); keyed by (ray precision, events, path, N_r, N_theta).
 # Filled in from measured counter runs of the current kernels; absent (null) otherwise.
-TRAFFIC = {("fp32", 2048, "plain", 192, 512): 3.8317e11,      # FETCH 104669529 KiB x 2.0 + WRITE 164846582 KiB
-           ("fp32", 2048, "fallback", 192, 512): 3.1422e11,   # FETCH 86252920 KiB x 2.0 + WRITE 134351369 KiB
-           ("fp32", 2048, "learned", 32, 128): 1.4074e11}     # FETCH 44009645 KiB x 2.0 + WRITE 49426296 KiB
+TRAFFIC = {("fp32", 2048, "plain", 192, 512): 2.3785e11,      # FETCH 68574614 KiB x 2.0 + WRITE 95127772 KiB
+           ("fp32", 2048, "fallback", 192, 512): 1.9308e11,   # FETCH 55158908 KiB x 2.0 + WRITE 78235439 KiB
+           ("fp32", 2048, "learned", 32, 128): 5.8938e10}     # FETCH 18143603 KiB x 2.0 + WRITE 21269333 KiB
 
 
 def cpu_baseline(w, mags, budget_s, seed=0):

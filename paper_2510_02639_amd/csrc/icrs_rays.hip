@@ -374,7 +374,8 @@ __device__ inline void shoot_sector(const double* sp, bool per, const Lens<N>& L
   const int lane = threadIdx.x & 63;
   // wave-uniform, which the compiler cannot tell from threadIdx.x >> 6: without it the row
   // loop counter is taken as divergent and the loop carries its conditions in vector registers
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // (2-9% on the binary lens; the triple lens's register allocation does 4% worse with it)
+  const int wave = N == 2 ? __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) : (int)(threadIdx.x >> 6);
   const double r_lo = sp[0], r_hi = sp[1];
   const T rho = (T)rho_d, u1 = (T)u1_d, delta_c = (T)delta_c_d;
   const T rho2 = (T)(rho_d * rho_d), inv_rho2 = (T)(1.0 / (rho_d * rho_d));
