@@ -275,7 +275,7 @@ def main():
                     help="only run a plain device copy of this many MiB (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the path has no multi-GPU leg); use --gpus 1",
+        print("bench.py: measures one GPU only (the path has no multi-GPU leg); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
 
