@@ -344,13 +344,14 @@ def test_fp32_rays_given_grid_planetary(n_r, n_theta):
 
 
 @pytest.mark.parametrize("delta_c", [0.05, 0.3, 0.6])
-@pytest.mark.parametrize("n_r,n_theta", [(32, 128), (64, 256)])
+@pytest.mark.parametrize("n_r,n_theta", [(32, 128), (64, 256), (48, 320), (128, 1024)])
 def test_fp32_edge_rule_branch_at_other_delta_c(n_r, n_theta, delta_c):
     """The limb-darkened edge rule jumps at delta_c (App. A.2), and the FP32 path takes the
     branch of a crossing within its rounding of delta_c from FP64 stencil distances.  With the
     jump moved to 0.05, 0.3 or 0.6 every epoch still matches the oracle's quadrature on the
     same sectors and delta_c to the FP32 bar (a branch flip costs ~0.2 of a node's weight,
-    up to 4e-4 of a poorly resolved image at these grids)."""
+    up to 4e-4 of a poorly resolved image at the coarse grids).  The grids cover the 2-, 4-,
+    8- (with a partial chunk) and 16-chunk kernels."""
     w = _planetary_subset(n_events=8, per_event=8, rho=1e-3)
     ref = _oracle(w)
     t = torch.tensor(w.t, device="cuda")
