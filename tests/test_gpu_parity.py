@@ -417,6 +417,36 @@ def test_triple_fp32_rays_config3_grid():
     assert np.all(rel <= FP32_TOL)
 
 
+@pytest.mark.parametrize("n_r,n_theta", [(32, 128), (64, 512)])
+@pytest.mark.parametrize("delta_c", [0.1, 0.3])
+def test_triple_fp32_edge_rule_branch(n_r, n_theta, delta_c):
+    """The triple lens's FP32 ray loop (its own kernel instantiation) with the FP64 retake of
+    crossings next to delta_c: given-grid parity with the oracle's quadrature on the same
+    sectors and delta_c, at a coarse and at the configured column count."""
+    big = W.config3(n_events=3, n_epochs=2000)
+    ts, off = [], [0]
+    for i in range(3):
+        seg = big.t[big.offsets[i]:big.offsets[i + 1]][980:1020:4]
+        ts.append(seg)
+        off.append(off[-1] + seg.size)
+    w = W.Workload("triple-fp32", 3, big.params, np.array(off, np.int64), np.concatenate(ts), 128, 128, 512,
+                   "fp32", "fp64")
+    ref = _oracle(w)
+    h = icrs.Handle(n_lens=3, n_limb=128, n_r=n_r, n_theta=n_theta, ray_precision="fp32", root_precision="fp64",
+                    delta_c=delta_c)
+    t = torch.tensor(w.t, device="cuda")
+    args = [torch.tensor(ref[k], device="cuda") for k in ("sectors", "periodic", "nsec")]
+    mag, _ = h.magnification_given(w.params, w.offsets, t, *args)
+    om = []
+    for i in range(w.n_events):
+        sl = slice(w.offsets[i], w.offsets[i + 1])
+        om.append(O.magnification_given(3, w.params[i], w.t[sl], ref["sectors"][sl], ref["periodic"][sl],
+                                        ref["nsec"][sl], n_r, n_theta, delta_c=delta_c)[0])
+    rel = np.abs(mag.cpu().numpy() / np.concatenate(om) - 1)
+    _report(f"triple fp32 given {n_r}x{n_theta} delta_c={delta_c}", rel)
+    assert np.all(rel <= FP32_TOL)
+
+
 def test_fp32_rays_on_poorly_resolved_near_caustic_images():
     """Epochs of the 2048-event benchmark workload where an image covers only a few hundred
     to a few thousand nodes of its 128 x 512 box, next to a caustic (magnification 10-30).
